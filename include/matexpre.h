@@ -1,0 +1,232 @@
+/*
+ * matexpre.h -- C ABI of the MatExPre hot path on one AMD MI355X (gfx950).
+ *
+ * The library solves the discrete Helmholtz problem
+ *
+ *     omega^2/c(x)^2 u + Lap_PML u = -f                      (paper Section 1, eq. helmholtz)
+ *
+ * on a structured 2D (five-point) or 3D (seven-point) node grid whose outer
+ * cells form a perfectly matched layer with the quadratic stretch
+ * s(x) = 1 + i C_pml/(delta omega) (dist/delta)^2 on every axis
+ * (Section 3.3, eq. pml-1d-s; Section 4 introduction), zero Dirichlet values
+ * beyond the grid.  It uses flexible GMRES preconditioned by MatExPre
+ * (Section 3.4, Algorithm 1): for a residual r,
+ *
+ *     r_hat = psi_1(i t A_s) r,   then GMRES on (I - exp(i t A_s)) w = r_hat
+ *     to relative tolerance fprtol, return w,
+ *
+ * with the complex-shifted operator A_s = A + i omega^2 s D, D = diag(1/c^2)
+ * (Section 3.4).  The matrix-function actions are evaluated by substepped
+ * Chebyshev expansions on HIP kernels.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Layout    Grid vectors hold n0*n1*n2 complex values (n2 = 1 in 2D),
+ *            interleaved (re, im), index i + n0*(j + n1*k), x fastest; the
+ *            same layout as C99 _Complex and torch.complex64/complex128.
+ *  Pointers  Vector arguments (f, u, x, y, r, w) are DEVICE pointers on the
+ *            context's device, caller-owned, valid for the duration of the
+ *            call, and must not overlap unless a call says otherwise.  The
+ *            wave-speed array c may be a host or a device pointer.
+ *  Streams   All device work is enqueued on the stream given to
+ *            mxp_context_create (NULL = the null stream).  Every call returns
+ *            only after its work has completed, so outputs and statistics are
+ *            valid on return.
+ *  Errors    Calls return mxp_status.  Arguments are validated before any
+ *            device work; a negative status means nothing usable was written.
+ *            MXP_NOT_CONVERGED (positive) means the iteration limit was hit:
+ *            u holds the last iterate and the statistics are filled in.
+ *            mxp_last_error() gives a message for the last failing call on the
+ *            calling thread.  No C++ exception crosses this interface.
+ *  Threads   A context (and its problems) is used by one host thread at a
+ *            time.
+ */
+#ifndef MATEXPRE_H
+#define MATEXPRE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MXP_OK = 0,
+    MXP_NOT_CONVERGED = 1,
+    MXP_ERR_INVALID_ARG = -1,
+    MXP_ERR_OOM = -2,
+    MXP_ERR_HIP = -3,
+    MXP_ERR_BREAKDOWN = -4,
+    MXP_ERR_NONFINITE = -5,
+    MXP_ERR_UNSUPPORTED = -6
+} mxp_status;
+
+typedef enum {
+    MXP_C64 = 0,   /* complex float  (8 bytes per value)  */
+    MXP_C128 = 1,  /* complex double (16 bytes per value) */
+    MXP_F32 = 2,   /* real float  (wave speed only)       */
+    MXP_F64 = 3    /* real double (wave speed only)       */
+} mxp_dtype;
+
+typedef enum {
+    MXP_PREC_FP64 = 0,  /* every step in complex double                              */
+    MXP_PREC_MIXED = 1  /* matrix-function actions in complex float; Krylov bases,     */
+                        /* Hessenberg, true residual and the outer iteration in double */
+} mxp_precision;
+
+typedef struct mxp_context mxp_context;
+typedef struct mxp_problem mxp_problem;
+
+/* ---------------------------------------------------------------- context */
+
+/* Binds `device` and borrows `hip_stream` (a hipStream_t, or NULL for the
+ * null stream) for all later work.  *out receives the context.
+ * Errors: INVALID_ARG (no such device, out == NULL), HIP. */
+mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out);
+
+/* Frees the context.  Problems created on it must be destroyed first. */
+void mxp_context_destroy(mxp_context* ctx);
+
+/* Message for the last failing call on this thread ("" if none).  The
+ * pointer stays valid until the next call on this thread. */
+const char* mxp_last_error(void);
+
+/* Library version string. */
+const char* mxp_version(void);
+
+/* ---------------------------------------------------------------- problem */
+
+/* The problem statement (Section 1 eq. helmholtz; Section 3.3 eq. pml-1d-s;
+ * Section 4 introduction).  Node x_i = i*h on every axis.  layer[d][0/1] is
+ * the number of absorbing-layer cells on the low/high face of axis d; those
+ * are the outermost nodes of the given grid, delta = layer*h, and the stretch
+ * distance is measured from the inner edge (layer*h, (n-1-layer)*h).  0 gives
+ * a bare Dirichlet face. */
+typedef struct {
+    int32_t dim;            /* 2 or 3                                           */
+    int64_t n[3];           /* nodes per axis, x first; n[2] = 1 in 2D; each >= 3 */
+    double h;               /* grid spacing, > 0                                */
+    double omega;           /* angular frequency, > 0                           */
+    int32_t layer[3][2];    /* absorbing cells per face, 0 <= layer < n/2       */
+    double pml_C;           /* C_pml (the paper's experiments use 20), >= 0     */
+    int32_t pml_power;      /* profile power (2 = quadratic), >= 1              */
+    const void* c;          /* wave speed per node (host or device), or NULL    */
+    mxp_dtype c_dtype;      /* MXP_F32 or MXP_F64 when c != NULL                */
+    double c_const;         /* wave speed everywhere when c == NULL, > 0        */
+} mxp_grid_desc;
+
+/* Copies the description, validates it (c finite and > 0 everywhere), builds
+ * the per-axis absorbing-layer coefficient tables and D = 1/c^2 on the
+ * device.  The library owns everything it allocates; mxp_problem_destroy
+ * frees it.  The caller's c may be freed after this call returns.
+ * Errors: INVALID_ARG (any bound above violated), OOM, HIP. */
+mxp_status mxp_problem_create(mxp_context* ctx, const mxp_grid_desc* desc, mxp_problem** out);
+void mxp_problem_destroy(mxp_problem* prob);
+
+/* Number of grid nodes n0*n1*n2 (0 for a NULL problem). */
+int64_t mxp_problem_size(const mxp_problem* prob);
+
+/* ---------------------------------------------------------------- options */
+
+typedef struct {
+    double t;               /* time length of the exponential (paper: t ~ 1/freq^2)  */
+    double shift;           /* complex shift s >= 0 of A_s                            */
+    double fprtol;          /* inner (fixed-point) relative tolerance, in (0, 1]     */
+    double rtol;            /* outer relative residual tolerance ||b-Au||/||b||      */
+    int32_t outer_restart;  /* FGMRES restart length, 1..200                         */
+    int32_t inner_restart;  /* inner GMRES restart length, 1..200                    */
+    int32_t max_outer;      /* outer iteration limit, >= 1                           */
+    int32_t max_inner;      /* inner iteration limit per preconditioner apply, >= 1  */
+    mxp_precision precision;
+    int32_t cheb_S;         /* > 0 forces the number of Chebyshev substeps (0 = designed) */
+    int32_t cheb_m;         /* > 0 forces the series degree per substep    (0 = designed) */
+} mxp_solve_opts;
+
+/* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per
+ * wavelength, Section 4.1), shift = 1/freq (Section 4.1.2), fprtol = 0.08
+ * (Section 4.2.1), rtol = 1e-6, restarts 30, max_outer 500, max_inner 300,
+ * MXP_PREC_FP64, designed schedule. */
+mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out);
+
+typedef struct {
+    int32_t outer_its;        /* outer FGMRES iterations                          */
+    int32_t inner_its_total;  /* inner GMRES iterations summed over applies       */
+    double inner_mean;        /* mean inner iterations per preconditioner apply   */
+    double inner_std;         /* population standard deviation of the same        */
+    int64_t stencil_steps;    /* stencil sweeps spent in matrix-function actions  */
+    int64_t fn_actions;       /* exp and psi_1 actions                            */
+    double true_relres;       /* ||b - A u|| / ||b|| of the returned u, in double */
+    double seconds;           /* wall time of the call                            */
+    int32_t restarts;         /* outer restart cycles after the first             */
+} mxp_solve_stats;
+
+/* --------------------------------------------------------------- schedule */
+
+/* The substepped Chebyshev schedule used for exp(i t A_s) and psi_1(i t A_s):
+ * exp(i t A_s) = (p(A_s))^S with p the degree-m Chebyshev expansion of
+ * exp(i tau z), tau = t/S, on the segment centre +- half_width (a horizontal
+ * segment in the complex plane), and q the degree-m_psi expansion of
+ * tau*psi_1(i tau z) on the same segment.  Designed from a rectangle that
+ * contains the field of values of A_s so that the truncation error of the
+ * whole action is below the stated tolerance. */
+typedef struct {
+    int32_t S;                    /* substeps                                       */
+    int32_t m;                    /* degree of the exp series                       */
+    int32_t m_psi;                /* degree of the psi_1 series                     */
+    double centre_re, centre_im;  /* segment centre                                 */
+    double half_width;            /* segment half-length                            */
+    double box[4];                /* field-of-values box: re_min re_max im_min im_max */
+    double trunc_bound;           /* bound on the truncation error of one action    */
+    double amplification;         /* max over the box of sum_k |c_k T_k|            */
+    double coef[2 * 512];         /* exp series, (re, im) pairs, m+1 used           */
+    double coef_psi[2 * 512];     /* psi_1 series, (re, im) pairs, m_psi+1 used     */
+} mxp_schedule;
+
+/* Host-only (no device work; usable without a GPU).  Designs the schedule for
+ * a problem description, time length t, shift and precision.  c, if given,
+ * must be a host pointer here.  Errors: INVALID_ARG, UNSUPPORTED (no schedule
+ * within 512 terms). */
+mxp_status mxp_design_schedule(const mxp_grid_desc* desc, double t, double shift,
+                               mxp_precision precision, mxp_schedule* out);
+
+/* ------------------------------------------------------- building blocks */
+/* dtype selects complex float or complex double vectors; the arithmetic runs
+ * in that precision.  x and y may not alias. */
+
+/* y = A_s x, the shifted stencil operator (Section 3.4; shift = 0 gives A). */
+mxp_status mxp_apply_A(mxp_problem* prob, double shift, mxp_dtype dtype, const void* x, void* y);
+
+/* y = exp(i t A_s) x  (Section 3.1). */
+mxp_status mxp_apply_exp(mxp_problem* prob, double t, double shift, mxp_dtype dtype,
+                         const void* x, void* y);
+
+/* y = psi_1(i t A_s) x  (Section 3.1, Def. psi; t psi_1(i t A) equals the time
+ * integral of exp(i tau A) over [0, t]). */
+mxp_status mxp_apply_psi1(mxp_problem* prob, double t, double shift, mxp_dtype dtype,
+                          const void* x, void* y);
+
+/* w = M(r), Algorithm 1 (Section 3.4): psi_1 action, then GMRES from w = 0 on
+ * (I - exp(i t A_s)) w = psi_1(i t A_s) r until the residual estimate is
+ * <= fprtol * ||psi_1(i t A_s) r||.  r and w are complex double; with
+ * MXP_PREC_MIXED the matrix-function actions run in complex float.
+ * *inner_its (may be NULL) receives the inner iteration count. */
+mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r,
+                             void* w, int32_t* inner_its);
+
+/* ------------------------------------------------------------------ solve */
+
+/* Solves A u = -f by FGMRES(outer_restart) preconditioned by Algorithm 1
+ * (Section 3.4).  f and u are complex double device vectors; u is read as the
+ * initial guess (zero it for the plain solve) and overwritten.  Stops when the
+ * true residual ||-f - A u|| <= rtol ||f||; the outer Krylov basis, Hessenberg
+ * matrix and true residual are always complex double.  stats may be NULL.
+ * Returns OK, NOT_CONVERGED (max_outer reached), or an error. */
+mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
+                     mxp_solve_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MATEXPRE_H */

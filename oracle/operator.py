@@ -1,0 +1,129 @@
+"""Discrete Helmholtz operator with a perfectly matched layer (oracle side).
+
+Paper passages followed:
+  * Helmholtz equation omega^2/c^2 u + Lap u = -f            (Section 1, eq. helmholtz)
+  * 1D stretched operator (1/s) d/dx((1/s) du/dx), quadratic
+    profile s = 1 + i C_pml/(delta omega) (dist/delta)^2     (Section 3.3, eq. pml-1d-s)
+  * three-point FD per axis; five-point 2D / seven-point 3D  (Section 3.3, Section 4 intro)
+  * zero Dirichlet outside the layer                          (Section 4 intro)
+  * shifted operator A_s = A + i omega^2 s D, D = diag(1/c^2)  (Section 3.4)
+
+Readings where the paper is silent (also listed in the design notes):
+  * multi-dimensional layer: sum over axes of (1/s_d) d_d((1/s_d) d_d u), each
+    s_d depending on x_d only; the node value 1/s_d(x_i) multiplies the flux
+    difference and the half-node values 1/s_d(x_{i+-1/2}) sit in the fluxes;
+  * the layer is part of the given grid: the outermost L nodes of each face,
+    delta = L h, distance measured from the inner edge x_a = L h,
+    x_b = (N-1-L) h; ghost nodes at indices -1 and N are zero;
+  * C_pml = 20, power 2.
+
+Parity: pinned by the tests (plane-wave consistency of the interior stencil,
+second-order consistency of the 1D stretched operator against its analytic
+form, closed-form DST spectrum without a layer, Green's function decay with a
+layer, and Im(eig) >= 0).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def pml_sigma(x: np.ndarray, n: int, L: int, h: float, omega: float,
+              C: float = 20.0, power: int = 2) -> np.ndarray:
+    """Imaginary part sigma(x) of the stretch s(x) = 1 + i sigma(x) along one axis
+    of n nodes with L layer cells on each face (eq. pml-1d-s)."""
+    x = np.asarray(x, dtype=float)
+    sig = np.zeros_like(x)
+    if L <= 0:
+        return sig
+    delta = L * h
+    xa = L * h
+    xb = (n - 1 - L) * h
+    lo = x < xa
+    hi = x > xb
+    sig[lo] = C / (delta * omega) * ((xa - x[lo]) / delta) ** power
+    sig[hi] = C / (delta * omega) * ((x[hi] - xb) / delta) ** power
+    return sig
+
+
+def axis_matrix(n: int, L: int, h: float, omega: float, C: float = 20.0,
+                power: int = 2) -> sp.csr_matrix:
+    """n x n three-point discretisation of (1/s) d/dx((1/s) du/dx) with zero
+    Dirichlet ghosts.  Row i:  (1/s_i) [ (u_{i+1}-u_i)/(s_{i+1/2} h)
+    - (u_i-u_{i-1})/(s_{i-1/2} h) ] / h."""
+    x = np.arange(n) * h
+    s_node = 1 + 1j * pml_sigma(x, n, L, h, omega, C, power)
+    s_left = 1 + 1j * pml_sigma(x - h / 2, n, L, h, omega, C, power)
+    s_right = 1 + 1j * pml_sigma(x + h / 2, n, L, h, omega, C, power)
+    w_left = 1.0 / (s_node * s_left * h * h)     # coefficient of u_{i-1}
+    w_right = 1.0 / (s_node * s_right * h * h)   # coefficient of u_{i+1}
+    rows = []
+    cols = []
+    vals = []
+    for i in range(n):
+        rows.append(i); cols.append(i); vals.append(-(w_left[i] + w_right[i]))
+        if i > 0:
+            rows.append(i); cols.append(i - 1); vals.append(w_left[i])
+        if i < n - 1:
+            rows.append(i); cols.append(i + 1); vals.append(w_right[i])
+    return sp.csr_matrix((np.array(vals, dtype=np.complex128), (rows, cols)), shape=(n, n))
+
+
+def laplacian_pml(n, L, h, omega, C: float = 20.0, power: int = 2) -> sp.csr_matrix:
+    """Sum over axes of the stretched second difference, as a Kronecker sum on
+    the flattened index i + n0*(j + n1*k)."""
+    n = tuple(n)
+    N = int(np.prod(n))
+    lap = sp.csr_matrix((N, N), dtype=np.complex128)
+    for ax, nd in enumerate(n):
+        Ld = axis_matrix(nd, L, h, omega, C, power)
+        inner = int(np.prod(n[:ax]))        # faster axes
+        outer = int(np.prod(n[ax + 1:]))    # slower axes
+        lap = lap + sp.kron(sp.identity(outer), sp.kron(Ld, sp.identity(inner)))
+    return lap.tocsr()
+
+
+def inverse_c2(prob) -> np.ndarray:
+    """Diagonal of D = 1/c^2, flattened."""
+    c = prob.c_array().ravel().astype(float)
+    return 1.0 / (c * c)
+
+
+def helmholtz(prob, shift: float = 0.0) -> sp.csr_matrix:
+    """A_s = omega^2 (1 + i s) D + Lap_PML; shift = 0 gives A itself."""
+    lap = laplacian_pml(prob.n, prob.layer, prob.h, prob.omega, prob.pml_C, prob.pml_power)
+    D = inverse_c2(prob)
+    return (lap + sp.diags(prob.omega ** 2 * (1 + 1j * shift) * D)).tocsr()
+
+
+def rhs(f: np.ndarray) -> np.ndarray:
+    """b = -f (eq. helmholtz)."""
+    return -np.asarray(f, dtype=np.complex128).ravel()
+
+
+def apply_rows(prob, shift: float, x: np.ndarray, points: np.ndarray) -> np.ndarray:
+    """(A_s x) at selected flat indices, computed one row at a time from the
+    stencil definition (for spot checks at sizes where assembling A is too big).
+    x: flat complex vector; points: flat indices."""
+    n = prob.n
+    d = len(n)
+    h, om, L = prob.h, prob.omega, prob.layer
+    D = inverse_c2(prob)
+    out = np.empty(len(points), dtype=np.complex128)
+    strides = [int(np.prod(n[:ax])) for ax in range(d)]
+    for q, p in enumerate(np.asarray(points, dtype=np.int64)):
+        idx = [(p // strides[ax]) % n[ax] for ax in range(d)]
+        acc = om * om * (1 + 1j * shift) * D[p] * x[p]
+        for ax in range(d):
+            i = idx[ax]
+            xi = i * h
+            s0 = 1 + 1j * pml_sigma(np.array([xi]), n[ax], L, h, om, prob.pml_C, prob.pml_power)[0]
+            sl = 1 + 1j * pml_sigma(np.array([xi - h / 2]), n[ax], L, h, om, prob.pml_C, prob.pml_power)[0]
+            sr = 1 + 1j * pml_sigma(np.array([xi + h / 2]), n[ax], L, h, om, prob.pml_C, prob.pml_power)[0]
+            wl = 1 / (s0 * sl * h * h)
+            wr = 1 / (s0 * sr * h * h)
+            um = x[p - strides[ax]] if i > 0 else 0.0
+            up = x[p + strides[ax]] if i < n[ax] - 1 else 0.0
+            acc += wl * um + wr * up - (wl + wr) * x[p]
+        out[q] = acc
+    return out

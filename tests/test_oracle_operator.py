@@ -1,0 +1,149 @@
+"""Pins for the oracle's operator assembly (oracle/operator.py)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import operator as op
+from oracle import matfun
+
+
+def test_dirichlet_eigs_match_dense_second_difference():
+    # textbook: eig of (1/h^2) tridiag(1,-2,1) are -4 sin^2(k pi/(2(n+1)))/h^2
+    n, h = 17, 0.1
+    T = (np.diag(-2 * np.ones(n)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)) / h**2
+    ev = np.sort(np.linalg.eigvalsh(T))
+    assert np.allclose(np.sort(matfun.dirichlet_eigs(n, h)), ev, rtol=1e-12, atol=1e-9)
+
+
+def test_no_layer_operator_is_dirichlet_laplacian_plus_diagonal():
+    prob = wl.small_problem((9, 7), layer=0)
+    A = op.helmholtz(prob, shift=0.3).toarray()
+    n0, n1 = prob.n
+    h = prob.h
+    T0 = (np.diag(-2 * np.ones(n0)) + np.diag(np.ones(n0 - 1), 1) + np.diag(np.ones(n0 - 1), -1)) / h**2
+    T1 = (np.diag(-2 * np.ones(n1)) + np.diag(np.ones(n1 - 1), 1) + np.diag(np.ones(n1 - 1), -1)) / h**2
+    ref = np.kron(np.eye(n1), T0) + np.kron(T1, np.eye(n0)) + prob.omega**2 * (1 + 0.3j) * np.eye(n0 * n1)
+    assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_plane_wave_interior_residual_vanishes(dim):
+    # P5: e^{i k.x} with sum_d 4 sin^2(k_d h/2)/h^2 = omega^2/c^2 is annihilated by
+    # the interior stencil.  c = 2 (constant) so a D = c^2 slip would show.
+    n = (40, 36, 30)[:dim]
+    prob = wl.small_problem(n, layer=6, ppw=12)
+    prob.c = np.full(prob.shape, 2.0)
+    h, om, c = prob.h, prob.omega, 2.0
+    dirs = np.array([0.6, 0.5, 0.62][:dim])
+    dirs = dirs / np.linalg.norm(dirs)
+    # solve for |k|: sum 4 sin^2(k d_i h/2)/h^2 = (om/c)^2
+    lo, hi = 0.0, math.pi / h
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        val = np.sum(4 * np.sin(mid * dirs * h / 2) ** 2) / h**2
+        lo, hi = (mid, hi) if val < (om / c) ** 2 else (lo, mid)
+    k = 0.5 * (lo + hi) * dirs
+    axes = [np.arange(m) * h for m in n]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    phase = sum(g * kk for g, kk in zip(grids, reversed(k)))
+    u = np.exp(1j * phase).ravel()
+    A = op.helmholtz(prob, 0.0)
+    r = (A @ u).reshape(prob.shape)
+    L = prob.layer
+    inner = tuple(slice(L + 2, m - L - 2) for m in reversed(n))
+    assert np.abs(r[inner]).max() <= 1e-9 * (om / c) ** 2
+    # and the residual is O(1) relative if omega^2 is dropped (sanity of the pin)
+    assert np.abs((A @ u - om**2 / c**2 * u).reshape(prob.shape)[inner]).max() > 0.5 * (om / c) ** 2
+
+
+def _analytic_stretched(x, u, du, d2u, sig, dsig):
+    s = 1 + 1j * sig
+    ds = 1j * dsig
+    return (1 / s) * (d2u / s - du * ds / s**2)
+
+
+def test_pml_axis_operator_second_order_consistent():
+    # (1/s) d/dx((1/s) du/dx) on u vanishing at the ghost nodes; error must fall
+    # like h^2 where the profile is smooth (quadratic profile: sigma' continuous).
+    errs = []
+    for n in (161, 321):
+        h = 1.0 / (n - 1)
+        L = (n - 1) // 8
+        omega = 40.0
+        C = 20.0
+        A = op.axis_matrix(n, L, h, omega, C).toarray()
+        x = np.arange(n) * h
+        a, b = -h, n * h
+        w = math.pi / (b - a)
+        beta = 7.0
+        u = np.sin(w * (x - a)) * np.exp(1j * beta * x)
+        du = (w * np.cos(w * (x - a)) + 1j * beta * np.sin(w * (x - a))) * np.exp(1j * beta * x)
+        d2u = (-w * w * np.sin(w * (x - a)) + 2j * beta * w * np.cos(w * (x - a))
+               - beta * beta * np.sin(w * (x - a))) * np.exp(1j * beta * x)
+        delta = L * h
+        xa, xb = L * h, (n - 1 - L) * h
+        sig = op.pml_sigma(x, n, L, h, omega, C)
+        dsig = np.where(x < xa, -2 * C / (delta * omega) * (xa - x) / delta**2,
+                        np.where(x > xb, 2 * C / (delta * omega) * (x - xb) / delta**2, 0.0))
+        ref = _analytic_stretched(x, u, du, d2u, sig, dsig)
+        got = A @ u
+        mask = (np.abs(x - xa) > 2.5 * h) & (np.abs(x - xb) > 2.5 * h)
+        errs.append(np.abs(got - ref)[mask].max() / np.abs(ref).max())
+    assert errs[1] < errs[0] / 3.0, errs
+    assert errs[1] < 2e-3  # a swapped left/right half-node stretch gives ~1.2
+
+
+def test_pml_sigma_profile_values():
+    # eq. pml-1d-s: zero inside, C/(delta omega) at distance delta, quadratic between
+    n, L, h, om, C = 41, 8, 0.025, 50.0, 20.0
+    x = np.arange(n) * h
+    sig = op.pml_sigma(x, n, L, h, om, C)
+    assert np.all(sig[L:n - L] == 0)
+    assert sig[0] == pytest.approx(C / (L * h * om))
+    assert sig[L // 2] == pytest.approx(C / (L * h * om) * 0.25)
+    assert sig[n - 1] == pytest.approx(sig[0])
+
+
+def test_spectrum_upper_half_plane_and_shift():
+    # P3: min Im eig(A) >= 0 with the layer; homogeneous: eig(A_s) = eig(A) + i omega^2 s
+    prob = wl.small_problem((24, 20), layer=5)
+    A = op.helmholtz(prob, 0.0).toarray()
+    ev = np.linalg.eigvals(A)
+    assert ev.imag.min() > -1e-8 * np.abs(ev).max()
+    s = 0.05
+    evs = np.linalg.eigvals(op.helmholtz(prob, s).toarray())
+    shifted = ev + 1j * prob.omega**2 * s
+    d = np.abs(np.sort_complex(evs)[:, None] - shifted[None, :]).min(axis=1)
+    assert d.max() <= 1e-8 * np.abs(ev).max()
+
+
+def test_apply_rows_matches_assembled_matrix():
+    prob = wl.small_problem((13, 11, 9), layer=3, inhomogeneous=True, seed=3)
+    x = wl.random_vector(prob.npts, 7)
+    As = op.helmholtz(prob, 0.07)
+    pts = np.array([0, 5, 100, 500, prob.npts - 1, 13 * 11 * 4 + 13 * 5 + 6])
+    assert np.allclose(op.apply_rows(prob, 0.07, x, pts), (As @ x)[pts], rtol=1e-13, atol=0)
+
+
+def test_greens_function_2d_outgoing():
+    # P6: delta source, homogeneous, with the layer: u ~ (i/4) H0^(1)(k r)
+    # (e^{-i omega t} convention).  ppw 30 keeps dispersion error ~1%.
+    from scipy.special import hankel1
+    n = 161
+    prob = wl.small_problem((n, n), layer=30, ppw=30)
+    f = wl.delta_source(prob, (n // 2, n // 2))
+    u = op.helmholtz(prob, 0.0)
+    import scipy.sparse.linalg as spla
+    sol = spla.splu(u.tocsc()).solve(op.rhs(f)).reshape(prob.shape)
+    h = prob.h
+    y, x = np.meshgrid(np.arange(n) * h, np.arange(n) * h, indexing="ij")
+    r = np.hypot(x - (n // 2) * h, y - (n // 2) * h)
+    ann = (r > 10 * h) & (r < 0.3)
+    green = 0.25j * hankel1(0, prob.omega * r[ann])
+    rel = np.linalg.norm(sol[ann] - green) / np.linalg.norm(green)
+    assert rel < 0.05, rel
+    # incoming (H0^(2)) must be far off: guards the sign of the layer
+    wrong = 0.25j * np.conj(hankel1(0, prob.omega * r[ann]))
+    assert np.linalg.norm(sol[ann] - wrong) / np.linalg.norm(wrong) > 0.5
