@@ -1,0 +1,194 @@
+"""Benchmark: time to solve the 2D inhomogeneous Helmholtz workload
+(2048^2 grid, Gaussian-random-field speed in [1, 3], ppw 8 at c_min,
+32-cell absorbing layer, one point source) to 1e-6 relative residual with
+MatExPre-preconditioned FGMRES on one MI355X.
+
+One step = one complete solve (outer FGMRES, every preconditioner apply,
+every exp / psi_1 action) in the chosen mixed form (complex-float stepping,
+complex-double Krylov bases and true residual).  The plain complex-double
+solve is timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2506_03617_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    rec = data.get(f"{kernel}@{workload}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, f, actions_per_solve: int, fraction: int = 16):
+    """The oracle, as it stands, on a bounded sample: one exp(i (t/fraction) A_s) v
+    action (SciPy expm_multiply, whose work grows linearly with t ||A||) at the
+    full grid, scaled by `fraction` and by the number of matrix-function actions
+    one GPU solve performs."""
+    from oracle import matfun, operator as op
+    threads = os.environ.get("OMP_NUM_THREADS")
+    As = op.helmholtz(prob, prob.default_shift())
+    v = f.ravel().astype(np.complex128)
+    t0 = time.perf_counter()
+    matfun.exp_action(As, prob.default_t() / fraction, v)
+    t_sample = time.perf_counter() - t0
+    return {
+        "value": round(t_sample * fraction * actions_per_solve, 1),
+        "unit": "s per solve (extrapolated)",
+        "cores": int(threads) if threads else os.cpu_count(),
+        "kind": "oracle",
+        "sample": f"one exp(i(t/{fraction})A_s)v action at {prob.n[0]}x{prob.n[1]} by expm_multiply "
+                  f"({t_sample:.1f} s), times {fraction} and {actions_per_solve} actions per solve",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="2d-grf-2048", choices=["2d-grf-2048", "2d-homog-128"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--roofline-reps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part "
+              "of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2506_03617_amd as mxp
+    import workloads as wl
+
+    prob = wl.config2() if args.workload == "2d-grf-2048" else wl.config1()
+    centre = tuple(m // 2 for m in prob.n)
+    f = wl.delta_source(prob, centre)
+    ctx = mxp.Context(0)
+    P = mxp.Problem(ctx, prob)
+    fd = torch.from_numpy(f.ravel()).to("cuda:0")
+    ud = torch.zeros_like(fd)
+    o_mixed = P.default_opts()
+    o_mixed.precision = mxp.MXP_PREC_MIXED
+    print(f"[bench] {prob.name}: n={prob.n} omega={prob.omega:.2f} t={o_mixed.t:.3e} "
+          f"s={o_mixed.shift:.4f}", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        ud.zero_()
+        st = mxp.mxp_solve(P, o_mixed, fd, ud)
+        print(f"[bench] warmup {w}: {st}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ud.zero_()
+        st = mxp.mxp_solve(P, o_mixed, fd, ud)
+        stats.append(st)
+        print(f"[bench] step {k}: {st}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s_per_solve = elapsed / args.steps
+    st = stats[-1]
+
+    fp64 = None
+    if not args.no_fp64:
+        o64 = P.default_opts()
+        ud.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st64 = mxp.mxp_solve(P, o64, fd, ud)
+        torch.cuda.synchronize()
+        fp64 = {"seconds": time.perf_counter() - t1, **{k: st64[k] for k in
+                ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions", "true_relres")}}
+        print(f"[bench] fp64: {fp64}", file=sys.stderr, flush=True)
+
+    # Dominant kernel: the complex-float Clenshaw stencil step.  Average launch
+    # duration from HIP events around complete exp actions on the library's
+    # stream (torch's current stream), divided by the stencil steps they run.
+    sch = mxp.mxp_design_schedule(P.desc, o_mixed.t, o_mixed.shift, mxp.MXP_PREC_MIXED)
+    steps_per_action = sch.S * sch.m
+    x32 = torch.randn(prob.npts, dtype=torch.complex64, device="cuda:0")
+    y32 = torch.empty_like(x32)
+    mxp.mxp_apply_exp(P, o_mixed.t, o_mixed.shift, x32, y32)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.roofline_reps):
+        mxp.mxp_apply_exp(P, o_mixed.t, o_mixed.shift, x32, y32)
+    ev1.record()
+    torch.cuda.synchronize()
+    avg_launch_s = ev0.elapsed_time(ev1) * 1e-3 / (args.roofline_reps * steps_per_action)
+    # algorithmic bytes per point of one step: read b_{k+1}, b_{k+2}, x (8 B each),
+    # D (4 B, inhomogeneous), write b_k (8 B)
+    bpp = 8 * 4 + (0 if prob.c is None else 4)
+    bytes_per_launch = bpp * prob.npts
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = load_traffic("stencil_c64", prob.name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": "k_stencil<float,2> (Clenshaw step)",
+                "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": bytes_per_launch}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(prob, f, int(st["fn_actions"]))
+        print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "s to 1e-6 rel. residual (plain vs FP32/learned); stencil HBM GB/s vs peak",
+        "value": round(s_per_solve, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(s_per_solve * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 stepping + c128 Krylov",
+        "data": "synthetic (seeded GRF speed, point source)",
+        "config": {"workload": prob.name, "grid": list(prob.n), "omega": round(prob.omega, 3),
+                   "layer": prob.layer, "t": o_mixed.t, "shift": o_mixed.shift, "fprtol": o_mixed.fprtol,
+                   "rtol": o_mixed.rtol, "outer_restart": o_mixed.outer_restart,
+                   "inner_restart": o_mixed.inner_restart, "precision": "mixed"},
+        "solve": {k: st[k] for k in ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions",
+                                     "true_relres")},
+        "schedule_c64": {"S": sch.S, "m": sch.m, "m_psi": sch.m_psi},
+        "plain_fp64": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    P.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,304 @@
+"""Python binding of libmatexpre (the MatExPre hot path on one MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Functions carry the C-ABI names and take torch tensors (device
+vectors), returning results or raising MxpError on a negative status.  The
+library must have been built (paper_2506_03617_amd.build); importing this
+module fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmatexpre.so")
+
+MXP_OK = 0
+MXP_NOT_CONVERGED = 1
+MXP_ERR_INVALID_ARG = -1
+MXP_ERR_OOM = -2
+MXP_ERR_HIP = -3
+MXP_ERR_BREAKDOWN = -4
+MXP_ERR_NONFINITE = -5
+MXP_ERR_UNSUPPORTED = -6
+
+MXP_C64, MXP_C128, MXP_F32, MXP_F64 = 0, 1, 2, 3
+MXP_PREC_FP64, MXP_PREC_MIXED = 0, 1
+
+
+class MxpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"status {status}: {message}")
+        self.status = status
+
+
+class mxp_grid_desc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("h", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("layer", (ctypes.c_int32 * 2) * 3),
+        ("pml_C", ctypes.c_double),
+        ("pml_power", ctypes.c_int32),
+        ("c", ctypes.c_void_p),
+        ("c_dtype", ctypes.c_int),
+        ("c_const", ctypes.c_double),
+    ]
+
+
+class mxp_solve_opts(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double),
+        ("shift", ctypes.c_double),
+        ("fprtol", ctypes.c_double),
+        ("rtol", ctypes.c_double),
+        ("outer_restart", ctypes.c_int32),
+        ("inner_restart", ctypes.c_int32),
+        ("max_outer", ctypes.c_int32),
+        ("max_inner", ctypes.c_int32),
+        ("precision", ctypes.c_int),
+        ("cheb_S", ctypes.c_int32),
+        ("cheb_m", ctypes.c_int32),
+    ]
+
+
+class mxp_solve_stats(ctypes.Structure):
+    _fields_ = [
+        ("outer_its", ctypes.c_int32),
+        ("inner_its_total", ctypes.c_int32),
+        ("inner_mean", ctypes.c_double),
+        ("inner_std", ctypes.c_double),
+        ("stencil_steps", ctypes.c_int64),
+        ("fn_actions", ctypes.c_int64),
+        ("true_relres", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("restarts", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class mxp_schedule(ctypes.Structure):
+    _fields_ = [
+        ("S", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("m_psi", ctypes.c_int32),
+        ("centre_re", ctypes.c_double),
+        ("centre_im", ctypes.c_double),
+        ("half_width", ctypes.c_double),
+        ("box", ctypes.c_double * 4),
+        ("trunc_bound", ctypes.c_double),
+        ("amplification", ctypes.c_double),
+        ("coef", ctypes.c_double * 1024),
+        ("coef_psi", ctypes.c_double * 1024),
+    ]
+
+    def coefficients(self) -> np.ndarray:
+        a = np.ctypeslib.as_array(self.coef)[: 2 * (self.m + 1)]
+        return a[0::2] + 1j * a[1::2]
+
+    def coefficients_psi(self) -> np.ndarray:
+        a = np.ctypeslib.as_array(self.coef_psi)[: 2 * (self.m_psi + 1)]
+        return a[0::2] + 1j * a[1::2]
+
+
+# C-ABI symbols declared in include/matexpre.h
+ABI_SYMBOLS = (
+    "mxp_context_create", "mxp_context_destroy", "mxp_last_error", "mxp_version",
+    "mxp_problem_create", "mxp_problem_destroy", "mxp_problem_size",
+    "mxp_solve_opts_default", "mxp_design_schedule",
+    "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_precond", "mxp_solve",
+)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_03617_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    st = ctypes.c_int
+    sig = {
+        "mxp_context_create": (st, [ctypes.c_int, P, ctypes.POINTER(P)]),
+        "mxp_context_destroy": (None, [P]),
+        "mxp_last_error": (ctypes.c_char_p, []),
+        "mxp_version": (ctypes.c_char_p, []),
+        "mxp_problem_create": (st, [P, ctypes.POINTER(mxp_grid_desc), ctypes.POINTER(P)]),
+        "mxp_problem_destroy": (None, [P]),
+        "mxp_problem_size": (ctypes.c_int64, [P]),
+        "mxp_solve_opts_default": (st, [ctypes.POINTER(mxp_grid_desc), ctypes.POINTER(mxp_solve_opts)]),
+        "mxp_design_schedule": (st, [ctypes.POINTER(mxp_grid_desc), ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.POINTER(mxp_schedule)]),
+        "mxp_apply_A": (st, [P, ctypes.c_double, ctypes.c_int, P, P]),
+        "mxp_apply_exp": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
+        "mxp_apply_psi1": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
+        "mxp_apply_precond": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(ctypes.c_int32)]),
+        "mxp_solve": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(mxp_solve_stats)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int, allow_not_converged: bool = False) -> int:
+    if status < 0 or (status == MXP_NOT_CONVERGED and not allow_not_converged):
+        raise MxpError(status, lib.mxp_last_error().decode())
+    return status
+
+
+def mxp_version() -> str:
+    return lib.mxp_version().decode()
+
+
+def grid_desc(prob, c_host: Optional[np.ndarray] = None) -> mxp_grid_desc:
+    """mxp_grid_desc from a workloads.Problem (c taken from prob.c as float64
+    host array unless c_host is given).  The returned struct keeps a reference
+    to the array it points at."""
+    d = mxp_grid_desc()
+    d.dim = prob.dim
+    n = list(prob.n) + [1] * (3 - prob.dim)
+    for a in range(3):
+        d.n[a] = n[a]
+    d.h = prob.h
+    d.omega = prob.omega
+    for a in range(3):
+        L = prob.layer if a < prob.dim else 0
+        d.layer[a][0] = L
+        d.layer[a][1] = L
+    d.pml_C = prob.pml_C
+    d.pml_power = prob.pml_power
+    c = c_host if c_host is not None else prob.c
+    if c is None:
+        d.c = None
+        d.c_dtype = MXP_F64
+        d.c_const = prob.c_const
+    else:
+        arr = np.ascontiguousarray(c)
+        if arr.dtype == np.float32:
+            d.c_dtype = MXP_F32
+        else:
+            arr = np.ascontiguousarray(arr, dtype=np.float64)
+            d.c_dtype = MXP_F64
+        d._keep = arr
+        d.c = arr.ctypes.data
+        d.c_const = 0.0
+    return d
+
+
+def mxp_solve_opts_default(desc: mxp_grid_desc) -> mxp_solve_opts:
+    o = mxp_solve_opts()
+    _check(lib.mxp_solve_opts_default(ctypes.byref(desc), ctypes.byref(o)))
+    return o
+
+
+def mxp_design_schedule(desc: mxp_grid_desc, t: float, shift: float, precision: int) -> mxp_schedule:
+    s = mxp_schedule()
+    _check(lib.mxp_design_schedule(ctypes.byref(desc), t, shift, precision, ctypes.byref(s)))
+    return s
+
+
+def _ptr(tensor) -> int:
+    return tensor.data_ptr()
+
+
+def _dtype_of(tensor) -> int:
+    import torch
+    if tensor.dtype == torch.complex128:
+        return MXP_C128
+    if tensor.dtype == torch.complex64:
+        return MXP_C64
+    raise TypeError("vectors must be torch.complex64 or torch.complex128")
+
+
+class Context:
+    """mxp_context bound to a CUDA/HIP device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        handle = ctypes.c_void_p()
+        _check(lib.mxp_context_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(handle)))
+        self.handle = handle
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib.mxp_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """mxp_problem for a workloads.Problem description."""
+
+    def __init__(self, ctx: Context, prob):
+        self.ctx = ctx
+        self.desc = grid_desc(prob)
+        self.spec = prob
+        handle = ctypes.c_void_p()
+        _check(lib.mxp_problem_create(ctx.handle, ctypes.byref(self.desc), ctypes.byref(handle)))
+        self.handle = handle
+
+    @property
+    def size(self) -> int:
+        return int(lib.mxp_problem_size(self.handle))
+
+    def default_opts(self) -> mxp_solve_opts:
+        return mxp_solve_opts_default(self.desc)
+
+    def close(self):
+        if self.handle:
+            lib.mxp_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mxp_apply_A(prob: Problem, shift: float, x, y) -> None:
+    _check(lib.mxp_apply_A(prob.handle, shift, _dtype_of(x), _ptr(x), _ptr(y)))
+
+
+def mxp_apply_exp(prob: Problem, t: float, shift: float, x, y) -> None:
+    _check(lib.mxp_apply_exp(prob.handle, t, shift, _dtype_of(x), _ptr(x), _ptr(y)))
+
+
+def mxp_apply_psi1(prob: Problem, t: float, shift: float, x, y) -> None:
+    _check(lib.mxp_apply_psi1(prob.handle, t, shift, _dtype_of(x), _ptr(x), _ptr(y)))
+
+
+def mxp_apply_precond(prob: Problem, opts: mxp_solve_opts, r, w) -> int:
+    its = ctypes.c_int32(0)
+    _check(lib.mxp_apply_precond(prob.handle, ctypes.byref(opts), _ptr(r), _ptr(w), ctypes.byref(its)))
+    return its.value
+
+
+def mxp_solve(prob: Problem, opts: mxp_solve_opts, f, u) -> dict:
+    st = mxp_solve_stats()
+    status = _check(lib.mxp_solve(prob.handle, ctypes.byref(opts), _ptr(f), _ptr(u), ctypes.byref(st)),
+                    allow_not_converged=True)
+    out = st.as_dict()
+    out["status"] = status
+    return out

@@ -1,0 +1,833 @@
+// C ABI of the MatExPre library: contexts, problems, matrix-function actions,
+// the preconditioner of Algorithm 1 and the outer flexible GMRES.
+//
+// Paper passages implemented here:
+//   * Section 3.1 (eq. inverse-1): exp(i t A) and psi_1(i t A) actions;
+//     t psi_1(i t A) r = sum_{k<S} exp(i k tau A) tau psi_1(i tau A) r, tau = t/S
+//     (semigroup property plus the variation-of-constants integral);
+//   * Section 3.4 (eq. fixed-point, Algorithm 1): inner GMRES on
+//     (I - exp(i t A_s)) w = psi_1(i t A_s) r to relative tolerance fprtol;
+//   * Section 3.4: complex shift A_s = A + i omega^2 s D; outer flexible GMRES
+//     (constant -i t dropped);
+//   * Section 4 introduction: restart 30 for both solvers.
+// Orthogonalisation is classical Gram--Schmidt with one re-orthogonalisation
+// (CGS2: two fused multi-dot / multi-update passes); the small least-squares
+// problems use Givens rotations on the host in double.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+#include "mxp_internal.h"
+
+struct mxp_context {
+    int device;
+    hipStream_t stream;
+};
+
+namespace mxp {
+
+thread_local std::string g_last_error;
+
+#define HIP_CHECK(expr)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) fail(MXP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Owned device allocation.
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t want) {
+        if (want <= bytes) return;
+        release();
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(MXP_ERR_OOM, "device allocation of " + std::to_string(want) + " bytes failed");
+        }
+        bytes = want;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename R>
+struct DevTables {
+    cpx<R>* alpha[3] = {nullptr, nullptr, nullptr};
+    cpx<R>* beta[3] = {nullptr, nullptr, nullptr};
+    cpx<R>* gamma[3] = {nullptr, nullptr, nullptr};
+};
+
+struct Sched {
+    mxp_schedule s;
+};
+
+}  // namespace mxp
+
+struct mxp_problem {
+    mxp_context* ctx;
+    mxp::GridInfo g;
+    mxp::DevMem tables64, tables32, D64, D32;
+    mxp::DevTables<double> t64;
+    mxp::DevTables<float> t32;
+    std::map<std::tuple<double, double, int, int, int>, std::unique_ptr<mxp::Sched>> scheds;
+    // workspaces
+    mxp::DevMem act64[4], act32[6];
+    mxp::DevMem innerV, innerRh, innerTmp, innerRr;
+    mxp::DevMem outerV, outerZ, outerR;
+    mxp::DevMem partial, small;
+    std::vector<mxp::cpx<double>> host_small;
+};
+
+namespace mxp {
+
+static int64_t npts(const mxp_problem* P) { return P->g.npts(); }
+
+template <typename R>
+static void upload_tables(mxp_problem* P, DevMem& mem, DevTables<R>& t) {
+    const GridInfo& g = P->g;
+    size_t total = 0;
+    for (int d = 0; d < 3; ++d) total += size_t(g.n[d]) * 3;
+    std::vector<cpx<R>> host(total);
+    size_t off = 0;
+    size_t offs[3][3];
+    for (int d = 0; d < 3; ++d) {
+        AxisTables at;
+        if (d < g.dim) {
+            at = build_axis_tables(g.axis(d));
+        } else {  // unused third axis in 2D: a single node with zero coefficients
+            at.alpha.assign(g.n[d], cd(0, 0));
+            at.beta.assign(g.n[d], cd(0, 0));
+            at.gamma.assign(g.n[d], cd(0, 0));
+        }
+        const std::vector<cd>* src[3] = {&at.alpha, &at.beta, &at.gamma};
+        for (int q = 0; q < 3; ++q) {
+            offs[d][q] = off;
+            for (int64_t i = 0; i < g.n[d]; ++i)
+                host[off + i] = {R((*src[q])[i].real()), R((*src[q])[i].imag())};
+            off += g.n[d];
+        }
+    }
+    mem.ensure(total * sizeof(cpx<R>));
+    HIP_CHECK(hipMemcpyAsync(mem.p, host.data(), total * sizeof(cpx<R>), hipMemcpyHostToDevice,
+                             P->ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(P->ctx->stream));
+    cpx<R>* base = mem.as<cpx<R>>();
+    for (int d = 0; d < 3; ++d) {
+        t.alpha[d] = base + offs[d][0];
+        t.beta[d] = base + offs[d][1];
+        t.gamma[d] = base + offs[d][2];
+    }
+}
+
+static const mxp_schedule& get_schedule(mxp_problem* P, double t, double shift, mxp_precision prec,
+                                        int forceS, int forcem) {
+    auto key = std::make_tuple(t, shift, int(prec), forceS, forcem);
+    auto it = P->scheds.find(key);
+    if (it != P->scheds.end()) return it->second->s;
+    auto sc = std::make_unique<Sched>();
+    design_schedule(P->g, t, shift, prec, &sc->s, forceS, forcem);
+    const mxp_schedule& ref = sc->s;
+    P->scheds.emplace(key, std::move(sc));
+    return ref;
+}
+
+template <typename R>
+static StencilArgs<R> base_args(mxp_problem* P, double shift) {
+    StencilArgs<R> a{};
+    const GridInfo& g = P->g;
+    a.dim = g.dim;
+    a.n0 = g.n[0];
+    a.n1 = g.n[1];
+    a.n2 = g.n[2];
+    const DevTables<R>* t;
+    if constexpr (sizeof(R) == 8) t = &P->t64; else t = &P->t32;
+    for (int d = 0; d < 3; ++d) {
+        a.alpha[d] = t->alpha[d];
+        a.beta[d] = t->beta[d];
+        a.gamma[d] = t->gamma[d];
+    }
+    if (g.homogeneous) {
+        a.D = nullptr;
+        a.Dconst = R(1.0 / (g.c_const * g.c_const));
+    } else {
+        if constexpr (sizeof(R) == 8) a.D = P->D64.as<double>(); else a.D = P->D32.as<float>();
+        a.Dconst = R(0);
+    }
+    const double w2 = g.omega * g.omega;
+    a.kD = {R(w2), R(w2 * shift)};
+    a.kc = {R(0), R(0)};
+    a.g = {R(1), R(0)};
+    a.cx = a.e2 = a.e3 = {R(0), R(0)};
+    return a;
+}
+
+template <typename R>
+static cpx<R> to_cpx(cd v) { return {R(v.real()), R(v.imag())}; }
+
+static cd coef_at(const double* c, int k) { return cd(c[2 * k], c[2 * k + 1]); }
+
+// out = post * (sum_{k<=m} c_k T_k(Ahat) x + add), Ahat = (A_s - centre)/hw,
+// by the Clenshaw recurrence b_k = c_k x + 2 Ahat b_{k+1} - b_{k+2}.
+// bufA, bufB: scratch distinct from x, add and out.  out may equal x.
+template <typename R>
+static void cheb_series(mxp_problem* P, const StencilArgs<R>& base, const mxp_schedule& sc,
+                        const double* coef, int m, const cpx<R>* x, cpx<R>* out, cpx<R>* bufA,
+                        cpx<R>* bufB, cd post, const cpx<R>* add, int64_t* steps) {
+    hipStream_t s = P->ctx->stream;
+    const cd c0(sc.centre_re, sc.centre_im);
+    const double hw = sc.half_width;
+    StencilArgs<R> a = base;
+    a.kc = to_cpx<R>(-c0);
+    a.x = x;
+    // b_{m-1} = c_{m-1} x + 2 Ahat (c_m x)
+    a.b1 = x;
+    a.g = to_cpx<R>(coef_at(coef, m) * (2.0 / hw));
+    a.cx = to_cpx<R>(coef_at(coef, m - 1));
+    a.b2 = nullptr;
+    a.b3 = nullptr;
+    a.out = bufA;
+    launch_stencil(a, s);
+    // b_{m-2} = c_{m-2} x + 2 Ahat b_{m-1} - c_m x
+    a.b1 = bufA;
+    a.g = to_cpx<R>(cd(2.0 / hw, 0.0));
+    a.cx = to_cpx<R>(coef_at(coef, m - 2) - coef_at(coef, m));
+    a.out = bufB;
+    launch_stencil(a, s);
+    cpx<R>* cur = bufB;   // b_{k+1}
+    cpx<R>* prev = bufA;  // b_{k+2}
+    for (int k = m - 3; k >= 1; --k) {
+        a.b1 = cur;
+        a.b2 = prev;
+        a.e2 = {R(-1), R(0)};
+        a.cx = to_cpx<R>(coef_at(coef, k));
+        a.out = prev;
+        launch_stencil(a, s);
+        std::swap(cur, prev);
+    }
+    // out = post * (c_0 x + Ahat b_1 - b_2 + add)
+    a.b1 = cur;
+    a.b2 = prev;
+    a.g = to_cpx<R>(post / hw);
+    a.cx = to_cpx<R>(post * coef_at(coef, 0));
+    a.e2 = to_cpx<R>(-post);
+    a.b3 = add;
+    a.e3 = to_cpx<R>(post);
+    a.out = out;
+    launch_stencil(a, s);
+    *steps += m;
+}
+
+template <typename R>
+static DevMem* act_buffers(mxp_problem* P) {
+    if constexpr (sizeof(R) == 8) return P->act64; else return P->act32;
+}
+
+// y = exp(i t A_s) x (psi = false) or psi_1(i t A_s) x (psi = true), precision R.
+// x and y distinct device vectors of precision R.
+template <typename R>
+static void action(mxp_problem* P, const mxp_schedule& sc, double t, double shift, bool psi,
+                   const cpx<R>* x, cpx<R>* y, int64_t* steps) {
+    const int64_t n = npts(P);
+    DevMem* W = act_buffers<R>(P);
+    for (int q = 0; q < 4; ++q) W[q].ensure(size_t(n) * sizeof(cpx<R>));
+    cpx<R>* w[3] = {W[0].as<cpx<R>>(), W[1].as<cpx<R>>(), W[2].as<cpx<R>>()};
+    cpx<R>* pbuf = W[3].as<cpx<R>>();
+    const StencilArgs<R> base = base_args<R>(P, shift);
+    const int S = sc.S;
+    auto others = [&](const cpx<R>* cur, cpx<R>** a, cpx<R>** b) {
+        int k = 0;
+        cpx<R>* pick[2];
+        for (int q = 0; q < 3 && k < 2; ++q)
+            if (w[q] != cur) pick[k++] = w[q];
+        *a = pick[0];
+        *b = pick[1];
+    };
+    const cpx<R>* xcur = x;
+    int first = 0;
+    const cpx<R>* add = nullptr;
+    if (psi) {
+        // p = tau psi_1(i tau A_s) x; with S == 1 the answer is p / t.
+        cpx<R>* bA = w[0];
+        cpx<R>* bB = w[1];
+        if (S == 1) {
+            cheb_series<R>(P, base, sc, sc.coef_psi, sc.m_psi, x, y, bA, bB, cd(1.0 / t, 0), nullptr, steps);
+            return;
+        }
+        cheb_series<R>(P, base, sc, sc.coef_psi, sc.m_psi, x, pbuf, bA, bB, cd(1.0, 0), nullptr, steps);
+        xcur = pbuf;
+        add = pbuf;
+        first = 1;
+    }
+    for (int sub = first; sub < S; ++sub) {
+        const bool last = (sub == S - 1);
+        cpx<R>* bA;
+        cpx<R>* bB;
+        others(xcur, &bA, &bB);
+        // The final Clenshaw step writes in place over b_2.  After the two
+        // opening steps b_{m-1} sits in bA and b_{m-2} in bB; each of the m-3
+        // loop steps swaps the roles, so b_2 ends in bA when m-3 is even.
+        cpx<R>* b2buf = ((sc.m - 3) % 2 == 0) ? bA : bB;
+        cpx<R>* out = last ? y : b2buf;
+        const cd post = (psi && last) ? cd(1.0 / t, 0.0) : cd(1.0, 0.0);
+        cheb_series<R>(P, base, sc, sc.coef, sc.m, xcur, out, bA, bB, post, add, steps);
+        xcur = out;
+    }
+}
+
+// ------------------------------------------------------------ Krylov helpers
+
+struct Small {
+    cpx<double>* partial;
+    cpx<double>* h1;
+    cpx<double>* h2;
+    cpx<double>* nrm;
+    cpx<double>* y;
+};
+
+static Small small_buffers(mxp_problem* P) {
+    const int64_t n = npts(P);
+    const int nb = reduce_blocks(n);
+    P->partial.ensure(size_t(nb) * 256 * sizeof(cpx<double>));
+    P->small.ensure(size_t(1024) * sizeof(cpx<double>));
+    P->host_small.resize(1024);
+    cpx<double>* sm = P->small.as<cpx<double>>();
+    return Small{P->partial.as<cpx<double>>(), sm, sm + 256, sm + 512, sm + 768};
+}
+
+static double norm2(mxp_problem* P, const cpx<double>* v) {
+    Small sm = small_buffers(P);
+    launch_nrm2sq(v, npts(P), sm.partial, sm.nrm, P->ctx->stream);
+    cpx<double> hv;
+    HIP_CHECK(hipMemcpyAsync(&hv, sm.nrm, sizeof(hv), hipMemcpyDeviceToHost, P->ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(P->ctx->stream));
+    if (!std::isfinite(hv.re)) fail(MXP_ERR_NONFINITE, "non-finite vector norm");
+    return std::sqrt(hv.re);
+}
+
+// CGS2: orthogonalise w against V_0..V_{nv-1}; h receives the projection
+// coefficients and the returned value is ||w|| afterwards.
+static double cgs2(mxp_problem* P, const cpx<double>* V, int64_t ld, int nv, cpx<double>* w,
+                   std::vector<cd>& h) {
+    const int64_t n = npts(P);
+    hipStream_t s = P->ctx->stream;
+    Small sm = small_buffers(P);
+    launch_mdot(V, ld, nv, w, n, sm.partial, sm.h1, s);
+    launch_mupdate(w, V, ld, nv, sm.h1, n, s);
+    launch_mdot(V, ld, nv, w, n, sm.partial, sm.h2, s);
+    launch_mupdate(w, V, ld, nv, sm.h2, n, s);
+    launch_nrm2sq(w, n, sm.partial, sm.nrm, s);
+    HIP_CHECK(hipMemcpyAsync(P->host_small.data(), P->small.p, 513 * sizeof(cpx<double>),
+                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    h.resize(nv);
+    for (int i = 0; i < nv; ++i)
+        h[i] = cd(P->host_small[i].re + P->host_small[256 + i].re,
+                  P->host_small[i].im + P->host_small[256 + i].im);
+    const double nn = P->host_small[512].re;
+    if (!std::isfinite(nn)) fail(MXP_ERR_NONFINITE, "non-finite value in the Arnoldi process");
+    return std::sqrt(nn);
+}
+
+// Incremental QR of the Hessenberg matrix by Givens rotations.
+struct Givens {
+    int m;
+    std::vector<cd> H;  // column-major (m+1) x m, rotated in place to R
+    std::vector<double> c;
+    std::vector<cd> s, g;
+    explicit Givens(int m_) : m(m_), H(size_t(m_ + 1) * m_), c(m_), s(m_), g(m_ + 1) {}
+    void reset(double beta) {
+        std::fill(H.begin(), H.end(), cd(0));
+        std::fill(g.begin(), g.end(), cd(0));
+        g[0] = beta;
+    }
+    cd& at(int i, int j) { return H[size_t(j) * (m + 1) + i]; }
+    // column j: h[0..j] and subdiagonal beta; returns |g_{j+1}|
+    double add_column(int j, const std::vector<cd>& h, double beta) {
+        for (int i = 0; i <= j; ++i) at(i, j) = h[i];
+        at(j + 1, j) = beta;
+        for (int i = 0; i < j; ++i) {
+            const cd a = at(i, j), b = at(i + 1, j);
+            at(i, j) = c[i] * a + s[i] * b;
+            at(i + 1, j) = -std::conj(s[i]) * a + c[i] * b;
+        }
+        const cd a = at(j, j);
+        const double b = std::abs(at(j + 1, j));
+        if (b == 0.0) {
+            c[j] = 1.0;
+            s[j] = 0.0;
+        } else if (std::abs(a) == 0.0) {
+            c[j] = 0.0;
+            s[j] = 1.0;
+            at(j, j) = b;
+        } else {
+            const double r = std::hypot(std::abs(a), b);
+            const cd ph = a / std::abs(a);
+            c[j] = std::abs(a) / r;
+            s[j] = ph * b / r;
+            at(j, j) = ph * r;
+        }
+        at(j + 1, j) = 0.0;
+        g[j + 1] = -std::conj(s[j]) * g[j];
+        g[j] = c[j] * g[j];
+        return std::abs(g[j + 1]);
+    }
+    std::vector<cd> solve(int k) {
+        std::vector<cd> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+            cd acc = g[i];
+            for (int q = i + 1; q < k; ++q) acc -= at(i, q) * y[q];
+            if (std::abs(at(i, i)) == 0.0)
+                fail(MXP_ERR_BREAKDOWN, "singular Hessenberg factor (the preconditioner returned zero)");
+            y[i] = acc / at(i, i);
+        }
+        return y;
+    }
+};
+
+static void upload_coeffs(mxp_problem* P, const std::vector<cd>& y) {
+    Small sm = small_buffers(P);
+    std::vector<cpx<double>> tmp(y.size());
+    for (size_t i = 0; i < y.size(); ++i) tmp[i] = {y[i].real(), y[i].imag()};
+    HIP_CHECK(hipMemcpyAsync(sm.y, tmp.data(), tmp.size() * sizeof(cpx<double>), hipMemcpyHostToDevice,
+                             P->ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(P->ctx->stream));
+}
+
+// y = exp or psi_1 action on complex-double vectors, in the requested precision.
+static void action64(mxp_problem* P, const mxp_schedule& sc, double t, double shift, bool psi,
+                     mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps) {
+    if (prec == MXP_PREC_FP64) {
+        action<double>(P, sc, t, shift, psi, x, y, steps);
+        return;
+    }
+    const int64_t n = npts(P);
+    P->act32[4].ensure(size_t(n) * sizeof(cpx<float>));
+    P->act32[5].ensure(size_t(n) * sizeof(cpx<float>));
+    cpx<float>* xs = P->act32[4].as<cpx<float>>();
+    cpx<float>* ys = P->act32[5].as<cpx<float>>();
+    launch_to_c64(x, xs, n, P->ctx->stream);
+    action<float>(P, sc, t, shift, psi, xs, ys, steps);
+    launch_to_c128(ys, y, n, P->ctx->stream);
+}
+
+struct Counters {
+    int64_t steps = 0, actions = 0;
+};
+
+// Algorithm 1.  r, w: complex double device vectors.
+static int precond(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w,
+                   Counters& cnt) {
+    const int64_t n = npts(P);
+    hipStream_t s = P->ctx->stream;
+    const mxp_schedule& sc = get_schedule(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
+    const int m = o.inner_restart;
+    P->innerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
+    P->innerRh.ensure(size_t(n) * sizeof(cpx<double>));
+    P->innerTmp.ensure(size_t(n) * sizeof(cpx<double>));
+    P->innerRr.ensure(size_t(n) * sizeof(cpx<double>));
+    cpx<double>* V = P->innerV.as<cpx<double>>();
+    cpx<double>* rhat = P->innerRh.as<cpx<double>>();
+    cpx<double>* tmp = P->innerTmp.as<cpx<double>>();
+    cpx<double>* rr = P->innerRr.as<cpx<double>>();
+    const cpx<double> one{1.0, 0.0}, mone{-1.0, 0.0};
+
+    // r_hat = psi_1(i t A_s) r; z = ||r_hat||
+    action64(P, sc, o.t, o.shift, true, o.precision, r, rhat, &cnt.steps);
+    cnt.actions++;
+    const double z = norm2(P, rhat);
+    launch_zero<double>(w, n, s);
+    const double tol = o.fprtol * z;
+    // Algorithm 1 tests the tolerance before the first inner iteration.
+    if (z == 0.0 || z <= tol) return 0;
+    const cpx<double>* rcur = rhat;
+    double beta = z;
+    int its = 0;
+    Givens gv(m);
+    std::vector<cd> h;
+    while (true) {
+        launch_scale({1.0 / beta, 0.0}, rcur, V, n, s);
+        gv.reset(beta);
+        int k = 0;
+        bool conv = false;
+        for (int j = 0; j < m; ++j) {
+            cpx<double>* vj = V + size_t(j) * n;
+            cpx<double>* vn = V + size_t(j + 1) * n;
+            action64(P, sc, o.t, o.shift, false, o.precision, vj, tmp, &cnt.steps);
+            cnt.actions++;
+            // v_{j+1} <- v_j - exp(i t A_s) v_j
+            launch_scale(one, vj, vn, n, s);
+            launch_axpby(mone, tmp, one, vn, n, s);
+            const double hn = cgs2(P, V, n, j + 1, vn, h);
+            ++its;
+            const double res = gv.add_column(j, h, hn);
+            if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite inner residual estimate");
+            const bool breakdown = hn <= 1e-14 * beta;
+            if (!breakdown) launch_scale({1.0 / hn, 0.0}, vn, vn, n, s);
+            k = j + 1;
+            if (res <= tol || breakdown) {
+                conv = true;
+                break;
+            }
+            if (its >= o.max_inner) break;
+        }
+        const std::vector<cd> y = gv.solve(k);
+        upload_coeffs(P, y);
+        launch_mcombine(w, V, n, k, small_buffers(P).y, n, s);
+        if (conv || its >= o.max_inner) break;
+        // restart: r = r_hat - (w - exp(i t A_s) w)
+        action64(P, sc, o.t, o.shift, false, o.precision, w, tmp, &cnt.steps);
+        cnt.actions++;
+        launch_scale(one, rhat, rr, n, s);
+        launch_axpby(mone, w, one, rr, n, s);
+        launch_axpby(one, tmp, one, rr, n, s);
+        rcur = rr;
+        beta = norm2(P, rr);
+        if (beta <= tol) break;
+    }
+    return its;
+}
+
+static void apply_A64(mxp_problem* P, double shift, const cpx<double>* x, cpx<double>* y, double g,
+                      const cpx<double>* add, double eadd) {
+    StencilArgs<double> a = base_args<double>(P, shift);
+    a.g = {g, 0.0};
+    a.b1 = x;
+    a.b2 = add;
+    a.e2 = {eadd, 0.0};
+    a.out = y;
+    launch_stencil(a, P->ctx->stream);
+}
+
+static void check_opts(const mxp_solve_opts* o) {
+    if (!o) fail(MXP_ERR_INVALID_ARG, "options are NULL");
+    if (!(o->t > 0) || !std::isfinite(o->t)) fail(MXP_ERR_INVALID_ARG, "t must be positive");
+    if (!(o->shift >= 0) || !std::isfinite(o->shift)) fail(MXP_ERR_INVALID_ARG, "shift must be >= 0");
+    if (!(o->fprtol > 0) || o->fprtol > 1) fail(MXP_ERR_INVALID_ARG, "fprtol must be in (0, 1]");
+    if (!(o->rtol > 0) || o->rtol >= 1) fail(MXP_ERR_INVALID_ARG, "rtol must be in (0, 1)");
+    if (o->outer_restart < 1 || o->outer_restart > 200) fail(MXP_ERR_INVALID_ARG, "outer_restart in 1..200");
+    if (o->inner_restart < 1 || o->inner_restart > 200) fail(MXP_ERR_INVALID_ARG, "inner_restart in 1..200");
+    if (o->max_outer < 1 || o->max_inner < 1) fail(MXP_ERR_INVALID_ARG, "iteration limits must be >= 1");
+    if (o->precision != MXP_PREC_FP64 && o->precision != MXP_PREC_MIXED)
+        fail(MXP_ERR_INVALID_ARG, "unknown precision");
+    if (o->cheb_S < 0 || o->cheb_m < 0) fail(MXP_ERR_INVALID_ARG, "cheb_S, cheb_m must be >= 0");
+}
+
+static mxp_status solve(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
+                        mxp_solve_stats* st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = npts(P);
+    hipStream_t s = P->ctx->stream;
+    const int m = o.outer_restart;
+    P->outerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
+    P->outerZ.ensure(size_t(m) * n * sizeof(cpx<double>));
+    P->outerR.ensure(size_t(n) * sizeof(cpx<double>));
+    cpx<double>* V = P->outerV.as<cpx<double>>();
+    cpx<double>* Z = P->outerZ.as<cpx<double>>();
+    cpx<double>* r = P->outerR.as<cpx<double>>();
+    Counters cnt;
+    std::vector<int> inner;
+    const double bnorm = norm2(P, f);
+    // r = -f - A u
+    apply_A64(P, 0.0, u, r, -1.0, f, -1.0);
+    double beta = norm2(P, r);
+    int its = 0, cycles = 0;
+    double relres = bnorm > 0 ? beta / bnorm : 0.0;
+    Givens gv(m);
+    std::vector<cd> h;
+    if (bnorm == 0.0) {
+        launch_zero<double>(u, n, s);
+        relres = 0.0;
+    }
+    while (bnorm > 0.0 && beta > o.rtol * bnorm) {
+        ++cycles;
+        launch_scale({1.0 / beta, 0.0}, r, V, n, s);
+        gv.reset(beta);
+        int k = 0;
+        bool est_ok = false;
+        for (int j = 0; j < m; ++j) {
+            cpx<double>* vj = V + size_t(j) * n;
+            cpx<double>* zj = Z + size_t(j) * n;
+            cpx<double>* vn = V + size_t(j + 1) * n;
+            inner.push_back(precond(P, o, vj, zj, cnt));
+            apply_A64(P, 0.0, zj, vn, 1.0, nullptr, 0.0);
+            const double hn = cgs2(P, V, n, j + 1, vn, h);
+            ++its;
+            const double res = gv.add_column(j, h, hn);
+            if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite outer residual estimate");
+            const bool breakdown = hn <= 1e-14 * beta;
+            if (!breakdown) launch_scale({1.0 / hn, 0.0}, vn, vn, n, s);
+            k = j + 1;
+            if (res <= o.rtol * bnorm || breakdown) {
+                est_ok = true;
+                break;
+            }
+            if (its >= o.max_outer) break;
+        }
+        const std::vector<cd> y = gv.solve(k);
+        upload_coeffs(P, y);
+        launch_mcombine(u, Z, n, k, small_buffers(P).y, n, s);
+        apply_A64(P, 0.0, u, r, -1.0, f, -1.0);
+        beta = norm2(P, r);
+        relres = beta / bnorm;
+        if ((est_ok && relres <= o.rtol) || its >= o.max_outer) break;
+        if (relres <= o.rtol) break;
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->outer_its = its;
+        int tot = 0;
+        for (int v : inner) tot += v;
+        st->inner_its_total = tot;
+        if (!inner.empty()) {
+            const double mean = double(tot) / inner.size();
+            double var = 0;
+            for (int v : inner) var += (v - mean) * (v - mean);
+            st->inner_mean = mean;
+            st->inner_std = std::sqrt(var / inner.size());
+        }
+        st->stencil_steps = cnt.steps;
+        st->fn_actions = cnt.actions;
+        st->true_relres = relres;
+        st->restarts = std::max(0, cycles - 1);
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return relres <= o.rtol ? MXP_OK : MXP_NOT_CONVERGED;
+}
+
+template <class F>
+static mxp_status guard(F&& fn) {
+    try {
+        g_last_error.clear();
+        return fn();
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return MXP_ERR_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return MXP_ERR_HIP;
+    }
+}
+
+static void use_device(const mxp_context* ctx) { HIP_CHECK(hipSetDevice(ctx->device)); }
+
+static void check_problem(const mxp_problem* P) {
+    if (!P) fail(MXP_ERR_INVALID_ARG, "problem is NULL");
+    use_device(P->ctx);
+}
+
+}  // namespace mxp
+
+using namespace mxp;
+
+extern "C" {
+
+const char* mxp_last_error(void) { return g_last_error.c_str(); }
+
+const char* mxp_version(void) { return "matexpre-mi355x 0.1.0 (gfx950)"; }
+
+mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out) {
+    return guard([&]() {
+        if (!out) fail(MXP_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+            (void)hipGetLastError();
+            fail(MXP_ERR_INVALID_ARG, "no HIP device available");
+        }
+        if (device < 0 || device >= count) fail(MXP_ERR_INVALID_ARG, "no such device");
+        HIP_CHECK(hipSetDevice(device));
+        auto* c = new mxp_context{device, static_cast<hipStream_t>(hip_stream)};
+        *out = c;
+        return MXP_OK;
+    });
+}
+
+void mxp_context_destroy(mxp_context* ctx) { delete ctx; }
+
+mxp_status mxp_problem_create(mxp_context* ctx, const mxp_grid_desc* desc, mxp_problem** out) {
+    return guard([&]() {
+        if (!ctx || !out) fail(MXP_ERR_INVALID_ARG, "context or out is NULL");
+        *out = nullptr;
+        GridInfo g = validate_grid(desc);
+        use_device(ctx);
+        auto P = std::make_unique<mxp_problem>();
+        P->ctx = ctx;
+        const int64_t n = g.npts();
+        if (!g.homogeneous) {
+            // Copy c to the host (it may live on either side) for validation
+            // and its range, and build D = 1/c^2 on the device.
+            const size_t esz = desc->c_dtype == MXP_F32 ? 4 : 8;
+            std::vector<unsigned char> hostc(size_t(n) * esz);
+            hipPointerAttribute_t attr;
+            bool on_device = false;
+            if (hipPointerGetAttributes(&attr, desc->c) == hipSuccess)
+                on_device = (attr.type == hipMemoryTypeDevice);
+            else
+                (void)hipGetLastError();
+            if (on_device)
+                HIP_CHECK(hipMemcpy(hostc.data(), desc->c, hostc.size(), hipMemcpyDeviceToHost));
+            else
+                std::memcpy(hostc.data(), desc->c, hostc.size());
+            speed_range_host(hostc.data(), desc->c_dtype, n, &g.dmin, &g.dmax);
+            DevMem cdev;
+            cdev.ensure(hostc.size());
+            HIP_CHECK(hipMemcpy(cdev.p, hostc.data(), hostc.size(), hipMemcpyHostToDevice));
+            P->D64.ensure(size_t(n) * 8);
+            P->D32.ensure(size_t(n) * 4);
+            launch_inv_c2(cdev.p, desc->c_dtype == MXP_F32, P->D64.as<double>(), P->D32.as<float>(), n,
+                          ctx->stream);
+            HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        }
+        P->g = g;
+        upload_tables<double>(P.get(), P->tables64, P->t64);
+        upload_tables<float>(P.get(), P->tables32, P->t32);
+        *out = P.release();
+        return MXP_OK;
+    });
+}
+
+void mxp_problem_destroy(mxp_problem* prob) {
+    if (!prob) return;
+    (void)hipSetDevice(prob->ctx->device);
+    (void)hipStreamSynchronize(prob->ctx->stream);
+    delete prob;
+}
+
+int64_t mxp_problem_size(const mxp_problem* prob) { return prob ? prob->g.npts() : 0; }
+
+mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out) {
+    return guard([&]() {
+        if (!out) fail(MXP_ERR_INVALID_ARG, "out is NULL");
+        GridInfo g = validate_grid(desc);
+        std::memset(out, 0, sizeof(*out));
+        const double freq = g.omega / (2.0 * M_PI);
+        out->t = 40.0 * g.h * g.h;
+        out->shift = 1.0 / freq;
+        out->fprtol = 0.08;
+        out->rtol = 1e-6;
+        out->outer_restart = 30;
+        out->inner_restart = 30;
+        out->max_outer = 500;
+        out->max_inner = 300;
+        out->precision = MXP_PREC_FP64;
+        return MXP_OK;
+    });
+}
+
+mxp_status mxp_design_schedule(const mxp_grid_desc* desc, double t, double shift, mxp_precision precision,
+                               mxp_schedule* out) {
+    return guard([&]() {
+        if (!out) fail(MXP_ERR_INVALID_ARG, "out is NULL");
+        if (precision != MXP_PREC_FP64 && precision != MXP_PREC_MIXED)
+            fail(MXP_ERR_INVALID_ARG, "unknown precision");
+        GridInfo g = validate_grid(desc);
+        if (!g.homogeneous)
+            speed_range_host(desc->c, desc->c_dtype, g.npts(), &g.dmin, &g.dmax);
+        design_schedule(g, t, shift, precision, out);
+        return MXP_OK;
+    });
+}
+
+mxp_status mxp_apply_A(mxp_problem* prob, double shift, mxp_dtype dtype, const void* x, void* y) {
+    return guard([&]() {
+        check_problem(prob);
+        if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
+        if (!(shift >= 0) || !std::isfinite(shift)) fail(MXP_ERR_INVALID_ARG, "shift must be >= 0");
+        if (dtype == MXP_C128) {
+            apply_A64(prob, shift, static_cast<const cpx<double>*>(x), static_cast<cpx<double>*>(y), 1.0,
+                      nullptr, 0.0);
+        } else if (dtype == MXP_C64) {
+            StencilArgs<float> a = base_args<float>(prob, shift);
+            a.b1 = static_cast<const cpx<float>*>(x);
+            a.out = static_cast<cpx<float>*>(y);
+            launch_stencil(a, prob->ctx->stream);
+        } else {
+            fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
+        }
+        HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
+        return MXP_OK;
+    });
+}
+
+static mxp_status apply_fn(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
+                           void* y, bool psi) {
+    return guard([&]() {
+        check_problem(prob);
+        if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
+        int64_t steps = 0;
+        if (dtype == MXP_C128) {
+            const mxp_schedule& sc = get_schedule(prob, t, shift, MXP_PREC_FP64, 0, 0);
+            action<double>(prob, sc, t, shift, psi, static_cast<const cpx<double>*>(x),
+                           static_cast<cpx<double>*>(y), &steps);
+        } else if (dtype == MXP_C64) {
+            const mxp_schedule& sc = get_schedule(prob, t, shift, MXP_PREC_MIXED, 0, 0);
+            action<float>(prob, sc, t, shift, psi, static_cast<const cpx<float>*>(x),
+                          static_cast<cpx<float>*>(y), &steps);
+        } else {
+            fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
+        }
+        HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
+        return MXP_OK;
+    });
+}
+
+mxp_status mxp_apply_exp(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
+                         void* y) {
+    return apply_fn(prob, t, shift, dtype, x, y, false);
+}
+
+mxp_status mxp_apply_psi1(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
+                          void* y) {
+    return apply_fn(prob, t, shift, dtype, x, y, true);
+}
+
+mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r, void* w,
+                             int32_t* inner_its) {
+    return guard([&]() {
+        check_problem(prob);
+        check_opts(opts);
+        if (!r || !w || r == w) fail(MXP_ERR_INVALID_ARG, "r and w must be distinct non-NULL pointers");
+        Counters cnt;
+        const int its = precond(prob, *opts, static_cast<const cpx<double>*>(r), static_cast<cpx<double>*>(w),
+                                cnt);
+        HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
+        if (inner_its) *inner_its = its;
+        return MXP_OK;
+    });
+}
+
+mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
+                     mxp_solve_stats* stats) {
+    return guard([&]() {
+        check_problem(prob);
+        check_opts(opts);
+        if (!f || !u || f == u) fail(MXP_ERR_INVALID_ARG, "f and u must be distinct non-NULL pointers");
+        return solve(prob, *opts, static_cast<const cpx<double>*>(f), static_cast<cpx<double>*>(u), stats);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations of the MatExPre library (not part of the C ABI).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/matexpre.h"
+
+namespace mxp {
+
+using cd = std::complex<double>;
+
+// Error carried from the depths of the library to the ABI boundary, where it
+// becomes an mxp_status plus a thread-local message.
+struct Error : std::runtime_error {
+    mxp_status status;
+    Error(mxp_status s, const std::string& msg) : std::runtime_error(msg), status(s) {}
+};
+
+[[noreturn]] inline void fail(mxp_status s, const std::string& msg) { throw Error(s, msg); }
+
+// Absorbing-layer stretch along one axis (Section 3.3, eq. pml-1d-s): the
+// imaginary part sigma(x) of s(x) = 1 + i sigma(x).  Nodes x_i = i h, the low
+// face has `lo` layer cells (inner edge at lo*h, delta = lo*h), the high face
+// `hi` cells (inner edge at (n-1-hi)*h, delta = hi*h).
+struct AxisLayer {
+    int64_t n;
+    int32_t lo, hi;
+    double h, omega, C;
+    int32_t power;
+    double sigma(double x) const;
+};
+
+// Per-axis three-point coefficients of (1/s) d/dx((1/s) du/dx):
+//   (L u)_i = alpha_i u_{i-1} + beta_i u_{i+1} + gamma_i u_i,
+//   alpha_i = 1/(s_i s_{i-1/2} h^2), beta_i = 1/(s_i s_{i+1/2} h^2),
+//   gamma_i = -(alpha_i + beta_i).
+struct AxisTables {
+    std::vector<cd> alpha, beta, gamma;
+};
+AxisTables build_axis_tables(const AxisLayer& ax);
+
+// Validated copy of a grid description plus derived host-side facts.
+struct GridInfo {
+    int dim;
+    int64_t n[3];
+    double h, omega, pml_C;
+    int32_t pml_power;
+    int32_t layer[3][2];
+    bool homogeneous;
+    double c_const;
+    double dmin, dmax;  // range of D = 1/c^2
+    int64_t npts() const { return n[0] * n[1] * n[2]; }
+    AxisLayer axis(int d) const {
+        return AxisLayer{n[d], layer[d][0], layer[d][1], h, omega, pml_C, pml_power};
+    }
+};
+
+// Checks the description; fills everything except dmin/dmax when c is given.
+GridInfo validate_grid(const mxp_grid_desc* desc);
+
+// Range of D = 1/c^2 over a host array of `count` speeds; fails on c <= 0 or
+// non-finite values.
+void speed_range_host(const void* c, mxp_dtype dt, int64_t count, double* dmin, double* dmax);
+
+// Field-of-values box of A_s (re_min, re_max, im_min, im_max).
+void fov_box(const GridInfo& g, double shift, double box[4]);
+
+// Substepped Chebyshev schedule for exp(i t A_s) and psi_1(i t A_s).
+// forceS / forcem > 0 fix the substep count / series degree (0 = designed).
+void design_schedule(const GridInfo& g, double t, double shift, mxp_precision prec,
+                     mxp_schedule* out, int forceS = 0, int forcem = 0);
+
+// Scalar psi_1(z) = (e^z - 1)/z with the power series near 0.
+cd psi1_scalar(cd z);
+
+}  // namespace mxp

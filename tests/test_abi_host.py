@@ -1,0 +1,191 @@
+"""Host-side checks of the C-ABI library (no device work): every declared
+symbol is exported, argument validation, defaults, and the Chebyshev schedule
+designer against the oracle's dense matrix functions on tiny grids."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.special import jv
+
+import workloads as wl
+from oracle import matfun, operator as op
+
+mxp = pytest.importorskip("paper_2506_03617_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "matexpre.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mxp_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_symbols()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(mxp.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(mxp.ABI_SYMBOLS)
+
+
+def test_version_string():
+    assert "gfx950" in mxp.mxp_version()
+
+
+def _desc(**kw):
+    prob = wl.small_problem((20, 18), layer=4)
+    d = mxp.grid_desc(prob)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("h", 0.0), ("omega", -1.0), ("h", float("nan")),
+                                         ("pml_power", 0), ("c_const", 0.0), ("pml_C", -1.0)])
+def test_invalid_descriptions_rejected(field, value):
+    d = _desc(**{field: value})
+    with pytest.raises(mxp.MxpError) as e:
+        mxp.mxp_design_schedule(d, 1e-3, 0.1, mxp.MXP_PREC_FP64)
+    assert e.value.status == mxp.MXP_ERR_INVALID_ARG
+
+
+def test_layer_and_size_limits():
+    d = _desc()
+    d.layer[0][1] = 10  # n0 = 20 -> layer must be < 10
+    with pytest.raises(mxp.MxpError):
+        mxp.mxp_design_schedule(d, 1e-3, 0.1, 0)
+    d = _desc()
+    d.n[1] = 2
+    with pytest.raises(mxp.MxpError):
+        mxp.mxp_design_schedule(d, 1e-3, 0.1, 0)
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")])
+def test_bad_wave_speed_rejected(bad):
+    prob = wl.small_problem((12, 10), layer=2)
+    c = np.ones(prob.shape)
+    c[3, 4] = bad
+    d = mxp.grid_desc(prob, c_host=c)
+    with pytest.raises(mxp.MxpError) as e:
+        mxp.mxp_design_schedule(d, 1e-3, 0.1, 0)
+    assert e.value.status == mxp.MXP_ERR_INVALID_ARG
+
+
+def test_bad_time_and_shift_rejected():
+    d = _desc()
+    for t, s in ((0.0, 0.1), (-1.0, 0.1), (1e-3, -0.1)):
+        with pytest.raises(mxp.MxpError):
+            mxp.mxp_design_schedule(d, t, s, 0)
+
+
+def test_default_options_follow_the_paper_rules():
+    prob = wl.config1()
+    o = mxp.mxp_solve_opts_default(mxp.grid_desc(prob))
+    freq = prob.omega / (2 * math.pi)
+    assert o.t == pytest.approx(0.4 / freq**2, rel=1e-12)   # t = 0.4/freq^2 at ppw 10
+    assert o.shift == pytest.approx(1 / freq)
+    assert o.fprtol == 0.08 and o.rtol == 1e-6
+    assert o.outer_restart == 30 and o.inner_restart == 30
+
+
+def test_context_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    st = mxp.lib.mxp_context_create(0, None, ctypes.byref(h))
+    assert st == mxp.MXP_ERR_INVALID_ARG
+    assert "device" in mxp.lib.mxp_last_error().decode()
+
+
+def _support(A, th):
+    M = np.exp(-1j * th) * A
+    return np.linalg.eigvalsh((M + M.conj().T) / 2)[-1]
+
+
+@pytest.mark.parametrize("dim,inh", [(2, False), (2, True), (3, False)])
+def test_fov_box_contains_and_touches_the_field_of_values(dim, inh):
+    n = (14, 12, 10)[:dim]
+    prob = wl.small_problem(n, layer=3, ppw=8, inhomogeneous=inh, seed=2)
+    s = prob.default_shift()
+    sch = mxp.mxp_design_schedule(mxp.grid_desc(prob), prob.default_t(), s, 0)
+    A = op.helmholtz(prob, s).toarray()
+    re_max, re_min = _support(A, 0.0), -_support(A, math.pi)
+    im_max, im_min = _support(A, math.pi / 2), -_support(A, -math.pi / 2)
+    box = list(sch.box)
+    scale = np.abs(A).max()
+    assert box[0] <= re_min + 1e-9 * scale and box[1] >= re_max - 1e-9 * scale
+    assert box[2] <= im_min + 1e-9 * scale and box[3] >= im_max - 1e-9 * scale
+    if not inh:  # Kronecker sum plus a constant diagonal: the box is tight
+        assert box[0] == pytest.approx(re_min, abs=1e-8 * scale)
+        assert box[1] == pytest.approx(re_max, abs=1e-8 * scale)
+        assert box[2] == pytest.approx(im_min, abs=1e-8 * scale)
+        assert box[3] == pytest.approx(im_max, abs=1e-8 * scale)
+
+
+def test_exp_coefficients_match_bessel_closed_form():
+    prob = wl.config1()
+    t, s = prob.default_t(), prob.default_shift()
+    sch = mxp.mxp_design_schedule(mxp.grid_desc(prob), t, s, 0)
+    tau = t / sch.S
+    c0 = sch.centre_re + 1j * sch.centre_im
+    k = np.arange(sch.m + 1)
+    ref = np.exp(1j * tau * c0) * np.where(k == 0, 1, 2) * (1j) ** k * jv(k, tau * sch.half_width)
+    got = sch.coefficients()
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_psi1_series_matches_scalar_psi1_on_the_segment():
+    prob = wl.config1()
+    t, s = prob.default_t(), prob.default_shift()
+    sch = mxp.mxp_design_schedule(mxp.grid_desc(prob), t, s, 0)
+    tau = t / sch.S
+    c0 = sch.centre_re + 1j * sch.centre_im
+    q = sch.coefficients_psi()
+    xs = np.linspace(-1, 1, 41)
+    T = np.cos(np.outer(np.arange(q.size), np.arccos(xs)))
+    got = q @ T
+    ref = np.array([tau * matfun.psi_scalar(1, 1j * tau * (c0 + sch.half_width * x)) for x in xs])
+    assert np.abs(got - ref).max() <= 1e-12 * tau
+
+
+def _cheb_matrix(coef, A, c0, hw):
+    N = A.shape[0]
+    Ah = (A - c0 * np.eye(N)) / hw
+    T0, T1 = np.eye(N), Ah.copy()
+    P = coef[0] * T0 + coef[1] * T1
+    for k in range(2, coef.size):
+        T0, T1 = T1, 2 * Ah @ T1 - T0
+        P = P + coef[k] * T1
+    return P
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-5)])
+def test_designed_schedule_reproduces_dense_exponential(prec, tol):
+    # (p(A_s))^S against the oracle's dense exp(i t A_s) on a tiny grid, and the
+    # psi_1 composition sum_k E^k q(A_s) / t against its dense psi_1.
+    prob = wl.small_problem((12, 11), layer=3, ppw=10, inhomogeneous=True, seed=4)
+    t, s = prob.default_t(), prob.default_shift()
+    sch = mxp.mxp_design_schedule(mxp.grid_desc(prob), t, s, prec)
+    A = op.helmholtz(prob, s).toarray()
+    c0 = sch.centre_re + 1j * sch.centre_im
+    P = _cheb_matrix(sch.coefficients(), A, c0, sch.half_width)
+    E = np.linalg.matrix_power(P, sch.S)
+    Eref = matfun.exp_dense(op.helmholtz(prob, s), t)
+    assert np.linalg.norm(E - Eref, 2) <= max(sch.trunc_bound, 1e-13) * 2 + 1e-12
+    assert np.linalg.norm(E - Eref, 2) <= tol
+    Q = _cheb_matrix(sch.coefficients_psi(), A, c0, sch.half_width)
+    acc = np.zeros_like(Q)
+    Pk = np.eye(A.shape[0])
+    for _ in range(sch.S):
+        acc = acc + Pk @ Q
+        Pk = P @ Pk
+    psi = acc / t
+    ref = matfun.phi1_dense(op.helmholtz(prob, s), t)
+    assert np.linalg.norm(psi - ref, 2) <= tol * max(1.0, np.linalg.norm(ref, 2))

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Sizes are small enough for the oracle yet span several 64x4 workgroup tiles
+with ragged edges in every axis.  Bars: FP64 paths <= 1e-10 relative (actions
+<= 1e-11), complex-float forms <= 1e-5, iteration counts within +-1."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import krylov, matfun, operator as op
+
+from gpu_util import announce, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_03617_amd as mxp  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mxp.Context(0)
+    yield c
+    c.close()
+
+
+CASES = {
+    "2d-homog": dict(n=(67, 45), layer=8, inh=False),
+    "2d-inh": dict(n=(67, 45), layer=8, inh=True),
+    "3d-homog": dict(n=(33, 29, 21), layer=4, inh=False),
+    "3d-inh": dict(n=(33, 29, 21), layer=4, inh=True),
+}
+
+
+def make(name, ppw=10.0):
+    c = CASES[name]
+    return wl.small_problem(c["n"], layer=c["layer"], ppw=ppw, inhomogeneous=c["inh"], seed=7, name=name)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_apply_A(ctx, name, dt):
+    prob = make(name)
+    announce("apply_A", name, dt, prob.n)
+    P = mxp.Problem(ctx, prob)
+    s = prob.default_shift()
+    x = wl.random_vector(prob.npts, 1)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    xd = to_dev(x, tdt)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_A(P, s, xd, yd)
+    torch.cuda.synchronize()
+    xr = to_host(xd)  # the rounded input actually used
+    As = op.helmholtz(prob, s)
+    ref = As @ xr
+    bound = abs(As) @ np.abs(xr)
+    eps = 2.0**-53 if dt == "c128" else 2.0**-24
+    assert np.linalg.norm(to_host(yd) - ref) <= 16 * eps * np.linalg.norm(bound)
+
+
+@pytest.mark.parametrize("name", ["2d-homog", "2d-inh", "3d-inh"])
+def test_apply_A_smooth_input_cancellation(ctx, name):
+    # smooth x: the Laplacian cancels, so the normwise |A||x| bound is the right one
+    prob = make(name)
+    announce("apply_A smooth", name)
+    P = mxp.Problem(ctx, prob)
+    axes = [np.sin(np.pi * (np.arange(m) + 1) / (m + 1)) for m in prob.n]
+    x = axes[0]
+    for a in axes[1:]:
+        x = np.multiply.outer(a, x)
+    x = (x * (1 + 0.5j)).ravel()
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_A(P, 0.0, xd, yd)
+    As = op.helmholtz(prob, 0.0)
+    assert np.linalg.norm(to_host(yd) - As @ x) <= 16 * 2.0**-53 * np.linalg.norm(abs(As) @ np.abs(x))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dt,tol", [("c128", 1e-11), ("c64", 1e-5)])
+def test_apply_exp(ctx, name, dt, tol):
+    prob = make(name)
+    announce("apply_exp", name, dt)
+    P = mxp.Problem(ctx, prob)
+    t, s = prob.default_t(), prob.default_shift()
+    x = wl.random_vector(prob.npts, 2)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    xd = to_dev(x, tdt)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_exp(P, t, s, xd, yd)
+    ref = matfun.exp_action(op.helmholtz(prob, s), t, to_host(xd))
+    assert rel(to_host(yd), ref) <= tol
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dt,tol", [("c128", 1e-11), ("c64", 1e-5)])
+def test_apply_psi1(ctx, name, dt, tol):
+    prob = make(name)
+    announce("apply_psi1", name, dt)
+    P = mxp.Problem(ctx, prob)
+    t, s = prob.default_t(), prob.default_shift()
+    x = wl.random_vector(prob.npts, 3)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    xd = to_dev(x, tdt)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_psi1(P, t, s, xd, yd)
+    ref = matfun.phi1_action(op.helmholtz(prob, s), t, to_host(xd))
+    assert rel(to_host(yd), ref) <= tol
+
+
+def test_apply_exp_delta_source_and_unshifted(ctx):
+    prob = make("2d-homog")
+    announce("apply_exp delta s=0")
+    P = mxp.Problem(ctx, prob)
+    t = prob.default_t()
+    f = wl.delta_source(prob, (33, 22)).ravel()
+    xd = to_dev(f)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_exp(P, t, 0.0, xd, yd)
+    assert rel(to_host(yd), matfun.exp_action(op.helmholtz(prob, 0.0), t, f)) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["2d-homog", "2d-inh", "3d-inh"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_precond(ctx, name, prec):
+    prob = make(name)
+    announce("apply_precond", name, prec)
+    P = mxp.Problem(ctx, prob)
+    o = P.default_opts()
+    o.precision = prec
+    r = wl.random_vector(prob.npts, 4)
+    rd = to_dev(r)
+    wd = torch.empty_like(rd)
+    its = mxp.mxp_apply_precond(P, o, rd, wd)
+    ref = krylov.precond_apply(op.helmholtz(prob, o.shift), o.t, r, o.fprtol)
+    assert abs(its - ref.inner_iterations) <= 1
+    if its == ref.inner_iterations:
+        assert rel(to_host(wd), ref.w) <= (1e-10 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("name", ["2d-homog", "2d-inh", "3d-homog", "3d-inh"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_counts_and_tight_solution(ctx, name, prec):
+    prob = make(name)
+    announce("solve", name, prec)
+    P = mxp.Problem(ctx, prob)
+    centre = tuple(m // 2 for m in prob.n)
+    f = wl.delta_source(prob, centre).ravel()
+    o = P.default_opts()
+    o.precision = prec
+    fd = to_dev(f)
+    ud = torch.zeros_like(fd)
+    st = mxp.mxp_solve(P, o, fd, ud)
+    ref = krylov.matexpre_solve(prob, f, o.t, o.shift, o.fprtol, o.rtol)
+    assert st["status"] == mxp.MXP_OK
+    assert st["true_relres"] <= o.rtol
+    assert abs(st["outer_its"] - ref.outer_iterations) <= 1
+    assert abs(st["inner_mean"] - ref.inner_mean) <= 1.0
+    # the iterate itself is a parity quantity once both are solved tightly
+    o.rtol = 1e-12
+    ud.zero_()
+    st = mxp.mxp_solve(P, o, fd, ud)
+    tight = krylov.direct_solve(prob, f)
+    assert st["true_relres"] <= 1e-12
+    assert rel(to_host(ud), tight) <= (1e-10 if prec == 0 else 1e-5)
+
+
+def test_solve_edge_cases(ctx):
+    prob = wl.small_problem((3, 3), layer=0)
+    announce("edge 3x3")
+    P = mxp.Problem(ctx, prob)
+    o = P.default_opts()
+    f = np.zeros(prob.npts, complex)
+    fd = to_dev(f)
+    ud = torch.ones_like(fd)
+    st = mxp.mxp_solve(P, o, fd, ud)
+    assert st["status"] == mxp.MXP_OK and np.all(to_host(ud) == 0)
+    f[4] = 1.0
+    fd = to_dev(f)
+    ud = torch.zeros_like(fd)
+    st = mxp.mxp_solve(P, o, fd, ud)
+    assert st["status"] == mxp.MXP_OK
+    assert rel(to_host(ud), krylov.direct_solve(prob, f)) <= 1e-6 * 1e3
+    # iteration limit -> NOT_CONVERGED with the statistics filled in
+    prob = make("2d-homog")
+    P = mxp.Problem(ctx, prob)
+    o = P.default_opts()
+    o.max_outer = 1
+    fd = to_dev(wl.delta_source(prob, (33, 22)).ravel())
+    ud = torch.zeros_like(fd)
+    st = mxp.mxp_solve(P, o, fd, ud)
+    assert st["status"] == mxp.MXP_NOT_CONVERGED and st["outer_its"] == 1
+    assert 0 < st["true_relres"] < 1
+    # a nearly degenerate preconditioner (fprtol just below 1: one inner step) still converges
+    o = P.default_opts()
+    o.fprtol = 0.99
+    ud.zero_()
+    st = mxp.mxp_solve(P, o, fd, ud)
+    assert st["status"] == mxp.MXP_OK and st["true_relres"] <= 1e-6
+
+
+def test_argument_errors(ctx):
+    prob = make("2d-homog")
+    P = mxp.Problem(ctx, prob)
+    xd = to_dev(np.zeros(prob.npts, complex))
+    with pytest.raises(mxp.MxpError) as e:
+        mxp.mxp_apply_A(P, 0.0, xd, xd)
+    assert e.value.status == mxp.MXP_ERR_INVALID_ARG
+    o = P.default_opts()
+    o.fprtol = 0.0
+    with pytest.raises(mxp.MxpError):
+        mxp.mxp_solve(P, o, xd, torch.zeros_like(xd))
+    with pytest.raises(mxp.MxpError):
+        mxp.mxp_apply_exp(P, -1.0, 0.1, xd, torch.zeros_like(xd))
