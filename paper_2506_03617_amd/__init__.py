@@ -8,10 +8,10 @@ module fails loudly if it is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
-import dataclasses
-import math
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -222,6 +222,20 @@ def _dtype_of(tensor) -> int:
     raise TypeError("vectors must be torch.complex64 or torch.complex128")
 
 
+# Live handles, closed at interpreter exit before the HIP runtime goes away
+# (problems first, then contexts).
+_LIVE_PROBLEMS: "weakref.WeakSet" = weakref.WeakSet()
+_LIVE_CONTEXTS: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_LIVE_PROBLEMS):
+        obj.close()
+    for obj in list(_LIVE_CONTEXTS):
+        obj.close()
+
+
 class Context:
     """mxp_context bound to a CUDA/HIP device and (by default) torch's current stream."""
 
@@ -234,6 +248,7 @@ class Context:
         _check(lib.mxp_context_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(handle)))
         self.handle = handle
         self.device = device
+        _LIVE_CONTEXTS.add(self)
 
     def close(self):
         if self.handle:
@@ -257,6 +272,7 @@ class Problem:
         handle = ctypes.c_void_p()
         _check(lib.mxp_problem_create(ctx.handle, ctypes.byref(self.desc), ctypes.byref(handle)))
         self.handle = handle
+        _LIVE_PROBLEMS.add(self)
 
     @property
     def size(self) -> int:

@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -30,6 +32,7 @@
 struct mxp_context {
     int device;
     hipStream_t stream;
+    int verbose;  // MXP_VERBOSE=1: one line per outer iteration on stderr
 };
 
 namespace mxp {
@@ -77,19 +80,31 @@ struct DevTables {
     cpx<R>* gamma[3] = {nullptr, nullptr, nullptr};
 };
 
+// Per-axis diagonal tables gamma_d + (kD * Dref - centre)/dim for one
+// (shift, centre) pair, in both precisions.
+struct DiagTables {
+    DevMem mem64, mem32;
+    cpx<double>* g64[3] = {nullptr, nullptr, nullptr};
+    cpx<float>* g32[3] = {nullptr, nullptr, nullptr};
+};
+
 struct Sched {
     mxp_schedule s;
+    DiagTables diag;
 };
 
 }  // namespace mxp
 
 struct mxp_problem {
-    mxp_context* ctx;
+    mxp_context ctx_copy;  // device, stream, verbosity: the problem outlives nothing it points to
+    mxp_context* ctx;      // == &ctx_copy
     mxp::GridInfo g;
     mxp::DevMem tables64, tables32, D64, D32;
     mxp::DevTables<double> t64;
     mxp::DevTables<float> t32;
     std::map<std::tuple<double, double, int, int, int>, std::unique_ptr<mxp::Sched>> scheds;
+    std::map<double, std::unique_ptr<mxp::DiagTables>> plain_diag;  // centre 0, keyed by shift
+    double Dref = 0.0;  // reference value of D folded into the diagonal tables
     // workspaces
     mxp::DevMem act64[4], act32[6];
     mxp::DevMem innerV, innerRh, innerTmp, innerRr;
@@ -139,20 +154,66 @@ static void upload_tables(mxp_problem* P, DevMem& mem, DevTables<R>& t) {
     }
 }
 
-static const mxp_schedule& get_schedule(mxp_problem* P, double t, double shift, mxp_precision prec,
-                                        int forceS, int forcem) {
+static void build_diag(mxp_problem* P, double shift, cd centre, DiagTables& dt) {
+    const GridInfo& g = P->g;
+    const cd share = (cd(g.omega * g.omega, g.omega * g.omega * shift) * P->Dref - centre) / double(g.dim);
+    size_t total = 0;
+    for (int d = 0; d < 3; ++d) total += size_t(g.n[d]);
+    std::vector<cpx<double>> h64(total);
+    std::vector<cpx<float>> h32(total);
+    size_t off = 0, offs[3];
+    for (int d = 0; d < 3; ++d) {
+        offs[d] = off;
+        if (d < g.dim) {
+            const AxisTables at = build_axis_tables(g.axis(d));
+            for (int64_t i = 0; i < g.n[d]; ++i) {
+                const cd v = at.gamma[i] + share;
+                h64[off + i] = {v.real(), v.imag()};
+                h32[off + i] = {float(v.real()), float(v.imag())};
+            }
+        } else {
+            for (int64_t i = 0; i < g.n[d]; ++i) {
+                h64[off + i] = {0.0, 0.0};
+                h32[off + i] = {0.0f, 0.0f};
+            }
+        }
+        off += g.n[d];
+    }
+    dt.mem64.ensure(total * sizeof(cpx<double>));
+    dt.mem32.ensure(total * sizeof(cpx<float>));
+    HIP_CHECK(hipMemcpy(dt.mem64.p, h64.data(), total * sizeof(cpx<double>), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(dt.mem32.p, h32.data(), total * sizeof(cpx<float>), hipMemcpyHostToDevice));
+    for (int d = 0; d < 3; ++d) {
+        dt.g64[d] = dt.mem64.as<cpx<double>>() + offs[d];
+        dt.g32[d] = dt.mem32.as<cpx<float>>() + offs[d];
+    }
+}
+
+static const DiagTables& plain_diag(mxp_problem* P, double shift) {
+    auto it = P->plain_diag.find(shift);
+    if (it != P->plain_diag.end()) return *it->second;
+    auto dt = std::make_unique<DiagTables>();
+    build_diag(P, shift, cd(0.0, 0.0), *dt);
+    const DiagTables& ref = *dt;
+    P->plain_diag.emplace(shift, std::move(dt));
+    return ref;
+}
+
+static const Sched& get_sched(mxp_problem* P, double t, double shift, mxp_precision prec,
+                              int forceS, int forcem) {
     auto key = std::make_tuple(t, shift, int(prec), forceS, forcem);
     auto it = P->scheds.find(key);
-    if (it != P->scheds.end()) return it->second->s;
+    if (it != P->scheds.end()) return *it->second;
     auto sc = std::make_unique<Sched>();
     design_schedule(P->g, t, shift, prec, &sc->s, forceS, forcem);
-    const mxp_schedule& ref = sc->s;
+    build_diag(P, shift, cd(sc->s.centre_re, sc->s.centre_im), sc->diag);
+    const Sched& ref = *sc;
     P->scheds.emplace(key, std::move(sc));
     return ref;
 }
 
 template <typename R>
-static StencilArgs<R> base_args(mxp_problem* P, double shift) {
+static StencilArgs<R> base_args(mxp_problem* P, double shift, const DiagTables& diag) {
     StencilArgs<R> a{};
     const GridInfo& g = P->g;
     a.dim = g.dim;
@@ -164,18 +225,18 @@ static StencilArgs<R> base_args(mxp_problem* P, double shift) {
     for (int d = 0; d < 3; ++d) {
         a.alpha[d] = t->alpha[d];
         a.beta[d] = t->beta[d];
-        a.gamma[d] = t->gamma[d];
+        if constexpr (sizeof(R) == 8) a.gamma[d] = diag.g64[d]; else a.gamma[d] = diag.g32[d];
     }
     if (g.homogeneous) {
         a.D = nullptr;
-        a.Dconst = R(1.0 / (g.c_const * g.c_const));
+        a.Dconst = R(P->Dref);  // D - Dref is exactly zero
     } else {
         if constexpr (sizeof(R) == 8) a.D = P->D64.as<double>(); else a.D = P->D32.as<float>();
         a.Dconst = R(0);
     }
+    a.Dref = R(P->Dref);
     const double w2 = g.omega * g.omega;
     a.kD = {R(w2), R(w2 * shift)};
-    a.kc = {R(0), R(0)};
     a.g = {R(1), R(0)};
     a.cx = a.e2 = a.e3 = {R(0), R(0)};
     return a;
@@ -194,10 +255,8 @@ static void cheb_series(mxp_problem* P, const StencilArgs<R>& base, const mxp_sc
                         const double* coef, int m, const cpx<R>* x, cpx<R>* out, cpx<R>* bufA,
                         cpx<R>* bufB, cd post, const cpx<R>* add, int64_t* steps) {
     hipStream_t s = P->ctx->stream;
-    const cd c0(sc.centre_re, sc.centre_im);
     const double hw = sc.half_width;
-    StencilArgs<R> a = base;
-    a.kc = to_cpx<R>(-c0);
+    StencilArgs<R> a = base;  // the centre is already folded into the diagonal tables
     a.x = x;
     // b_{m-1} = c_{m-1} x + 2 Ahat (c_m x)
     a.b1 = x;
@@ -245,14 +304,15 @@ static DevMem* act_buffers(mxp_problem* P) {
 // y = exp(i t A_s) x (psi = false) or psi_1(i t A_s) x (psi = true), precision R.
 // x and y distinct device vectors of precision R.
 template <typename R>
-static void action(mxp_problem* P, const mxp_schedule& sc, double t, double shift, bool psi,
+static void action(mxp_problem* P, const Sched& sd, double t, double shift, bool psi,
                    const cpx<R>* x, cpx<R>* y, int64_t* steps) {
+    const mxp_schedule& sc = sd.s;
     const int64_t n = npts(P);
     DevMem* W = act_buffers<R>(P);
     for (int q = 0; q < 4; ++q) W[q].ensure(size_t(n) * sizeof(cpx<R>));
     cpx<R>* w[3] = {W[0].as<cpx<R>>(), W[1].as<cpx<R>>(), W[2].as<cpx<R>>()};
     cpx<R>* pbuf = W[3].as<cpx<R>>();
-    const StencilArgs<R> base = base_args<R>(P, shift);
+    const StencilArgs<R> base = base_args<R>(P, shift, sd.diag);
     const int S = sc.S;
     auto others = [&](const cpx<R>* cur, cpx<R>** a, cpx<R>** b) {
         int k = 0;
@@ -414,7 +474,7 @@ static void upload_coeffs(mxp_problem* P, const std::vector<cd>& y) {
 }
 
 // y = exp or psi_1 action on complex-double vectors, in the requested precision.
-static void action64(mxp_problem* P, const mxp_schedule& sc, double t, double shift, bool psi,
+static void action64(mxp_problem* P, const Sched& sc, double t, double shift, bool psi,
                      mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps) {
     if (prec == MXP_PREC_FP64) {
         action<double>(P, sc, t, shift, psi, x, y, steps);
@@ -439,7 +499,7 @@ static int precond(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* r
                    Counters& cnt) {
     const int64_t n = npts(P);
     hipStream_t s = P->ctx->stream;
-    const mxp_schedule& sc = get_schedule(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
+    const Sched& sc = get_sched(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
     const int m = o.inner_restart;
     P->innerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
     P->innerRh.ensure(size_t(n) * sizeof(cpx<double>));
@@ -509,7 +569,7 @@ static int precond(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* r
 
 static void apply_A64(mxp_problem* P, double shift, const cpx<double>* x, cpx<double>* y, double g,
                       const cpx<double>* add, double eadd) {
-    StencilArgs<double> a = base_args<double>(P, shift);
+    StencilArgs<double> a = base_args<double>(P, shift, plain_diag(P, shift));
     a.g = {g, 0.0};
     a.b1 = x;
     a.b2 = add;
@@ -573,6 +633,12 @@ static mxp_status solve(mxp_problem* P, const mxp_solve_opts& o, const cpx<doubl
             const double hn = cgs2(P, V, n, j + 1, vn, h);
             ++its;
             const double res = gv.add_column(j, h, hn);
+            if (P->ctx->verbose) {
+                const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                std::fprintf(stderr, "[mxp] outer %d: est relres %.3e, inner %d, steps %lld, %.2f s\n", its,
+                             res / bnorm, inner.back(), (long long)cnt.steps, el);
+                std::fflush(stderr);
+            }
             if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite outer residual estimate");
             const bool breakdown = hn <= 1e-14 * beta;
             if (!breakdown) launch_scale({1.0 / hn, 0.0}, vn, vn, n, s);
@@ -660,7 +726,8 @@ mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out) {
         }
         if (device < 0 || device >= count) fail(MXP_ERR_INVALID_ARG, "no such device");
         HIP_CHECK(hipSetDevice(device));
-        auto* c = new mxp_context{device, static_cast<hipStream_t>(hip_stream)};
+        const char* v = std::getenv("MXP_VERBOSE");
+        auto* c = new mxp_context{device, static_cast<hipStream_t>(hip_stream), (v && *v && *v != '0') ? 1 : 0};
         *out = c;
         return MXP_OK;
     });
@@ -675,7 +742,8 @@ mxp_status mxp_problem_create(mxp_context* ctx, const mxp_grid_desc* desc, mxp_p
         GridInfo g = validate_grid(desc);
         use_device(ctx);
         auto P = std::make_unique<mxp_problem>();
-        P->ctx = ctx;
+        P->ctx_copy = *ctx;
+        P->ctx = &P->ctx_copy;
         const int64_t n = g.npts();
         if (!g.homogeneous) {
             // Copy c to the host (it may live on either side) for validation
@@ -699,10 +767,11 @@ mxp_status mxp_problem_create(mxp_context* ctx, const mxp_grid_desc* desc, mxp_p
             P->D64.ensure(size_t(n) * 8);
             P->D32.ensure(size_t(n) * 4);
             launch_inv_c2(cdev.p, desc->c_dtype == MXP_F32, P->D64.as<double>(), P->D32.as<float>(), n,
-                          ctx->stream);
-            HIP_CHECK(hipStreamSynchronize(ctx->stream));
+                          P->ctx->stream);
+            HIP_CHECK(hipStreamSynchronize(P->ctx->stream));
         }
         P->g = g;
+        P->Dref = 0.5 * (g.dmin + g.dmax);
         upload_tables<double>(P.get(), P->tables64, P->t64);
         upload_tables<float>(P.get(), P->tables32, P->t32);
         *out = P.release();
@@ -761,7 +830,7 @@ mxp_status mxp_apply_A(mxp_problem* prob, double shift, mxp_dtype dtype, const v
             apply_A64(prob, shift, static_cast<const cpx<double>*>(x), static_cast<cpx<double>*>(y), 1.0,
                       nullptr, 0.0);
         } else if (dtype == MXP_C64) {
-            StencilArgs<float> a = base_args<float>(prob, shift);
+            StencilArgs<float> a = base_args<float>(prob, shift, plain_diag(prob, shift));
             a.b1 = static_cast<const cpx<float>*>(x);
             a.out = static_cast<cpx<float>*>(y);
             launch_stencil(a, prob->ctx->stream);
@@ -780,11 +849,11 @@ static mxp_status apply_fn(mxp_problem* prob, double t, double shift, mxp_dtype 
         if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
         int64_t steps = 0;
         if (dtype == MXP_C128) {
-            const mxp_schedule& sc = get_schedule(prob, t, shift, MXP_PREC_FP64, 0, 0);
+            const Sched& sc = get_sched(prob, t, shift, MXP_PREC_FP64, 0, 0);
             action<double>(prob, sc, t, shift, psi, static_cast<const cpx<double>*>(x),
                            static_cast<cpx<double>*>(y), &steps);
         } else if (dtype == MXP_C64) {
-            const mxp_schedule& sc = get_schedule(prob, t, shift, MXP_PREC_MIXED, 0, 0);
+            const Sched& sc = get_sched(prob, t, shift, MXP_PREC_MIXED, 0, 0);
             action<float>(prob, sc, t, shift, psi, static_cast<const cpx<float>*>(x),
                           static_cast<cpx<float>*>(y), &steps);
         } else {

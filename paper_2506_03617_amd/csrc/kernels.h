@@ -14,19 +14,23 @@ struct alignas(2 * sizeof(R)) cpx {
 
 // One fused sweep of the shifted stencil operator with affine extras:
 //
-//   out[p] = g * ( (Lap_PML v)[p] + (kD * D[p] + kc) * v[p] )
+//   out[p] = g * ( sum_d [alpha_d v[p-e_d] + beta_d v[p+e_d] + gamma_d v[p]]
+//                  + kD * (D[p] - Dref) * v[p] )
 //            + cx * x[p] + e2 * b2[p] + e3 * b3[p]
 //
-// with v = b1 (the stencil input), Lap_PML the per-axis three-point stretched
-// second difference (tables alpha/beta/gamma per axis, zero Dirichlet ghosts)
-// and D = 1/c^2 per node (or the constant Dconst when D == nullptr).  Any of
+// with v = b1 (the stencil input), per-axis three-point tables alpha/beta of
+// the stretched second difference (zero Dirichlet ghosts), D = 1/c^2 per node
+// (or the constant Dconst when D == nullptr).  The diagonal tables gamma_d
+// carry -(alpha_d + beta_d) plus an equal share of every constant diagonal
+// term (kD * Dref - centre), summed in double on the host: summing the large
+// axis terms and the shift in the working precision would cancel badly.  Any of
 // x, b2, b3 may be nullptr (term omitted).  out may alias x, b2 or b3 (each
 // point is read before it is written by the same thread) but not b1.
 //
-// Used for:  y = A_s x                         (g = 1, kD = omega^2(1+is), kc = 0)
+// Used for:  y = A_s x                         (g = 1, kD = omega^2(1+is))
 //            r = -A u - f                      (g = -1, e2 = -1, b2 = f)
 //            Clenshaw step b_k = c_k x + 2 Ahat b_{k+1} - b_{k+2},
-//            Ahat = (A_s - centre)/half_width  (g = 2/half_width, kc = -centre)
+//            Ahat = (A_s - centre)/half_width  (g = 2/half_width, centre in gamma)
 template <typename R>
 struct StencilArgs {
     int dim;
@@ -35,8 +39,8 @@ struct StencilArgs {
     const cpx<R>* beta[3];
     const cpx<R>* gamma[3];
     const R* D;
-    R Dconst;
-    cpx<R> g, kD, kc, cx, e2, e3;
+    R Dconst, Dref;
+    cpx<R> g, kD, cx, e2, e3;
     const cpx<R>* x;
     const cpx<R>* b1;
     const cpx<R>* b2;

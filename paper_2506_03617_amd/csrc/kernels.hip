@@ -48,8 +48,8 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<R> a) {
     const cpx<R> c = v[p];
     cpx<R> diag = cadd(a.gamma[0][i], a.gamma[1][j]);
     if (DIM == 3) diag = cadd(diag, a.gamma[2][k]);
-    const R Dp = a.D ? a.D[p] : a.Dconst;
-    diag = cadd(diag, cadd(cscale(Dp, a.kD), a.kc));
+    const R Dp = (a.D ? a.D[p] : a.Dconst) - a.Dref;
+    diag = cadd(diag, cscale(Dp, a.kD));
     cpx<R> s = cmul(diag, c);
     if (i > 0) s = cfma(a.alpha[0][i], v[p - 1], s);
     if (i < a.n0 - 1) s = cfma(a.beta[0][i], v[p + 1], s);
