@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-reps", type=int, default=3)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="skip the solves: run only the exp-action timing loop and a plain "
+                         "1 GiB device copy (counter calibration); for profiler runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part "
@@ -100,6 +103,17 @@ def main():
     print(f"[bench] {prob.name}: n={prob.n} omega={prob.omega:.2f} t={o_mixed.t:.3e} "
           f"s={o_mixed.shift:.4f}", file=sys.stderr, flush=True)
 
+    if args.roofline_only:
+        args.warmup = 0
+        args.steps = 0
+        args.no_fp64 = True
+        args.no_cpu = True
+        # plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
+        src = torch.ones(1 << 26, dtype=torch.complex128, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for w in range(args.warmup):
         ud.zero_()
         st = mxp.mxp_solve(P, o_mixed, fd, ud)
@@ -114,8 +128,8 @@ def main():
         print(f"[bench] step {k}: {st}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    s_per_solve = elapsed / args.steps
-    st = stats[-1]
+    s_per_solve = elapsed / max(args.steps, 1)
+    st = stats[-1] if stats else None
 
     fp64 = None
     if not args.no_fp64:
@@ -179,7 +193,7 @@ def main():
                    "rtol": o_mixed.rtol, "outer_restart": o_mixed.outer_restart,
                    "inner_restart": o_mixed.inner_restart, "precision": "mixed"},
         "solve": {k: st[k] for k in ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions",
-                                     "true_relres")},
+                                     "true_relres")} if st else None,
         "schedule_c64": {"S": sch.S, "m": sch.m, "m_psi": sch.m_psi},
         "plain_fp64": fp64,
         "roofline": roofline,
