@@ -214,6 +214,22 @@ mxp_status mxp_apply_psi1(mxp_problem* prob, double t, double shift, mxp_dtype d
 mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r,
                              void* w, int32_t* inner_its);
 
+/* ------------------------------------------------------------ tiling */
+
+/* 2D grids evaluate the Chebyshev series by temporally blocked passes: K
+ * consecutive Clenshaw levels per pass over HBM (1..8), NX complex values per
+ * work-item (1 or 2), Ly grid rows per wavefront segment (>= 1).  By default
+ * the first action on a problem times a set of candidates on the problem's
+ * own buffers and keeps the fastest (per precision).
+ * mxp_set_tiles fixes the configuration (K = 0 restores autotuning at the
+ * next action); mxp_get_tiles reports it (K = 0 if not tuned yet) with the
+ * measured microseconds per Clenshaw level (0 if fixed by the caller).
+ * precision selects the complex-double (MXP_PREC_FP64) or complex-float
+ * (MXP_PREC_MIXED) kernels.  Errors: INVALID_ARG. */
+mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, int32_t NX, int32_t Ly);
+mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32_t* K, int32_t* NX,
+                         int32_t* Ly, double* us_per_level);
+
 /* ------------------------------------------------------------------ solve */
 
 /* Solves A u = -f by FGMRES(outer_restart) preconditioned by Algorithm 1

@@ -3,7 +3,7 @@
 Argument marshalling only: every step of the computation runs in the HIP
 library.  Functions carry the C-ABI names and take torch tensors (device
 vectors), returning results or raising MxpError on a negative status.  The
-library must have been built (paper_2506_03617_amd.build); importing this
+library must have been built (paper_2506_03617_amd/build.py); importing this
 module fails loudly if it is missing.
 """
 from __future__ import annotations
@@ -116,12 +116,13 @@ ABI_SYMBOLS = (
     "mxp_problem_create", "mxp_problem_destroy", "mxp_problem_size",
     "mxp_solve_opts_default", "mxp_design_schedule",
     "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_precond", "mxp_solve",
+    "mxp_set_tiles", "mxp_get_tiles",
 )
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_03617_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2506_03617_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     st = ctypes.c_int
@@ -141,6 +142,9 @@ def _load():
         "mxp_apply_psi1": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_precond": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(ctypes.c_int32)]),
         "mxp_solve": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(mxp_solve_stats)]),
+        "mxp_set_tiles": (st, [P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+        "mxp_get_tiles": (st, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -318,3 +322,15 @@ def mxp_solve(prob: Problem, opts: mxp_solve_opts, f, u) -> dict:
     out = st.as_dict()
     out["status"] = status
     return out
+
+
+def mxp_set_tiles(prob: Problem, precision: int, K: int, NX: int, Ly: int) -> None:
+    _check(lib.mxp_set_tiles(prob.handle, precision, K, NX, Ly))
+
+
+def mxp_get_tiles(prob: Problem, precision: int) -> dict:
+    K, NX, Ly = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    us = ctypes.c_double()
+    _check(lib.mxp_get_tiles(prob.handle, precision, ctypes.byref(K), ctypes.byref(NX), ctypes.byref(Ly),
+                             ctypes.byref(us)))
+    return {"K": K.value, "NX": NX.value, "Ly": Ly.value, "us_per_level": us.value}

@@ -1,6 +1,7 @@
 """Builds libmatexpre.so (HIP for gfx950) in the package directory.
 
-Run as `python -m paper_2506_03617_amd.build` or through __graft_entry__.build().
+Run as `python paper_2506_03617_amd/build.py` or through __graft_entry__.build()
+(not through the package, whose import loads the library being rebuilt).
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmatexpre.so")
 
-SOURCES = ["kernels.hip", "schedule.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "cheb2d.hip", "schedule.cpp", "api.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

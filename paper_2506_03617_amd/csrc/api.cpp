@@ -86,11 +86,23 @@ struct DiagTables {
     DevMem mem64, mem32;
     cpx<double>* g64[3] = {nullptr, nullptr, nullptr};
     cpx<float>* g32[3] = {nullptr, nullptr, nullptr};
+    // 2D fused passes: h^2-scaled alpha, beta, gamma of the x and y axes
+    // ([axis][alpha, beta, gamma]) and the interior box with unit weights
+    DevMem fmem64, fmem32;
+    cpx<double>* f64[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    cpx<float>* f32[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int64_t ix0 = 0, ix1 = 0, iy0 = 0, iy1 = 0;
 };
 
 struct Sched {
     mxp_schedule s;
     DiagTables diag;
+};
+
+// Tile configuration of the temporally blocked 2D Clenshaw pass.
+struct TileCfg {
+    int K = 0, NX = 1, Ly = 32;
+    double us_per_level = 0.0;
 };
 
 }  // namespace mxp
@@ -106,7 +118,8 @@ struct mxp_problem {
     std::map<double, std::unique_ptr<mxp::DiagTables>> plain_diag;  // centre 0, keyed by shift
     double Dref = 0.0;  // reference value of D folded into the diagonal tables
     // workspaces
-    mxp::DevMem act64[4], act32[6];
+    mxp::DevMem act64[8], act32[10];  // [0..5] pass/substep buffers, [6] psi addend, (f32) [7..8] casts
+    mxp::TileCfg tiles[2];             // per precision (0 = double, 1 = float); K = 0 until tuned
     mxp::DevMem innerV, innerRh, innerTmp, innerRr;
     mxp::DevMem outerV, outerZ, outerR;
     mxp::DevMem partial, small;
@@ -178,6 +191,53 @@ static void build_diag(mxp_problem* P, double shift, cd centre, DiagTables& dt) 
             }
         }
         off += g.n[d];
+    }
+    // Interior box: a node needs alpha = beta = 1/h^2 on its axis, i.e. the
+    // stretch is 1 at the node and both half-nodes.  Nodes 0 and n-1 are
+    // excluded so that every neighbour read stays inside the grid there.
+    auto span = [&](int d, int64_t* lo, int64_t* hi) {
+        const AxisLayer ax = g.axis(d);
+        int64_t a0 = 1, a1 = g.n[d] - 1;
+        while (a0 < a1 && (ax.sigma(a0 * g.h) != 0.0 || ax.sigma((a0 - 0.5) * g.h) != 0.0 ||
+                           ax.sigma((a0 + 0.5) * g.h) != 0.0))
+            ++a0;
+        while (a1 > a0 && (ax.sigma((a1 - 1) * g.h) != 0.0 || ax.sigma((a1 - 0.5) * g.h) != 0.0 ||
+                           ax.sigma((a1 - 1.5) * g.h) != 0.0))
+            --a1;
+        *lo = a0;
+        *hi = a1;
+    };
+    if (g.dim == 2) {
+        span(0, &dt.ix0, &dt.ix1);
+        span(1, &dt.iy0, &dt.iy1);
+        if (!(dt.ix0 < dt.ix1 && dt.iy0 < dt.iy1)) dt.ix0 = dt.ix1 = dt.iy0 = dt.iy1 = 0;
+        const double h2 = g.h * g.h;
+        const size_t tot2 = 3 * size_t(g.n[0] + g.n[1]);
+        std::vector<cpx<double>> s64(tot2);
+        std::vector<cpx<float>> s32(tot2);
+        size_t o = 0, fo[2][3];
+        for (int d = 0; d < 2; ++d) {
+            const AxisTables at = build_axis_tables(g.axis(d));
+            const std::vector<cd>* src[3] = {&at.alpha, &at.beta, &at.gamma};
+            for (int q = 0; q < 3; ++q) {
+                fo[d][q] = o;
+                for (int64_t i = 0; i < g.n[d]; ++i) {
+                    const cd v = ((*src[q])[i] + (q == 2 ? share : cd(0.0, 0.0))) * h2;
+                    s64[o + i] = {v.real(), v.imag()};
+                    s32[o + i] = {float(v.real()), float(v.imag())};
+                }
+                o += g.n[d];
+            }
+        }
+        dt.fmem64.ensure(tot2 * sizeof(cpx<double>));
+        dt.fmem32.ensure(tot2 * sizeof(cpx<float>));
+        HIP_CHECK(hipMemcpy(dt.fmem64.p, s64.data(), tot2 * sizeof(cpx<double>), hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(dt.fmem32.p, s32.data(), tot2 * sizeof(cpx<float>), hipMemcpyHostToDevice));
+        for (int d = 0; d < 2; ++d)
+            for (int q = 0; q < 3; ++q) {
+                dt.f64[d][q] = dt.fmem64.as<cpx<double>>() + fo[d][q];
+                dt.f32[d][q] = dt.fmem32.as<cpx<float>>() + fo[d][q];
+            }
     }
     dt.mem64.ensure(total * sizeof(cpx<double>));
     dt.mem32.ensure(total * sizeof(cpx<float>));
@@ -301,6 +361,83 @@ static DevMem* act_buffers(mxp_problem* P) {
     if constexpr (sizeof(R) == 8) return P->act64; else return P->act32;
 }
 
+template <typename R>
+static ChebPassArgs<R> pass_base(mxp_problem* P, const StencilArgs<R>& st, const DiagTables& dt) {
+    ChebPassArgs<R> a{};
+    a.n0 = st.n0;
+    a.n1 = st.n1;
+    cpx<R>* const(*f)[3];
+    if constexpr (sizeof(R) == 8) f = dt.f64; else f = dt.f32;
+    a.ax = f[0][0];
+    a.bx = f[0][1];
+    a.gx = f[0][2];
+    a.ay = f[1][0];
+    a.by = f[1][1];
+    a.gy = f[1][2];
+    a.D = st.D;
+    a.Dconst = st.Dconst;
+    a.Dref = st.Dref;
+    const double h2 = P->g.h * P->g.h;
+    a.kD = {R(double(st.kD.re) * h2), R(double(st.kD.im) * h2)};
+    a.ix0 = dt.ix0;
+    a.ix1 = dt.ix1;
+    a.iy0 = dt.iy0;
+    a.iy1 = dt.iy1;
+    return a;
+}
+
+// out = post * (sum_k c_k T_k(Ahat) x + add) by fused Clenshaw passes (2D).
+// bufs: four scratch vectors distinct from x, add and out.
+template <typename R>
+static void cheb_series_fused(mxp_problem* P, const StencilArgs<R>& st, const DiagTables& dt, const TileCfg& tc,
+                              const mxp_schedule& sc, const double* coef, int m, const cpx<R>* x,
+                              cpx<R>* out, cpx<R>* const bufs[4], cd post, const cpx<R>* add,
+                              int64_t* steps) {
+    ChebPassArgs<R> a = pass_base<R>(P, st, dt);
+    a.x = x;
+    if (post.imag() != 0.0) fail(MXP_ERR_INVALID_ARG, "series scaling must be real");
+    const double inv_h2 = 1.0 / (P->g.h * P->g.h);
+    a.post = R(post.real());
+    a.e3 = add ? R(post.real()) : R(0);
+    const R post_final = a.post, e3_final = a.e3;
+    const cpx<R>* prevA = nullptr;
+    const cpx<R>* prevB = nullptr;
+    int pair = 0;
+    int q0 = 0;
+    while (q0 <= m) {
+        const int nlev = std::min(tc.K, m + 1 - q0);
+        const bool last = (q0 + nlev == m + 1);
+        for (int l = 0; l < nlev; ++l) {
+            // level q: b_{m-q} = c_{m-q} x + (2/hw) A_s-step - b_{m-q+2}; the final
+            // level uses c_0 and 1/hw and is scaled by post in the kernel
+            const int q = q0 + l;
+            const cd cx = coef_at(coef, m - q);
+            const double gq = (q == 0) ? 0.0 : (q == m ? 1.0 : 2.0) / sc.half_width;
+            a.cx[l] = to_cpx<R>(cx);
+            a.g[l] = R(gq * inv_h2);
+        }
+        a.final_pass = last ? 1 : 0;
+        // non-final passes end on a plain level: unit scale, no addend
+        a.post = last ? post_final : R(1);
+        a.e3 = last ? e3_final : R(0);
+        a.in0 = prevA;
+        a.in1 = prevB;
+        a.add = last ? add : nullptr;
+        a.outA = last ? nullptr : bufs[2 * pair];
+        a.outB = last ? out : bufs[2 * pair + 1];
+        cheb2d_geometry<R>(a, nlev, tc.NX, tc.Ly);
+        launch_cheb2d<R>(a, nlev, tc.NX, P->ctx->stream);
+        prevA = a.outA;
+        prevB = a.outB;
+        pair ^= 1;
+        q0 += nlev;
+    }
+    *steps += m;
+}
+
+template <typename R>
+static void tune_tiles(mxp_problem* P, const Sched& sd);
+
 // y = exp(i t A_s) x (psi = false) or psi_1(i t A_s) x (psi = true), precision R.
 // x and y distinct device vectors of precision R.
 template <typename R>
@@ -309,49 +446,137 @@ static void action(mxp_problem* P, const Sched& sd, double t, double shift, bool
     const mxp_schedule& sc = sd.s;
     const int64_t n = npts(P);
     DevMem* W = act_buffers<R>(P);
-    for (int q = 0; q < 4; ++q) W[q].ensure(size_t(n) * sizeof(cpx<R>));
-    cpx<R>* w[3] = {W[0].as<cpx<R>>(), W[1].as<cpx<R>>(), W[2].as<cpx<R>>()};
-    cpx<R>* pbuf = W[3].as<cpx<R>>();
+    for (int q = 0; q < 7; ++q) W[q].ensure(size_t(n) * sizeof(cpx<R>));
+    cpx<R>* w[6];
+    for (int q = 0; q < 6; ++q) w[q] = W[q].as<cpx<R>>();
+    cpx<R>* pbuf = W[6].as<cpx<R>>();
     const StencilArgs<R> base = base_args<R>(P, shift, sd.diag);
+    const bool fused = (P->g.dim == 2);
+    TileCfg tc;
+    if (fused) {
+        TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
+        if (slot.K == 0) tune_tiles<R>(P, sd);
+        tc = slot;
+    }
     const int S = sc.S;
-    auto others = [&](const cpx<R>* cur, cpx<R>** a, cpx<R>** b) {
+    // Scratch for one series: five buffers other than its input (four for the
+    // passes, one for the output); the unfused path uses two of them.
+    auto pick = [&](const cpx<R>* cur, cpx<R>** b, cpx<R>** o) {
         int k = 0;
-        cpx<R>* pick[2];
-        for (int q = 0; q < 3 && k < 2; ++q)
-            if (w[q] != cur) pick[k++] = w[q];
-        *a = pick[0];
-        *b = pick[1];
+        for (int q = 0; q < 6 && k < 5; ++q)
+            if (w[q] != cur) {
+                if (k < 4) b[k] = w[q]; else *o = w[q];
+                ++k;
+            }
+    };
+    auto series = [&](const double* coef, int m, const cpx<R>* xin, cpx<R>* out, cd post,
+                      const cpx<R>* add) {
+        cpx<R>* b[4];
+        cpx<R>* spare;
+        pick(xin, b, &spare);
+        if (fused) {
+            cheb_series_fused<R>(P, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
+        } else {
+            // unfused: the final step writes in place over b_2 unless out is given
+            cheb_series<R>(P, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
+        }
+    };
+    auto substep_out = [&](const cpx<R>* xin) {
+        cpx<R>* b[4];
+        cpx<R>* spare = nullptr;
+        pick(xin, b, &spare);
+        return spare;
     };
     const cpx<R>* xcur = x;
     int first = 0;
     const cpx<R>* add = nullptr;
     if (psi) {
         // p = tau psi_1(i tau A_s) x; with S == 1 the answer is p / t.
-        cpx<R>* bA = w[0];
-        cpx<R>* bB = w[1];
         if (S == 1) {
-            cheb_series<R>(P, base, sc, sc.coef_psi, sc.m_psi, x, y, bA, bB, cd(1.0 / t, 0), nullptr, steps);
+            series(sc.coef_psi, sc.m_psi, x, y, cd(1.0 / t, 0.0), nullptr);
             return;
         }
-        cheb_series<R>(P, base, sc, sc.coef_psi, sc.m_psi, x, pbuf, bA, bB, cd(1.0, 0), nullptr, steps);
+        series(sc.coef_psi, sc.m_psi, x, pbuf, cd(1.0, 0.0), nullptr);
         xcur = pbuf;
         add = pbuf;
         first = 1;
     }
     for (int sub = first; sub < S; ++sub) {
         const bool last = (sub == S - 1);
-        cpx<R>* bA;
-        cpx<R>* bB;
-        others(xcur, &bA, &bB);
-        // The final Clenshaw step writes in place over b_2.  After the two
-        // opening steps b_{m-1} sits in bA and b_{m-2} in bB; each of the m-3
-        // loop steps swaps the roles, so b_2 ends in bA when m-3 is even.
-        cpx<R>* b2buf = ((sc.m - 3) % 2 == 0) ? bA : bB;
-        cpx<R>* out = last ? y : b2buf;
+        cpx<R>* out = last ? y : substep_out(xcur);
         const cd post = (psi && last) ? cd(1.0 / t, 0.0) : cd(1.0, 0.0);
-        cheb_series<R>(P, base, sc, sc.coef, sc.m, xcur, out, bA, bB, post, add, steps);
+        series(sc.coef, sc.m, xcur, out, post, add);
         xcur = out;
     }
+}
+
+// Times candidate tile configurations of the fused 2D pass on this problem's
+// own buffers (HIP events on the context stream) and keeps the fastest per
+// Clenshaw level.
+template <typename R>
+static void tune_tiles(mxp_problem* P, const Sched& sd) {
+    const int64_t n = npts(P);
+    hipStream_t s = P->ctx->stream;
+    DevMem* W = act_buffers<R>(P);
+    for (int q = 0; q < 7; ++q) {
+        W[q].ensure(size_t(n) * sizeof(cpx<R>));
+        launch_zero<R>(W[q].as<cpx<R>>(), n, s);
+    }
+    const StencilArgs<R> st = base_args<R>(P, 0.0, sd.diag);
+    ChebPassArgs<R> a = pass_base<R>(P, st, sd.diag);
+    a.x = W[0].as<cpx<R>>();
+    a.in0 = W[1].as<cpx<R>>();
+    a.in1 = W[2].as<cpx<R>>();
+    a.outA = W[3].as<cpx<R>>();
+    a.outB = W[4].as<cpx<R>>();
+    for (int l = 0; l < kMaxFused; ++l) {
+        a.cx[l] = {R(0.1), R(0)};
+        a.g[l] = R(0.1);
+    }
+    a.post = R(1);
+    a.e3 = R(0);
+    a.final_pass = 0;
+    TileCfg best;
+    best.us_per_level = 1e300;
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    const int Ks[] = {2, 3, 4, 6, 8};
+    const int Lys[] = {16, 32, 64, 128};
+    for (int NX = 1; NX <= 2; ++NX) {
+        for (int K : Ks) {
+            if (sizeof(R) == 8 && NX == 2 && K > 3) continue;  // register-limited
+            for (int Ly : Lys) {
+                // segments longer than the grid only repeat the one-segment case
+                if (Ly != Lys[0] && Ly / 2 >= P->g.n[1]) continue;
+                cheb2d_geometry<R>(a, K, NX, Ly);
+                if (a.W <= 0) continue;
+                launch_cheb2d<R>(a, K, NX, s);  // warm
+                HIP_CHECK(hipEventRecord(e0, s));
+                const int reps = 3;
+                for (int r = 0; r < reps; ++r) launch_cheb2d<R>(a, K, NX, s);
+                HIP_CHECK(hipEventRecord(e1, s));
+                HIP_CHECK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1e3 * ms / (reps * K);
+                if (P->ctx->verbose) {
+                    std::fprintf(stderr, "[mxp] tune %s K=%d NX=%d Ly=%d: %.3f us/level\n",
+                                 sizeof(R) == 4 ? "c64" : "c128", K, NX, Ly, us);
+                }
+                if (us < best.us_per_level) {
+                    best.K = K;
+                    best.NX = NX;
+                    best.Ly = Ly;
+                    best.us_per_level = us;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best.K == 0) fail(MXP_ERR_HIP, "tile autotuning measured no candidate");
+    P->tiles[sizeof(R) == 4 ? 1 : 0] = best;
 }
 
 // ------------------------------------------------------------ Krylov helpers
@@ -481,10 +706,10 @@ static void action64(mxp_problem* P, const Sched& sc, double t, double shift, bo
         return;
     }
     const int64_t n = npts(P);
-    P->act32[4].ensure(size_t(n) * sizeof(cpx<float>));
-    P->act32[5].ensure(size_t(n) * sizeof(cpx<float>));
-    cpx<float>* xs = P->act32[4].as<cpx<float>>();
-    cpx<float>* ys = P->act32[5].as<cpx<float>>();
+    P->act32[7].ensure(size_t(n) * sizeof(cpx<float>));
+    P->act32[8].ensure(size_t(n) * sizeof(cpx<float>));
+    cpx<float>* xs = P->act32[7].as<cpx<float>>();
+    cpx<float>* ys = P->act32[8].as<cpx<float>>();
     launch_to_c64(x, xs, n, P->ctx->stream);
     action<float>(P, sc, t, shift, psi, xs, ys, steps);
     launch_to_c128(ys, y, n, P->ctx->stream);
@@ -885,6 +1110,35 @@ mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, cons
                                 cnt);
         HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
         if (inner_its) *inner_its = its;
+        return MXP_OK;
+    });
+}
+
+mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, int32_t NX, int32_t Ly) {
+    return guard([&]() {
+        if (!prob) fail(MXP_ERR_INVALID_ARG, "problem is NULL");
+        if (precision != MXP_PREC_FP64 && precision != MXP_PREC_MIXED) fail(MXP_ERR_INVALID_ARG, "unknown precision");
+        if (K < 0 || K > kMaxFused || (NX != 1 && NX != 2) || Ly < 1 || (K > 0 && NX * 64 - 2 * K <= 0))
+            fail(MXP_ERR_INVALID_ARG, "tiles: K in 0..8, NX in {1, 2}, Ly >= 1");
+        TileCfg& t = prob->tiles[precision == MXP_PREC_MIXED ? 1 : 0];
+        t.K = K;
+        t.NX = NX;
+        t.Ly = Ly;
+        t.us_per_level = 0.0;
+        return MXP_OK;
+    });
+}
+
+mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32_t* K, int32_t* NX,
+                         int32_t* Ly, double* us_per_level) {
+    return guard([&]() {
+        if (!prob) fail(MXP_ERR_INVALID_ARG, "problem is NULL");
+        if (precision != MXP_PREC_FP64 && precision != MXP_PREC_MIXED) fail(MXP_ERR_INVALID_ARG, "unknown precision");
+        const TileCfg& t = prob->tiles[precision == MXP_PREC_MIXED ? 1 : 0];
+        if (K) *K = t.K;
+        if (NX) *NX = t.NX;
+        if (Ly) *Ly = t.Ly;
+        if (us_per_level) *us_per_level = t.us_per_level;
         return MXP_OK;
     });
 }

@@ -51,6 +51,51 @@ struct StencilArgs {
 template <typename R>
 void launch_stencil(const StencilArgs<R>& a, hipStream_t s);
 
+// One temporally blocked Clenshaw pass on a 2D grid (vectors below 4 GiB):
+// K consecutive levels
+//   L_l = cx_l x + g_l S(L_{l-1}) - L_{l-2}
+// with S the h^2-scaled stencil (tables ax/bx/gx, ay/by/gy multiplied by h^2,
+// kD likewise, so interior nodes have unit neighbour weights), inputs
+// in0 = L_{-2}, in1 = L_{-1} (nullptr = zero).  A non-final pass writes its
+// second-to-last level to outA and its last to outB; a final pass writes
+// post * L_last + e3 * add to outB only.  Outputs must not alias any input:
+// neighbouring strips and segments read input halos concurrently.
+constexpr int kMaxFused = 8;
+template <typename R>
+struct ChebPassArgs {
+    int64_t n0, n1;
+    const cpx<R>* ax;
+    const cpx<R>* bx;
+    const cpx<R>* gx;
+    const cpx<R>* ay;
+    const cpx<R>* by;
+    const cpx<R>* gy;
+    const R* D;
+    R Dconst, Dref;
+    cpx<R> kD;
+    const cpx<R>* x;
+    const cpx<R>* in0;
+    const cpx<R>* in1;
+    const cpx<R>* add;
+    cpx<R>* outA;
+    cpx<R>* outB;
+    cpx<R> cx[kMaxFused];
+    R g[kMaxFused];
+    R post, e3;
+    int final_pass;
+    // interior box: columns [ix0, ix1) and rows [iy0, iy1) have unit
+    // neighbour weights on both axes (outside the layers and the end nodes)
+    int64_t ix0, ix1, iy0, iy1;
+    // set by launch_cheb2d: every pointer is valid, these flags mark absent operands
+    int in0_zero, in1_zero, D_const;
+    // geometry (cheb2d_geometry): strips of W output columns, segments of Ly rows
+    int W, strips, Ly, segs;
+};
+template <typename R>
+void cheb2d_geometry(ChebPassArgs<R>& a, int K, int NX, int Ly);
+template <typename R>
+void launch_cheb2d(const ChebPassArgs<R>& a, int K, int NX, hipStream_t s);
+
 // Complex-double BLAS-1 and deterministic reductions.  Vectors have length n;
 // a "block" V holds nv vectors of length n back to back (stride ld >= n).
 // Reductions write per-workgroup partial sums to `partial` and a second

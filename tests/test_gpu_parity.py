@@ -215,3 +215,39 @@ def test_argument_errors(ctx):
         mxp.mxp_solve(P, o, xd, torch.zeros_like(xd))
     with pytest.raises(mxp.MxpError):
         mxp.mxp_apply_exp(P, -1.0, 0.1, xd, torch.zeros_like(xd))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("NX", [1, 2])
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_fused_passes_every_tile_shape(ctx, K, NX, prec):
+    # every level count a final pass can have, both lane widths, segments that
+    # do not divide the grid (67 x 45 with Ly = 13), against the oracle
+    if prec == 0 and NX == 2 and K > 3:
+        pytest.skip("register-limited shape, never selected")
+    prob = make("2d-inh")
+    announce("fused tiles", K, NX, prec)
+    P = mxp.Problem(ctx, prob)
+    mxp.mxp_set_tiles(P, prec, K, NX, 13)
+    t, s = prob.default_t(), prob.default_shift()
+    x = wl.random_vector(prob.npts, 8)
+    tdt = torch.complex128 if prec == 0 else torch.complex64
+    xd = to_dev(x, tdt)
+    yd = torch.empty_like(xd)
+    As = op.helmholtz(prob, s)
+    mxp.mxp_apply_exp(P, t, s, xd, yd)
+    assert rel(to_host(yd), matfun.exp_action(As, t, to_host(xd))) <= (1e-11 if prec == 0 else 1e-5)
+    mxp.mxp_apply_psi1(P, t, s, xd, yd)
+    assert rel(to_host(yd), matfun.phi1_action(As, t, to_host(xd))) <= (1e-11 if prec == 0 else 1e-5)
+    assert mxp.mxp_get_tiles(P, prec)["K"] == K
+
+
+def test_autotuned_tiles_are_recorded(ctx):
+    prob = make("2d-homog")
+    P = mxp.Problem(ctx, prob)
+    assert mxp.mxp_get_tiles(P, 1)["K"] == 0
+    xd = to_dev(wl.random_vector(prob.npts, 1), torch.complex64)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_exp(P, prob.default_t(), prob.default_shift(), xd, yd)
+    tiles = mxp.mxp_get_tiles(P, 1)
+    assert 1 <= tiles["K"] <= 8 and tiles["NX"] in (1, 2) and tiles["us_per_level"] > 0
