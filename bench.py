@@ -27,7 +27,7 @@ PEAK_HBM_GBS = 8000.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("kernels.hip", "kernels.h"):
+    for name in ("kernels.hip", "kernels.h", "cheb2d.hip"):
         with open(os.path.join(ROOT, "paper_2506_03617_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-reps", type=int, default=3)
+    ap.add_argument("--tiles", default=None,
+                    help="K,NX,Ly of the fused 2D passes for both precisions (default: autotuned)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="skip the solves: run only the exp-action timing loop and a plain "
                          "1 GiB device copy (counter calibration); for profiler runs")
@@ -100,6 +102,10 @@ def main():
     ud = torch.zeros_like(fd)
     o_mixed = P.default_opts()
     o_mixed.precision = mxp.MXP_PREC_MIXED
+    if args.tiles:
+        K_, NX_, Ly_ = (int(v) for v in args.tiles.split(","))
+        for prec in (mxp.MXP_PREC_FP64, mxp.MXP_PREC_MIXED):
+            mxp.mxp_set_tiles(P, prec, K_, NX_, Ly_)
     print(f"[bench] {prob.name}: n={prob.n} omega={prob.omega:.2f} t={o_mixed.t:.3e} "
           f"s={o_mixed.shift:.4f}", file=sys.stderr, flush=True)
 
@@ -143,14 +149,15 @@ def main():
                 ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions", "true_relres")}}
         print(f"[bench] fp64: {fp64}", file=sys.stderr, flush=True)
 
-    # Dominant kernel: the complex-float Clenshaw stencil step.  Average launch
-    # duration from HIP events around complete exp actions on the library's
-    # stream (torch's current stream), divided by the stencil steps they run.
+    # Dominant kernel: the complex-float fused Clenshaw pass k_cheb2d<float, K, NX>
+    # (each launch computes K Clenshaw levels).  Average launch duration from HIP
+    # events around complete exp actions on the library's stream (torch's current
+    # stream), divided by the passes they launch.
     sch = mxp.mxp_design_schedule(P.desc, o_mixed.t, o_mixed.shift, mxp.MXP_PREC_MIXED)
-    steps_per_action = sch.S * sch.m
     x32 = torch.randn(prob.npts, dtype=torch.complex64, device="cuda:0")
     y32 = torch.empty_like(x32)
-    mxp.mxp_apply_exp(P, o_mixed.t, o_mixed.shift, x32, y32)
+    mxp.mxp_apply_exp(P, o_mixed.t, o_mixed.shift, x32, y32)  # tunes the tiles if needed
+    tiles = mxp.mxp_get_tiles(P, mxp.MXP_PREC_MIXED)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
@@ -158,17 +165,30 @@ def main():
         mxp.mxp_apply_exp(P, o_mixed.t, o_mixed.shift, x32, y32)
     ev1.record()
     torch.cuda.synchronize()
-    avg_launch_s = ev0.elapsed_time(ev1) * 1e-3 / (args.roofline_reps * steps_per_action)
-    # algorithmic bytes per point of one step: read b_{k+1}, b_{k+2}, x (8 B each),
-    # D (4 B, inhomogeneous), write b_k (8 B)
-    bpp = 8 * 4 + (0 if prob.c is None else 4)
-    bytes_per_launch = bpp * prob.npts
+    t_action = ev0.elapsed_time(ev1) * 1e-3 / args.roofline_reps
+    K = tiles["K"]
+    passes = -(-(sch.m + 1) // K)   # passes per series (m + 1 Clenshaw levels)
+    # algorithmic bytes per pass and point: inputs L_{-2}, L_{-1} (8 B each, absent
+    # in the first pass), x (8 B), D (4 B, inhomogeneous only); outputs two levels
+    # (8 B each; one in the final pass)
+    rd_xD = 8 + (0 if prob.c is None else 4)
+    if passes == 1:
+        per_series = rd_xD + 8
+    else:
+        per_series = (rd_xD + 16) + (passes - 2) * (16 + rd_xD + 16) + (16 + rd_xD + 8)
+    launches = sch.S * passes
+    bytes_per_launch = per_series * prob.npts / passes
+    avg_launch_s = t_action / launches
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic("stencil_c64", prob.name)
+    traffic = load_traffic(f"cheb2d_c64_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}", prob.name)
+    # the same work as unfused Clenshaw steps (36 B per point per step read and written)
+    unfused_equiv = (36 if prob.c is not None else 32) * prob.npts * sch.S * sch.m / t_action / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": "k_stencil<float,2> (Clenshaw step)",
-                "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": bytes_per_launch}
+                "kernel": f"k_cheb2d<float,{K},{tiles['NX']}> (fused Clenshaw pass, Ly={tiles['Ly']})",
+                "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": round(bytes_per_launch),
+                "levels_per_launch": K, "us_per_clenshaw_level": round(t_action / (sch.S * sch.m) * 1e6, 3),
+                "unfused_step_equivalent_GBps": round(unfused_equiv, 1)}
 
     cpu = None
     if not args.no_cpu:
