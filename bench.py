@@ -1,7 +1,8 @@
 """Benchmark: time to solve the 2D inhomogeneous Helmholtz workload
 (2048^2 grid, Gaussian-random-field speed in [1, 3], ppw 8 at c_min,
 32-cell absorbing layer, one point source) to 1e-6 relative residual with
-MatExPre-preconditioned FGMRES on one MI355X.
+MatExPre-preconditioned FGMRES on one MI355X.  `--workload` selects the
+2D homogeneous 128^2 or the 3D homogeneous 256^3 workload instead.
 
 One step = one complete solve (outer FGMRES, every preconditioner apply,
 every exp / psi_1 action) in the chosen mixed form (complex-float stepping,
@@ -53,6 +54,8 @@ def cpu_baseline(prob, f, actions_per_solve: int, fraction: int = 16):
     full grid, scaled by `fraction` and by the number of matrix-function actions
     one GPU solve performs."""
     from oracle import matfun, operator as op
+    if prob.dim == 3:
+        fraction *= 2
     threads = os.environ.get("OMP_NUM_THREADS")
     As = op.helmholtz(prob, prob.default_shift())
     v = f.ravel().astype(np.complex128)
@@ -64,9 +67,69 @@ def cpu_baseline(prob, f, actions_per_solve: int, fraction: int = 16):
         "unit": "s per solve (extrapolated)",
         "cores": int(threads) if threads else os.cpu_count(),
         "kind": "oracle",
-        "sample": f"one exp(i(t/{fraction})A_s)v action at {prob.n[0]}x{prob.n[1]} by expm_multiply "
+        "sample": f"one exp(i(t/{fraction})A_s)v action at {'x'.join(map(str, prob.n))} by expm_multiply "
                   f"({t_sample:.1f} s), times {fraction} and {actions_per_solve} actions per solve",
     }
+
+
+def measure_roofline(mxp, torch, P, prob, o, reps):
+    """Roofline of the dominant kernel of the mixed solve: the complex-float
+    Clenshaw kernel.  Its average launch duration comes from HIP events around
+    complete exp actions on the library's stream (torch's current stream),
+    divided by the launches those actions make."""
+    sch = mxp.mxp_design_schedule(P.desc, o.t, o.shift, mxp.MXP_PREC_MIXED)
+    x32 = torch.randn(prob.npts, dtype=torch.complex64, device="cuda:0")
+    y32 = torch.empty_like(x32)
+    mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)  # tunes the tiles if needed
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_action = ev0.elapsed_time(ev1) * 1e-3 / reps
+    rd_D = 0 if prob.c is None else 4
+    m = sch.m
+    if prob.dim == 2:
+        # fused pass k_cheb2d<float, K, NX>: K Clenshaw levels per launch
+        tiles = mxp.mxp_get_tiles(P, mxp.MXP_PREC_MIXED)
+        K = tiles["K"]
+        passes = -(-(m + 1) // K)   # passes per series (m + 1 Clenshaw levels)
+        # per point: inputs L_{-2}, L_{-1} (8 B each, absent in the first pass),
+        # x (8 B), D; outputs two levels (8 B each; one in the final pass)
+        rd_xD = 8 + rd_D
+        if passes == 1:
+            per_series = rd_xD + 8
+        else:
+            per_series = (rd_xD + 16) + (passes - 2) * (16 + rd_xD + 16) + (16 + rd_xD + 8)
+        launches_per_series = passes
+        kernel = f"k_cheb2d<float,{K},{tiles['NX']}> (fused Clenshaw pass, Ly={tiles['Ly']})"
+        key = f"cheb2d_c64_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}"
+        extra = {"levels_per_launch": K}
+    else:
+        # unfused Clenshaw step k_stencil<float, 3>: one level per launch.  Per
+        # point: the first step reads x and writes b_{m-1}; the second reads
+        # b_{m-1}, x; every later step reads b_{k+1}, b_{k+2}, x; each reads D
+        # and writes one level (8 B per complex-float value)
+        per_series = (16 + rd_D) + (24 + rd_D) + (m - 2) * (32 + rd_D)
+        launches_per_series = m
+        kernel = "k_stencil3d<float,OPS> (z-marching Clenshaw step)"
+        key = "stencil3d_c64"
+        extra = {"levels_per_launch": 1}
+    launches = sch.S * launches_per_series
+    bytes_per_launch = per_series * prob.npts / launches_per_series
+    avg_launch_s = t_action / launches
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    # the same work as unfused Clenshaw steps (32 / 36 B per point per step)
+    unfused_equiv = (32 + rd_D) * prob.npts * sch.S * m / t_action / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(key, prob.name),
+            "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "bytes_per_launch": round(bytes_per_launch), **extra,
+            "us_per_clenshaw_level": round(t_action / (sch.S * m) * 1e6, 3),
+            "unfused_step_equivalent_GBps": round(unfused_equiv, 1),
+            "schedule_c64": {"S": sch.S, "m": m, "m_psi": sch.m_psi}}
 
 
 def main():
@@ -74,7 +137,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="2d-grf-2048", choices=["2d-grf-2048", "2d-homog-128"])
+    ap.add_argument("--workload", default="2d-grf-2048",
+                    choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-reps", type=int, default=3)
@@ -93,15 +157,21 @@ def main():
     import paper_2506_03617_amd as mxp
     import workloads as wl
 
-    prob = wl.config2() if args.workload == "2d-grf-2048" else wl.config1()
+    prob = {"2d-grf-2048": wl.config2, "2d-homog-128": wl.config1, "3d-homog-256": wl.config3}[args.workload]()
     centre = tuple(m // 2 for m in prob.n)
-    f = wl.delta_source(prob, centre)
+    if prob.dim == 3:
+        # Gaussian-smoothed point source, standard deviation 2 cells
+        f = wl.gaussian_source(prob, tuple(c * prob.h for c in centre), 2 * prob.h)
+    else:
+        f = wl.delta_source(prob, centre)
     ctx = mxp.Context(0)
     P = mxp.Problem(ctx, prob)
     fd = torch.from_numpy(f.ravel()).to("cuda:0")
     ud = torch.zeros_like(fd)
     o_mixed = P.default_opts()
     o_mixed.precision = mxp.MXP_PREC_MIXED
+    if prob.dim == 3:
+        o_mixed.outer_restart = 20   # FGMRES(20) for the 3D workloads
     if args.tiles:
         K_, NX_, Ly_ = (int(v) for v in args.tiles.split(","))
         for prec in (mxp.MXP_PREC_FP64, mxp.MXP_PREC_MIXED):
@@ -140,6 +210,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         o64 = P.default_opts()
+        o64.outer_restart = o_mixed.outer_restart
         ud.zero_()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -149,46 +220,7 @@ def main():
                 ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions", "true_relres")}}
         print(f"[bench] fp64: {fp64}", file=sys.stderr, flush=True)
 
-    # Dominant kernel: the complex-float fused Clenshaw pass k_cheb2d<float, K, NX>
-    # (each launch computes K Clenshaw levels).  Average launch duration from HIP
-    # events around complete exp actions on the library's stream (torch's current
-    # stream), divided by the passes they launch.
-    sch = mxp.mxp_design_schedule(P.desc, o_mixed.t, o_mixed.shift, mxp.MXP_PREC_MIXED)
-    x32 = torch.randn(prob.npts, dtype=torch.complex64, device="cuda:0")
-    y32 = torch.empty_like(x32)
-    mxp.mxp_apply_exp(P, o_mixed.t, o_mixed.shift, x32, y32)  # tunes the tiles if needed
-    tiles = mxp.mxp_get_tiles(P, mxp.MXP_PREC_MIXED)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.roofline_reps):
-        mxp.mxp_apply_exp(P, o_mixed.t, o_mixed.shift, x32, y32)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_action = ev0.elapsed_time(ev1) * 1e-3 / args.roofline_reps
-    K = tiles["K"]
-    passes = -(-(sch.m + 1) // K)   # passes per series (m + 1 Clenshaw levels)
-    # algorithmic bytes per pass and point: inputs L_{-2}, L_{-1} (8 B each, absent
-    # in the first pass), x (8 B), D (4 B, inhomogeneous only); outputs two levels
-    # (8 B each; one in the final pass)
-    rd_xD = 8 + (0 if prob.c is None else 4)
-    if passes == 1:
-        per_series = rd_xD + 8
-    else:
-        per_series = (rd_xD + 16) + (passes - 2) * (16 + rd_xD + 16) + (16 + rd_xD + 8)
-    launches = sch.S * passes
-    bytes_per_launch = per_series * prob.npts / passes
-    avg_launch_s = t_action / launches
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic(f"cheb2d_c64_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}", prob.name)
-    # the same work as unfused Clenshaw steps (36 B per point per step read and written)
-    unfused_equiv = (36 if prob.c is not None else 32) * prob.npts * sch.S * sch.m / t_action / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": f"k_cheb2d<float,{K},{tiles['NX']}> (fused Clenshaw pass, Ly={tiles['Ly']})",
-                "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": round(bytes_per_launch),
-                "levels_per_launch": K, "us_per_clenshaw_level": round(t_action / (sch.S * sch.m) * 1e6, 3),
-                "unfused_step_equivalent_GBps": round(unfused_equiv, 1)}
+    roofline = measure_roofline(mxp, torch, P, prob, o_mixed, args.roofline_reps)
 
     cpu = None
     if not args.no_cpu:
@@ -207,14 +239,14 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64 stepping + c128 Krylov",
-        "data": "synthetic (seeded GRF speed, point source)",
+        "data": "synthetic (seeded GRF speed, point source)" if prob.c is not None
+                else "synthetic (constant speed, point source)",
         "config": {"workload": prob.name, "grid": list(prob.n), "omega": round(prob.omega, 3),
                    "layer": prob.layer, "t": o_mixed.t, "shift": o_mixed.shift, "fprtol": o_mixed.fprtol,
                    "rtol": o_mixed.rtol, "outer_restart": o_mixed.outer_restart,
                    "inner_restart": o_mixed.inner_restart, "precision": "mixed"},
         "solve": {k: st[k] for k in ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions",
                                      "true_relres")} if st else None,
-        "schedule_c64": {"S": sch.S, "m": sch.m, "m_psi": sch.m_psi},
         "plain_fp64": fp64,
         "roofline": roofline,
         "cpu_baseline": cpu,
