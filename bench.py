@@ -132,13 +132,74 @@ def measure_roofline(mxp, torch, P, prob, o, reps):
             "schedule_c64": {"S": sch.S, "m": m, "m_psi": sch.m_psi}}
 
 
+def bench_layered_batch(args, torch, mxp, wl):
+    """The layered batch: `--rhs` of the 32 surface sources on the 512x512x256
+    grid plus the 16 uneven 96^3..192^3 problems (one source each), solved by
+    one mxp_solve_batch call in the mixed form with FGMRES(20).  One step =
+    the whole batched solve."""
+    os.environ.setdefault("MXP_VERBOSE", "1")   # one line per outer iteration: progress
+    main_p = wl.config4_main()
+    extras = wl.config4_extras()
+    ctx = mxp.Context(0)
+    probs = [main_p] + extras
+    handles = [mxp.Problem(ctx, p) for p in probs]
+    which = [round(k * 31 / max(args.rhs - 1, 1)) for k in range(args.rhs)]
+    rhs = [wl.config4_sources(main_p, which)]
+    for p in extras:
+        rhs.append(wl.delta_source(p, (p.n[0] // 2, p.n[1] // 2, p.layer + 2)).ravel()[None, :])
+    opts = []
+    for h in handles:
+        o = h.default_opts()
+        o.precision = mxp.MXP_PREC_MIXED
+        o.outer_restart = 20
+        opts.append(o)
+    f_list = [torch.from_numpy(f).to("cuda:0") for f in rhs]
+    del rhs
+    u_list = [torch.zeros_like(f) for f in f_list]
+    print(f"[bench] layered batch: {args.rhs} sources on {main_p.n} + {len(extras)} extra grids",
+          file=sys.stderr, flush=True)
+    times, all_stats = [], None
+    for k in range(args.warmup + max(args.steps, 1)):
+        for u in u_list:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, all_stats = mxp.mxp_solve_batch(ctx, handles, opts, f_list, u_list, 0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"[bench] batch solve {k}: status {status}, {dt:.2f} s", file=sys.stderr, flush=True)
+        if k >= args.warmup:
+            times.append(dt)
+    s_per = sum(times) / len(times)
+    n_rhs = len(all_stats)
+    pts = sum(p.npts * (args.rhs if i == 0 else 1) for i, p in enumerate(probs))
+    line = {
+        "metric": "s to 1e-6 rel. residual (plain vs FP32/learned); stencil HBM GB/s vs peak",
+        "value": round(s_per, 3), "unit": "s", "n_gpus": 1, "steps": len(times), "warmup": args.warmup,
+        "ms_per_step": round(s_per * 1e3, 1), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 stepping + c128 Krylov",
+        "data": "synthetic (seeded layered speeds with two lenses, point sources)",
+        "config": {"workload": "3d-layered-batch", "main_grid": list(main_p.n), "main_sources": args.rhs,
+                   "extra_grids": [list(p.n) for p in extras], "right_hand_sides": n_rhs,
+                   "grid_points_total": pts, "precision": "mixed", "outer_restart": 20},
+        "per_rhs": [{k: s[k] for k in ("outer_its", "inner_mean", "stencil_steps", "true_relres", "seconds",
+                                       "status")} for s in all_stats],
+    }
+    print(json.dumps(line), flush=True)
+    for h in handles:
+        h.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d-grf-2048",
-                    choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256"])
+                    choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256", "3d-layered-batch"])
+    ap.add_argument("--rhs", type=int, default=2,
+                    help="3d-layered-batch: surface sources on the 512x512x256 grid (of 32)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-reps", type=int, default=3)
@@ -157,6 +218,9 @@ def main():
     import paper_2506_03617_amd as mxp
     import workloads as wl
 
+    if args.workload == "3d-layered-batch":
+        bench_layered_batch(args, torch, mxp, wl)
+        return
     prob = {"2d-grf-2048": wl.config2, "2d-homog-128": wl.config1, "3d-homog-256": wl.config3}[args.workload]()
     centre = tuple(m // 2 for m in prob.n)
     if prob.dim == 3:

@@ -159,6 +159,7 @@ typedef struct {
     double true_relres;       /* ||b - A u|| / ||b|| of the returned u, in double */
     double seconds;           /* wall time of the call                            */
     int32_t restarts;         /* outer restart cycles after the first             */
+    int32_t status;           /* this solve's outcome (mxp_status)                */
 } mxp_solve_stats;
 
 /* --------------------------------------------------------------- schedule */
@@ -240,6 +241,25 @@ mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32
  * Returns OK, NOT_CONVERGED (max_outer reached), or an error. */
 mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
                      mxp_solve_stats* stats);
+
+/* Solves many right-hand sides of one or more problems together (Section 3.4
+ * method, as mxp_solve, for each).  Problem q has nrhs[q] right-hand sides
+ * stored back to back at f[q] (nrhs[q] * size(q) complex doubles, device) and
+ * as many solutions at u[q] (read as initial guesses, overwritten); opts[q]
+ * are its options.  Every right-hand side runs its own FGMRES; their
+ * matrix-function actions advance in lockstep, and on 3D grids the stencil
+ * sweeps of one step run as one launch over all grids, uneven sizes
+ * included.  Right-hand sides are admitted while their estimated workspaces
+ * fit in free device memory (at most max_resident at once when > 0; at least
+ * one always runs).  stats (may be NULL) receives one entry per right-hand
+ * side, in order, with its own status.  Results equal those of separate
+ * mxp_solve calls bit for bit.  Returns OK, NOT_CONVERGED if any right-hand
+ * side did not converge, or the first error (its message names the
+ * right-hand side). */
+mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* problems,
+                           const int32_t* nrhs, const void* const* f, void* const* u,
+                           const mxp_solve_opts* opts, int32_t max_resident,
+                           mxp_solve_stats* stats);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,7 @@ class mxp_solve_stats(ctypes.Structure):
         ("true_relres", ctypes.c_double),
         ("seconds", ctypes.c_double),
         ("restarts", ctypes.c_int32),
+        ("status", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -116,7 +117,7 @@ ABI_SYMBOLS = (
     "mxp_problem_create", "mxp_problem_destroy", "mxp_problem_size",
     "mxp_solve_opts_default", "mxp_design_schedule",
     "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_precond", "mxp_solve",
-    "mxp_set_tiles", "mxp_get_tiles",
+    "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
 )
 
 
@@ -145,6 +146,9 @@ def _load():
         "mxp_set_tiles": (st, [P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "mxp_get_tiles": (st, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+        "mxp_solve_batch": (st, [P, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(mxp_solve_opts),
+                                 ctypes.c_int32, ctypes.POINTER(mxp_solve_stats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -322,6 +326,31 @@ def mxp_solve(prob: Problem, opts: mxp_solve_opts, f, u) -> dict:
     out = st.as_dict()
     out["status"] = status
     return out
+
+
+def mxp_solve_batch(ctx: Context, problems, opts, f_list, u_list, max_resident: int = 0):
+    """Batched solve: problems[q] with options opts[q]; f_list[q] / u_list[q]
+    are complex128 device tensors holding nrhs_q right-hand sides / solutions
+    back to back (shape (nrhs_q, size) or flat).  Returns (status, list of
+    per-right-hand-side stats dicts, in order)."""
+    nprob = len(problems)
+    sizes = [p.size for p in problems]
+    nrhs = [int(f.numel()) // n for f, n in zip(f_list, sizes)]
+    for f, u, n, k in zip(f_list, u_list, sizes, nrhs):
+        if f.numel() != k * n or u.numel() != k * n:
+            raise ValueError("f and u must hold a whole number of right-hand sides")
+        if _dtype_of(f) != MXP_C128 or _dtype_of(u) != MXP_C128:
+            raise ValueError("batched solves take complex128 tensors")
+    Parr = (ctypes.c_void_p * nprob)(*[p.handle.value for p in problems])
+    Narr = (ctypes.c_int32 * nprob)(*nrhs)
+    Farr = (ctypes.c_void_p * nprob)(*[_ptr(f) for f in f_list])
+    Uarr = (ctypes.c_void_p * nprob)(*[_ptr(u) for u in u_list])
+    Oarr = (mxp_solve_opts * nprob)(*opts)
+    total = sum(nrhs)
+    Sarr = (mxp_solve_stats * max(total, 1))()
+    status = _check(lib.mxp_solve_batch(ctx.handle, nprob, Parr, Narr, Farr, Uarr, Oarr, max_resident, Sarr),
+                    allow_not_converged=True)
+    return status, [Sarr[k].as_dict() for k in range(total)]
 
 
 def mxp_set_tiles(prob: Problem, precision: int, K: int, NX: int, Ly: int) -> None:

@@ -21,8 +21,11 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <condition_variable>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -105,6 +108,30 @@ struct TileCfg {
     double us_per_level = 0.0;
 };
 
+// Device workspace of one solve: Krylov bases, matrix-function buffers and
+// reduction scratch.  A problem owns one for its single-solve calls; a
+// batched solve gives every right-hand side its own.
+struct Workspace {
+    DevMem act64[8], act32[10];  // [0..5] pass/substep buffers, [6] psi addend, (f32) [7..8] casts
+    DevMem innerV, innerRh, innerTmp, innerRr;
+    DevMem outerV, outerZ, outerR;
+    DevMem partial, small;
+    std::vector<cpx<double>> host_small;
+};
+
+class Batcher;
+
+// One solve in progress: its problem (read-only while solving), workspace,
+// the stream its Krylov work runs on, and the batcher its matrix-function
+// actions go to (nullptr: run them directly on that stream).
+struct Run {
+    mxp_problem* P;
+    Workspace* W;
+    hipStream_t s;
+    Batcher* batch;
+    hipEvent_t ev;  // batched runs: marks the action input ready on s
+};
+
 }  // namespace mxp
 
 struct mxp_problem {
@@ -117,13 +144,8 @@ struct mxp_problem {
     std::map<std::tuple<double, double, int, int, int>, std::unique_ptr<mxp::Sched>> scheds;
     std::map<double, std::unique_ptr<mxp::DiagTables>> plain_diag;  // centre 0, keyed by shift
     double Dref = 0.0;  // reference value of D folded into the diagonal tables
-    // workspaces
-    mxp::DevMem act64[8], act32[10];  // [0..5] pass/substep buffers, [6] psi addend, (f32) [7..8] casts
-    mxp::TileCfg tiles[2];             // per precision (0 = double, 1 = float); K = 0 until tuned
-    mxp::DevMem innerV, innerRh, innerTmp, innerRr;
-    mxp::DevMem outerV, outerZ, outerR;
-    mxp::DevMem partial, small;
-    std::vector<mxp::cpx<double>> host_small;
+    mxp::TileCfg tiles[2];  // per precision (0 = double, 1 = float); K = 0 until tuned
+    mxp::Workspace ws;      // workspace of the single-solve calls
 };
 
 namespace mxp {
@@ -307,14 +329,51 @@ static cpx<R> to_cpx(cd v) { return {R(v.real()), R(v.imag())}; }
 
 static cd coef_at(const double* c, int k) { return cd(c[2 * k], c[2 * k + 1]); }
 
+// Where the launches of a matrix-function action go: straight onto a stream,
+// or into a list that a batched solve replays in lockstep with other actions.
+template <typename R>
+struct StepRec {
+    int kind;  // 0: stencil sweep (st); 1: temporally blocked 2D pass (cp, K, NX)
+    StencilArgs<R> st;
+    ChebPassArgs<R> cp;
+    int K, NX;
+};
+
+template <typename R>
+struct Emit {
+    hipStream_t s;
+    std::vector<StepRec<R>>* rec;  // non-null: record instead of launching
+    void sweep(const StencilArgs<R>& a) const {
+        if (rec) {
+            StepRec<R> r{};
+            r.kind = 0;
+            r.st = a;
+            rec->push_back(r);
+        } else {
+            launch_stencil(a, s);
+        }
+    }
+    void pass(const ChebPassArgs<R>& a, int K, int NX) const {
+        if (rec) {
+            StepRec<R> r{};
+            r.kind = 1;
+            r.cp = a;
+            r.K = K;
+            r.NX = NX;
+            rec->push_back(r);
+        } else {
+            launch_cheb2d<R>(a, K, NX, s);
+        }
+    }
+};
+
 // out = post * (sum_{k<=m} c_k T_k(Ahat) x + add), Ahat = (A_s - centre)/hw,
 // by the Clenshaw recurrence b_k = c_k x + 2 Ahat b_{k+1} - b_{k+2}.
 // bufA, bufB: scratch distinct from x, add and out.  out may equal x.
 template <typename R>
-static void cheb_series(mxp_problem* P, const StencilArgs<R>& base, const mxp_schedule& sc,
+static void cheb_series(const Emit<R>& em, const StencilArgs<R>& base, const mxp_schedule& sc,
                         const double* coef, int m, const cpx<R>* x, cpx<R>* out, cpx<R>* bufA,
                         cpx<R>* bufB, cd post, const cpx<R>* add, int64_t* steps) {
-    hipStream_t s = P->ctx->stream;
     const double hw = sc.half_width;
     StencilArgs<R> a = base;  // the centre is already folded into the diagonal tables
     a.x = x;
@@ -325,13 +384,13 @@ static void cheb_series(mxp_problem* P, const StencilArgs<R>& base, const mxp_sc
     a.b2 = nullptr;
     a.b3 = nullptr;
     a.out = bufA;
-    launch_stencil(a, s);
+    em.sweep(a);
     // b_{m-2} = c_{m-2} x + 2 Ahat b_{m-1} - c_m x
     a.b1 = bufA;
     a.g = to_cpx<R>(cd(2.0 / hw, 0.0));
     a.cx = to_cpx<R>(coef_at(coef, m - 2) - coef_at(coef, m));
     a.out = bufB;
-    launch_stencil(a, s);
+    em.sweep(a);
     cpx<R>* cur = bufB;   // b_{k+1}
     cpx<R>* prev = bufA;  // b_{k+2}
     for (int k = m - 3; k >= 1; --k) {
@@ -340,7 +399,7 @@ static void cheb_series(mxp_problem* P, const StencilArgs<R>& base, const mxp_sc
         a.e2 = {R(-1), R(0)};
         a.cx = to_cpx<R>(coef_at(coef, k));
         a.out = prev;
-        launch_stencil(a, s);
+        em.sweep(a);
         std::swap(cur, prev);
     }
     // out = post * (c_0 x + Ahat b_1 - b_2 + add)
@@ -352,13 +411,13 @@ static void cheb_series(mxp_problem* P, const StencilArgs<R>& base, const mxp_sc
     a.b3 = add;
     a.e3 = to_cpx<R>(post);
     a.out = out;
-    launch_stencil(a, s);
+    em.sweep(a);
     *steps += m;
 }
 
 template <typename R>
-static DevMem* act_buffers(mxp_problem* P) {
-    if constexpr (sizeof(R) == 8) return P->act64; else return P->act32;
+static DevMem* act_buffers(Workspace& W) {
+    if constexpr (sizeof(R) == 8) return W.act64; else return W.act32;
 }
 
 template <typename R>
@@ -389,7 +448,8 @@ static ChebPassArgs<R> pass_base(mxp_problem* P, const StencilArgs<R>& st, const
 // out = post * (sum_k c_k T_k(Ahat) x + add) by fused Clenshaw passes (2D).
 // bufs: four scratch vectors distinct from x, add and out.
 template <typename R>
-static void cheb_series_fused(mxp_problem* P, const StencilArgs<R>& st, const DiagTables& dt, const TileCfg& tc,
+static void cheb_series_fused(mxp_problem* P, const Emit<R>& em, const StencilArgs<R>& st, const DiagTables& dt,
+                              const TileCfg& tc,
                               const mxp_schedule& sc, const double* coef, int m, const cpx<R>* x,
                               cpx<R>* out, cpx<R>* const bufs[4], cd post, const cpx<R>* add,
                               int64_t* steps) {
@@ -426,7 +486,7 @@ static void cheb_series_fused(mxp_problem* P, const StencilArgs<R>& st, const Di
         a.outA = last ? nullptr : bufs[2 * pair];
         a.outB = last ? out : bufs[2 * pair + 1];
         cheb2d_geometry<R>(a, nlev, tc.NX, tc.Ly);
-        launch_cheb2d<R>(a, nlev, tc.NX, P->ctx->stream);
+        em.pass(a, nlev, tc.NX);
         prevA = a.outA;
         prevB = a.outB;
         pair ^= 1;
@@ -436,16 +496,16 @@ static void cheb_series_fused(mxp_problem* P, const StencilArgs<R>& st, const Di
 }
 
 template <typename R>
-static void tune_tiles(mxp_problem* P, const Sched& sd);
+static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s);
 
 // y = exp(i t A_s) x (psi = false) or psi_1(i t A_s) x (psi = true), precision R.
-// x and y distinct device vectors of precision R.
+// x and y distinct device vectors of precision R; buffers from workspace ws.
 template <typename R>
-static void action(mxp_problem* P, const Sched& sd, double t, double shift, bool psi,
-                   const cpx<R>* x, cpx<R>* y, int64_t* steps) {
+static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched& sd, double t, double shift,
+                   bool psi, const cpx<R>* x, cpx<R>* y, int64_t* steps) {
     const mxp_schedule& sc = sd.s;
     const int64_t n = npts(P);
-    DevMem* W = act_buffers<R>(P);
+    DevMem* W = act_buffers<R>(ws);
     for (int q = 0; q < 7; ++q) W[q].ensure(size_t(n) * sizeof(cpx<R>));
     cpx<R>* w[6];
     for (int q = 0; q < 6; ++q) w[q] = W[q].as<cpx<R>>();
@@ -455,7 +515,10 @@ static void action(mxp_problem* P, const Sched& sd, double t, double shift, bool
     TileCfg tc;
     if (fused) {
         TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
-        if (slot.K == 0) tune_tiles<R>(P, sd);
+        if (slot.K == 0) {
+            if (em.rec) fail(MXP_ERR_HIP, "tiles must be tuned before a batched action");
+            tune_tiles<R>(P, ws, sd, em.s);
+        }
         tc = slot;
     }
     const int S = sc.S;
@@ -475,10 +538,9 @@ static void action(mxp_problem* P, const Sched& sd, double t, double shift, bool
         cpx<R>* spare;
         pick(xin, b, &spare);
         if (fused) {
-            cheb_series_fused<R>(P, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
+            cheb_series_fused<R>(P, em, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
         } else {
-            // unfused: the final step writes in place over b_2 unless out is given
-            cheb_series<R>(P, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
+            cheb_series<R>(em, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
         }
     };
     auto substep_out = [&](const cpx<R>* xin) {
@@ -514,10 +576,9 @@ static void action(mxp_problem* P, const Sched& sd, double t, double shift, bool
 // own buffers (HIP events on the context stream) and keeps the fastest per
 // Clenshaw level.
 template <typename R>
-static void tune_tiles(mxp_problem* P, const Sched& sd) {
+static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s) {
     const int64_t n = npts(P);
-    hipStream_t s = P->ctx->stream;
-    DevMem* W = act_buffers<R>(P);
+    DevMem* W = act_buffers<R>(ws);
     for (int q = 0; q < 7; ++q) {
         W[q].ensure(size_t(n) * sizeof(cpx<R>));
         launch_zero<R>(W[q].as<cpx<R>>(), n, s);
@@ -589,46 +650,48 @@ struct Small {
     cpx<double>* y;
 };
 
-static Small small_buffers(mxp_problem* P) {
-    const int64_t n = npts(P);
+static Small small_buffers(Run& run) {
+    const int64_t n = npts(run.P);
     const int nb = reduce_blocks(n);
-    P->partial.ensure(size_t(nb) * 256 * sizeof(cpx<double>));
-    P->small.ensure(size_t(1024) * sizeof(cpx<double>));
-    P->host_small.resize(1024);
-    cpx<double>* sm = P->small.as<cpx<double>>();
-    return Small{P->partial.as<cpx<double>>(), sm, sm + 256, sm + 512, sm + 768};
+    Workspace& W = *run.W;
+    W.partial.ensure(size_t(nb) * 256 * sizeof(cpx<double>));
+    W.small.ensure(size_t(1024) * sizeof(cpx<double>));
+    W.host_small.resize(1024);
+    cpx<double>* sm = W.small.as<cpx<double>>();
+    return Small{W.partial.as<cpx<double>>(), sm, sm + 256, sm + 512, sm + 768};
 }
 
-static double norm2(mxp_problem* P, const cpx<double>* v) {
-    Small sm = small_buffers(P);
-    launch_nrm2sq(v, npts(P), sm.partial, sm.nrm, P->ctx->stream);
+static double norm2(Run& run, const cpx<double>* v) {
+    Small sm = small_buffers(run);
+    launch_nrm2sq(v, npts(run.P), sm.partial, sm.nrm, run.s);
     cpx<double> hv;
-    HIP_CHECK(hipMemcpyAsync(&hv, sm.nrm, sizeof(hv), hipMemcpyDeviceToHost, P->ctx->stream));
-    HIP_CHECK(hipStreamSynchronize(P->ctx->stream));
+    HIP_CHECK(hipMemcpyAsync(&hv, sm.nrm, sizeof(hv), hipMemcpyDeviceToHost, run.s));
+    HIP_CHECK(hipStreamSynchronize(run.s));
     if (!std::isfinite(hv.re)) fail(MXP_ERR_NONFINITE, "non-finite vector norm");
     return std::sqrt(hv.re);
 }
 
 // CGS2: orthogonalise w against V_0..V_{nv-1}; h receives the projection
 // coefficients and the returned value is ||w|| afterwards.
-static double cgs2(mxp_problem* P, const cpx<double>* V, int64_t ld, int nv, cpx<double>* w,
+static double cgs2(Run& run, const cpx<double>* V, int64_t ld, int nv, cpx<double>* w,
                    std::vector<cd>& h) {
-    const int64_t n = npts(P);
-    hipStream_t s = P->ctx->stream;
-    Small sm = small_buffers(P);
+    const int64_t n = npts(run.P);
+    hipStream_t s = run.s;
+    Small sm = small_buffers(run);
+    Workspace& W = *run.W;
     launch_mdot(V, ld, nv, w, n, sm.partial, sm.h1, s);
     launch_mupdate(w, V, ld, nv, sm.h1, n, s);
     launch_mdot(V, ld, nv, w, n, sm.partial, sm.h2, s);
     launch_mupdate(w, V, ld, nv, sm.h2, n, s);
     launch_nrm2sq(w, n, sm.partial, sm.nrm, s);
-    HIP_CHECK(hipMemcpyAsync(P->host_small.data(), P->small.p, 513 * sizeof(cpx<double>),
+    HIP_CHECK(hipMemcpyAsync(W.host_small.data(), W.small.p, 513 * sizeof(cpx<double>),
                              hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     h.resize(nv);
     for (int i = 0; i < nv; ++i)
-        h[i] = cd(P->host_small[i].re + P->host_small[256 + i].re,
-                  P->host_small[i].im + P->host_small[256 + i].im);
-    const double nn = P->host_small[512].re;
+        h[i] = cd(W.host_small[i].re + W.host_small[256 + i].re,
+                  W.host_small[i].im + W.host_small[256 + i].im);
+    const double nn = W.host_small[512].re;
     if (!std::isfinite(nn)) fail(MXP_ERR_NONFINITE, "non-finite value in the Arnoldi process");
     return std::sqrt(nn);
 }
@@ -689,30 +752,284 @@ struct Givens {
     }
 };
 
-static void upload_coeffs(mxp_problem* P, const std::vector<cd>& y) {
-    Small sm = small_buffers(P);
+static void upload_coeffs(Run& run, const std::vector<cd>& y) {
+    Small sm = small_buffers(run);
     std::vector<cpx<double>> tmp(y.size());
     for (size_t i = 0; i < y.size(); ++i) tmp[i] = {y[i].real(), y[i].imag()};
-    HIP_CHECK(hipMemcpyAsync(sm.y, tmp.data(), tmp.size() * sizeof(cpx<double>), hipMemcpyHostToDevice,
-                             P->ctx->stream));
-    HIP_CHECK(hipStreamSynchronize(P->ctx->stream));
+    HIP_CHECK(hipMemcpyAsync(sm.y, tmp.data(), tmp.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, run.s));
+    HIP_CHECK(hipStreamSynchronize(run.s));
 }
 
-// y = exp or psi_1 action on complex-double vectors, in the requested precision.
-static void action64(mxp_problem* P, const Sched& sc, double t, double shift, bool psi,
-                     mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps) {
+// y = exp or psi_1 action on complex-double vectors, in the requested
+// precision, enqueued on stream s with workspace ws, or recorded into
+// rec64 / rec32 when given (the caller then launches the records and, for
+// the mixed form, the cast back).  The mixed form casts at the boundary.
+static void action64_on(mxp_problem* P, Workspace& ws, hipStream_t s, const Sched& sc, double t, double shift,
+                        bool psi, mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps,
+                        std::vector<StepRec<double>>* rec64 = nullptr,
+                        std::vector<StepRec<float>>* rec32 = nullptr) {
     if (prec == MXP_PREC_FP64) {
-        action<double>(P, sc, t, shift, psi, x, y, steps);
+        action<double>(P, ws, Emit<double>{s, rec64}, sc, t, shift, psi, x, y, steps);
         return;
     }
     const int64_t n = npts(P);
-    P->act32[7].ensure(size_t(n) * sizeof(cpx<float>));
-    P->act32[8].ensure(size_t(n) * sizeof(cpx<float>));
-    cpx<float>* xs = P->act32[7].as<cpx<float>>();
-    cpx<float>* ys = P->act32[8].as<cpx<float>>();
-    launch_to_c64(x, xs, n, P->ctx->stream);
-    action<float>(P, sc, t, shift, psi, xs, ys, steps);
-    launch_to_c128(ys, y, n, P->ctx->stream);
+    ws.act32[7].ensure(size_t(n) * sizeof(cpx<float>));
+    ws.act32[8].ensure(size_t(n) * sizeof(cpx<float>));
+    cpx<float>* xs = ws.act32[7].as<cpx<float>>();
+    cpx<float>* ys = ws.act32[8].as<cpx<float>>();
+    launch_to_c64(x, xs, n, s);
+    action<float>(P, ws, Emit<float>{s, rec32}, sc, t, shift, psi, xs, ys, steps);
+    if (!rec32) launch_to_c128(ys, y, n, s);
+}
+
+static void action64(Run& run, const Sched& sc, double t, double shift, bool psi, mxp_precision prec,
+                     const cpx<double>* x, cpx<double>* y, int64_t* steps);
+
+// ------------------------------------------------------------ batched actions
+//
+// A batched solve runs every right-hand side's FGMRES in its own host thread
+// and HIP stream.  Each matrix-function action a thread needs becomes a
+// request; when every active thread has one pending, the requests run as one
+// lockstep action: step k of every request is launched before step k + 1 of
+// any, and the 3D sweeps of one step that share an operand set go out as a
+// single launch over all their grids (uneven sizes included).  The 2D
+// temporally blocked passes are launched per request within the same step.
+
+struct ActionReq {
+    Run* run;
+    const Sched* sd;
+    double t, shift;
+    bool psi;
+    mxp_precision prec;
+    const cpx<double>* x;
+    cpx<double>* y;
+    int64_t steps = 0;
+    bool done = false;
+    bool failed = false;
+    mxp_status status = MXP_OK;
+    std::string msg;
+};
+
+class Batcher {
+  public:
+    Batcher(int device, hipStream_t s) : device_(device), s_(s) {
+        HIP_CHECK(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
+    }
+    ~Batcher() {
+        (void)hipEventDestroy(done_);
+        if (host_) (void)hipHostFree(host_);
+    }
+    Batcher(const Batcher&) = delete;
+    Batcher& operator=(const Batcher&) = delete;
+
+    // A solve thread starts (before its first request) or ends (after its last).
+    void join() {
+        std::lock_guard<std::mutex> lk(mu_);
+        ++active_;
+    }
+    void leave() {
+        std::unique_lock<std::mutex> lk(mu_);
+        --active_;
+        maybe_run(lk);
+    }
+    // Blocks until the lockstep action holding r has been enqueued and has
+    // finished on the device.
+    void act(ActionReq& r) {
+        std::unique_lock<std::mutex> lk(mu_);
+        r.done = false;
+        pending_.push_back(&r);
+        maybe_run(lk);
+        cv_.wait(lk, [&] { return r.done; });
+        if (r.failed) fail(r.status, r.msg);
+    }
+    int64_t launches() const { return launches_; }
+
+  private:
+    void maybe_run(std::unique_lock<std::mutex>& lk) {
+        while (!running_ && active_ > 0 && int(pending_.size()) >= active_) {
+            std::vector<ActionReq*> batch;
+            batch.swap(pending_);
+            running_ = true;
+            lk.unlock();
+            try {
+                execute(batch);
+            } catch (const Error& e) {
+                for (ActionReq* q : batch) {
+                    q->failed = true;
+                    q->status = e.status;
+                    q->msg = e.what();
+                }
+            } catch (const std::exception& e) {
+                for (ActionReq* q : batch) {
+                    q->failed = true;
+                    q->status = MXP_ERR_HIP;
+                    q->msg = e.what();
+                }
+            }
+            lk.lock();
+            running_ = false;
+            for (ActionReq* q : batch) q->done = true;
+            cv_.notify_all();
+        }
+    }
+
+    struct Group {  // one batched 3D launch
+        int prec;   // 0 double, 1 float
+        int ops;
+        size_t jobs_off, lut_off;
+        int64_t blocks;
+    };
+
+    template <typename R>
+    static void add_jobs(std::vector<unsigned char>& buf, Group& g, const std::vector<const StencilArgs<R>*>& sw) {
+        // jobs, then the lookup table (one uint32 per 64 workgroups)
+        auto align = [&](size_t a) { buf.resize((buf.size() + a - 1) / a * a); };
+        align(256);
+        g.jobs_off = buf.size();
+        std::vector<Sweep3DJob<R>> jobs(sw.size());
+        int64_t b0 = 0;
+        for (size_t q = 0; q < sw.size(); ++q) {
+            jobs[q].a = *sw[q];
+            jobs[q].geom = sweep3d_geometry(*sw[q]);
+            jobs[q].block0 = b0;
+            jobs[q].blocks = int64_t(jobs[q].geom.tiles_x) * jobs[q].geom.tiles_y * jobs[q].geom.zchunks;
+            b0 += (jobs[q].blocks + 63) / 64 * 64;
+        }
+        g.blocks = b0;
+        const size_t jb = jobs.size() * sizeof(Sweep3DJob<R>);
+        buf.resize(buf.size() + jb);
+        std::memcpy(buf.data() + g.jobs_off, jobs.data(), jb);
+        align(256);
+        g.lut_off = buf.size();
+        std::vector<uint32_t> lut(size_t(b0 / 64));
+        for (size_t q = 0; q < jobs.size(); ++q)
+            for (int64_t c = jobs[q].block0 / 64; c < (jobs[q].block0 + jobs[q].blocks + 63) / 64; ++c)
+                lut[size_t(c)] = uint32_t(q);
+        buf.resize(buf.size() + lut.size() * sizeof(uint32_t));
+        std::memcpy(buf.data() + g.lut_off, lut.data(), lut.size() * sizeof(uint32_t));
+    }
+
+    void execute(std::vector<ActionReq*>& reqs) {
+        HIP_CHECK(hipSetDevice(device_));
+        const size_t nq = reqs.size();
+        // inputs are ready once each solve's stream reaches this point
+        for (ActionReq* q : reqs) {
+            HIP_CHECK(hipEventRecord(q->run->ev, q->run->s));
+            HIP_CHECK(hipStreamWaitEvent(s_, q->run->ev, 0));
+        }
+        std::vector<std::vector<StepRec<double>>> r64(nq);
+        std::vector<std::vector<StepRec<float>>> r32(nq);
+        size_t L = 0;
+        for (size_t i = 0; i < nq; ++i) {
+            ActionReq* q = reqs[i];
+            action64_on(q->run->P, *q->run->W, s_, *q->sd, q->t, q->shift, q->psi, q->prec, q->x, q->y, &q->steps,
+                        &r64[i], &r32[i]);
+            L = std::max(L, r64[i].size() + r32[i].size());
+        }
+        // plan: per step, the 3D sweeps grouped by precision and operand set
+        std::vector<unsigned char> buf;
+        std::vector<std::vector<Group>> plan(L);
+        for (size_t k = 0; k < L; ++k) {
+            std::map<int, std::vector<const StencilArgs<double>*>> g64;
+            std::map<int, std::vector<const StencilArgs<float>*>> g32;
+            for (size_t i = 0; i < nq; ++i) {
+                if (k < r64[i].size() && r64[i][k].kind == 0 && r64[i][k].st.dim == 3)
+                    g64[sweep_ops(r64[i][k].st)].push_back(&r64[i][k].st);
+                if (k < r32[i].size() && r32[i][k].kind == 0 && r32[i][k].st.dim == 3)
+                    g32[sweep_ops(r32[i][k].st)].push_back(&r32[i][k].st);
+            }
+            for (auto& kv : g64) {
+                Group g{0, kv.first, 0, 0, 0};
+                add_jobs<double>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+            for (auto& kv : g32) {
+                Group g{1, kv.first, 0, 0, 0};
+                add_jobs<float>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+        }
+        // one upload of every job table of this action
+        if (!buf.empty()) {
+            if (host_bytes_ < buf.size()) {
+                if (host_) HIP_CHECK(hipHostFree(host_));
+                host_ = nullptr;
+                host_bytes_ = 0;
+                HIP_CHECK(hipHostMalloc(&host_, buf.size()));
+                host_bytes_ = buf.size();
+            }
+            std::memcpy(host_, buf.data(), buf.size());
+            table_.ensure(buf.size());
+            HIP_CHECK(hipMemcpyAsync(table_.p, host_, buf.size(), hipMemcpyHostToDevice, s_));
+        }
+        const unsigned char* dev = table_.as<unsigned char>();
+        for (size_t k = 0; k < L; ++k) {
+            // launches that are not batched: 2D passes and 2D sweeps
+            for (size_t i = 0; i < nq; ++i) {
+                if (k < r64[i].size()) {
+                    const StepRec<double>& r = r64[i][k];
+                    if (r.kind == 1) launch_cheb2d<double>(r.cp, r.K, r.NX, s_);
+                    else if (r.st.dim != 3) launch_stencil(r.st, s_);
+                }
+                if (k < r32[i].size()) {
+                    const StepRec<float>& r = r32[i][k];
+                    if (r.kind == 1) launch_cheb2d<float>(r.cp, r.K, r.NX, s_);
+                    else if (r.st.dim != 3) launch_stencil(r.st, s_);
+                }
+            }
+            for (const Group& g : plan[k]) {
+                if (g.prec == 0)
+                    launch_stencil3d_batch<double>(reinterpret_cast<const Sweep3DJob<double>*>(dev + g.jobs_off),
+                                                   reinterpret_cast<const uint32_t*>(dev + g.lut_off), g.blocks,
+                                                   g.ops, s_);
+                else
+                    launch_stencil3d_batch<float>(reinterpret_cast<const Sweep3DJob<float>*>(dev + g.jobs_off),
+                                                  reinterpret_cast<const uint32_t*>(dev + g.lut_off), g.blocks,
+                                                  g.ops, s_);
+                ++launches_;
+            }
+        }
+        // mixed form: cast the results back
+        for (ActionReq* q : reqs)
+            if (q->prec != MXP_PREC_FP64)
+                launch_to_c128(q->run->W->act32[8].as<cpx<float>>(), q->y, npts(q->run->P), s_);
+        HIP_CHECK(hipEventRecord(done_, s_));
+        for (ActionReq* q : reqs) HIP_CHECK(hipStreamWaitEvent(q->run->s, done_, 0));
+        // the staging buffer and job tables are reused by the next action
+        HIP_CHECK(hipStreamSynchronize(s_));
+    }
+
+    std::mutex mu_;
+    std::condition_variable cv_;
+    int active_ = 0;
+    bool running_ = false;
+    std::vector<ActionReq*> pending_;
+    int device_;
+    hipStream_t s_;
+    hipEvent_t done_ = nullptr;
+    DevMem table_;
+    void* host_ = nullptr;
+    size_t host_bytes_ = 0;
+    int64_t launches_ = 0;
+};
+
+static void action64(Run& run, const Sched& sc, double t, double shift, bool psi, mxp_precision prec,
+                     const cpx<double>* x, cpx<double>* y, int64_t* steps) {
+    if (!run.batch) {
+        action64_on(run.P, *run.W, run.s, sc, t, shift, psi, prec, x, y, steps);
+        return;
+    }
+    ActionReq r;
+    r.run = &run;
+    r.sd = &sc;
+    r.t = t;
+    r.shift = shift;
+    r.psi = psi;
+    r.prec = prec;
+    r.x = x;
+    r.y = y;
+    run.batch->act(r);
+    *steps += r.steps;
 }
 
 struct Counters {
@@ -720,26 +1037,27 @@ struct Counters {
 };
 
 // Algorithm 1.  r, w: complex double device vectors.
-static int precond(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w,
-                   Counters& cnt) {
+static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt) {
+    mxp_problem* P = run.P;
+    Workspace& WS = *run.W;
     const int64_t n = npts(P);
-    hipStream_t s = P->ctx->stream;
+    hipStream_t s = run.s;
     const Sched& sc = get_sched(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
     const int m = o.inner_restart;
-    P->innerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
-    P->innerRh.ensure(size_t(n) * sizeof(cpx<double>));
-    P->innerTmp.ensure(size_t(n) * sizeof(cpx<double>));
-    P->innerRr.ensure(size_t(n) * sizeof(cpx<double>));
-    cpx<double>* V = P->innerV.as<cpx<double>>();
-    cpx<double>* rhat = P->innerRh.as<cpx<double>>();
-    cpx<double>* tmp = P->innerTmp.as<cpx<double>>();
-    cpx<double>* rr = P->innerRr.as<cpx<double>>();
+    WS.innerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
+    WS.innerRh.ensure(size_t(n) * sizeof(cpx<double>));
+    WS.innerTmp.ensure(size_t(n) * sizeof(cpx<double>));
+    WS.innerRr.ensure(size_t(n) * sizeof(cpx<double>));
+    cpx<double>* V = WS.innerV.as<cpx<double>>();
+    cpx<double>* rhat = WS.innerRh.as<cpx<double>>();
+    cpx<double>* tmp = WS.innerTmp.as<cpx<double>>();
+    cpx<double>* rr = WS.innerRr.as<cpx<double>>();
     const cpx<double> one{1.0, 0.0}, mone{-1.0, 0.0};
 
     // r_hat = psi_1(i t A_s) r; z = ||r_hat||
-    action64(P, sc, o.t, o.shift, true, o.precision, r, rhat, &cnt.steps);
+    action64(run, sc, o.t, o.shift, true, o.precision, r, rhat, &cnt.steps);
     cnt.actions++;
-    const double z = norm2(P, rhat);
+    const double z = norm2(run, rhat);
     launch_zero<double>(w, n, s);
     const double tol = o.fprtol * z;
     // Algorithm 1 tests the tolerance before the first inner iteration.
@@ -757,12 +1075,12 @@ static int precond(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* r
         for (int j = 0; j < m; ++j) {
             cpx<double>* vj = V + size_t(j) * n;
             cpx<double>* vn = V + size_t(j + 1) * n;
-            action64(P, sc, o.t, o.shift, false, o.precision, vj, tmp, &cnt.steps);
+            action64(run, sc, o.t, o.shift, false, o.precision, vj, tmp, &cnt.steps);
             cnt.actions++;
             // v_{j+1} <- v_j - exp(i t A_s) v_j
             launch_scale(one, vj, vn, n, s);
             launch_axpby(mone, tmp, one, vn, n, s);
-            const double hn = cgs2(P, V, n, j + 1, vn, h);
+            const double hn = cgs2(run, V, n, j + 1, vn, h);
             ++its;
             const double res = gv.add_column(j, h, hn);
             if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite inner residual estimate");
@@ -776,31 +1094,31 @@ static int precond(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* r
             if (its >= o.max_inner) break;
         }
         const std::vector<cd> y = gv.solve(k);
-        upload_coeffs(P, y);
-        launch_mcombine(w, V, n, k, small_buffers(P).y, n, s);
+        upload_coeffs(run, y);
+        launch_mcombine(w, V, n, k, small_buffers(run).y, n, s);
         if (conv || its >= o.max_inner) break;
         // restart: r = r_hat - (w - exp(i t A_s) w)
-        action64(P, sc, o.t, o.shift, false, o.precision, w, tmp, &cnt.steps);
+        action64(run, sc, o.t, o.shift, false, o.precision, w, tmp, &cnt.steps);
         cnt.actions++;
         launch_scale(one, rhat, rr, n, s);
         launch_axpby(mone, w, one, rr, n, s);
         launch_axpby(one, tmp, one, rr, n, s);
         rcur = rr;
-        beta = norm2(P, rr);
+        beta = norm2(run, rr);
         if (beta <= tol) break;
     }
     return its;
 }
 
-static void apply_A64(mxp_problem* P, double shift, const cpx<double>* x, cpx<double>* y, double g,
-                      const cpx<double>* add, double eadd) {
+static void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x, cpx<double>* y,
+                      double g, const cpx<double>* add, double eadd) {
     StencilArgs<double> a = base_args<double>(P, shift, plain_diag(P, shift));
     a.g = {g, 0.0};
     a.b1 = x;
     a.b2 = add;
     a.e2 = {eadd, 0.0};
     a.out = y;
-    launch_stencil(a, P->ctx->stream);
+    launch_stencil(a, s);
 }
 
 static void check_opts(const mxp_solve_opts* o) {
@@ -817,24 +1135,26 @@ static void check_opts(const mxp_solve_opts* o) {
     if (o->cheb_S < 0 || o->cheb_m < 0) fail(MXP_ERR_INVALID_ARG, "cheb_S, cheb_m must be >= 0");
 }
 
-static mxp_status solve(mxp_problem* P, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
+static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
                         mxp_solve_stats* st) {
     const auto t0 = std::chrono::steady_clock::now();
+    mxp_problem* P = run.P;
+    Workspace& WS = *run.W;
     const int64_t n = npts(P);
-    hipStream_t s = P->ctx->stream;
+    hipStream_t s = run.s;
     const int m = o.outer_restart;
-    P->outerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
-    P->outerZ.ensure(size_t(m) * n * sizeof(cpx<double>));
-    P->outerR.ensure(size_t(n) * sizeof(cpx<double>));
-    cpx<double>* V = P->outerV.as<cpx<double>>();
-    cpx<double>* Z = P->outerZ.as<cpx<double>>();
-    cpx<double>* r = P->outerR.as<cpx<double>>();
+    WS.outerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
+    WS.outerZ.ensure(size_t(m) * n * sizeof(cpx<double>));
+    WS.outerR.ensure(size_t(n) * sizeof(cpx<double>));
+    cpx<double>* V = WS.outerV.as<cpx<double>>();
+    cpx<double>* Z = WS.outerZ.as<cpx<double>>();
+    cpx<double>* r = WS.outerR.as<cpx<double>>();
     Counters cnt;
     std::vector<int> inner;
-    const double bnorm = norm2(P, f);
+    const double bnorm = norm2(run, f);
     // r = -f - A u
-    apply_A64(P, 0.0, u, r, -1.0, f, -1.0);
-    double beta = norm2(P, r);
+    apply_A64(P, s, 0.0, u, r, -1.0, f, -1.0);
+    double beta = norm2(run, r);
     int its = 0, cycles = 0;
     double relres = bnorm > 0 ? beta / bnorm : 0.0;
     Givens gv(m);
@@ -853,9 +1173,9 @@ static mxp_status solve(mxp_problem* P, const mxp_solve_opts& o, const cpx<doubl
             cpx<double>* vj = V + size_t(j) * n;
             cpx<double>* zj = Z + size_t(j) * n;
             cpx<double>* vn = V + size_t(j + 1) * n;
-            inner.push_back(precond(P, o, vj, zj, cnt));
-            apply_A64(P, 0.0, zj, vn, 1.0, nullptr, 0.0);
-            const double hn = cgs2(P, V, n, j + 1, vn, h);
+            inner.push_back(precond(run, o, vj, zj, cnt));
+            apply_A64(P, s, 0.0, zj, vn, 1.0, nullptr, 0.0);
+            const double hn = cgs2(run, V, n, j + 1, vn, h);
             ++its;
             const double res = gv.add_column(j, h, hn);
             if (P->ctx->verbose) {
@@ -875,10 +1195,10 @@ static mxp_status solve(mxp_problem* P, const mxp_solve_opts& o, const cpx<doubl
             if (its >= o.max_outer) break;
         }
         const std::vector<cd> y = gv.solve(k);
-        upload_coeffs(P, y);
-        launch_mcombine(u, Z, n, k, small_buffers(P).y, n, s);
-        apply_A64(P, 0.0, u, r, -1.0, f, -1.0);
-        beta = norm2(P, r);
+        upload_coeffs(run, y);
+        launch_mcombine(u, Z, n, k, small_buffers(run).y, n, s);
+        apply_A64(P, s, 0.0, u, r, -1.0, f, -1.0);
+        beta = norm2(run, r);
         relres = beta / bnorm;
         if ((est_ok && relres <= o.rtol) || its >= o.max_outer) break;
         if (relres <= o.rtol) break;
@@ -901,6 +1221,7 @@ static mxp_status solve(mxp_problem* P, const mxp_solve_opts& o, const cpx<doubl
         st->fn_actions = cnt.actions;
         st->true_relres = relres;
         st->restarts = std::max(0, cycles - 1);
+        st->status = relres <= o.rtol ? MXP_OK : MXP_NOT_CONVERGED;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return relres <= o.rtol ? MXP_OK : MXP_NOT_CONVERGED;
@@ -1052,8 +1373,8 @@ mxp_status mxp_apply_A(mxp_problem* prob, double shift, mxp_dtype dtype, const v
         if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
         if (!(shift >= 0) || !std::isfinite(shift)) fail(MXP_ERR_INVALID_ARG, "shift must be >= 0");
         if (dtype == MXP_C128) {
-            apply_A64(prob, shift, static_cast<const cpx<double>*>(x), static_cast<cpx<double>*>(y), 1.0,
-                      nullptr, 0.0);
+            apply_A64(prob, prob->ctx->stream, shift, static_cast<const cpx<double>*>(x),
+                      static_cast<cpx<double>*>(y), 1.0, nullptr, 0.0);
         } else if (dtype == MXP_C64) {
             StencilArgs<float> a = base_args<float>(prob, shift, plain_diag(prob, shift));
             a.b1 = static_cast<const cpx<float>*>(x);
@@ -1075,12 +1396,12 @@ static mxp_status apply_fn(mxp_problem* prob, double t, double shift, mxp_dtype 
         int64_t steps = 0;
         if (dtype == MXP_C128) {
             const Sched& sc = get_sched(prob, t, shift, MXP_PREC_FP64, 0, 0);
-            action<double>(prob, sc, t, shift, psi, static_cast<const cpx<double>*>(x),
-                           static_cast<cpx<double>*>(y), &steps);
+            action<double>(prob, prob->ws, Emit<double>{prob->ctx->stream, nullptr}, sc, t, shift, psi,
+                           static_cast<const cpx<double>*>(x), static_cast<cpx<double>*>(y), &steps);
         } else if (dtype == MXP_C64) {
             const Sched& sc = get_sched(prob, t, shift, MXP_PREC_MIXED, 0, 0);
-            action<float>(prob, sc, t, shift, psi, static_cast<const cpx<float>*>(x),
-                          static_cast<cpx<float>*>(y), &steps);
+            action<float>(prob, prob->ws, Emit<float>{prob->ctx->stream, nullptr}, sc, t, shift, psi,
+                          static_cast<const cpx<float>*>(x), static_cast<cpx<float>*>(y), &steps);
         } else {
             fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
         }
@@ -1106,8 +1427,8 @@ mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, cons
         check_opts(opts);
         if (!r || !w || r == w) fail(MXP_ERR_INVALID_ARG, "r and w must be distinct non-NULL pointers");
         Counters cnt;
-        const int its = precond(prob, *opts, static_cast<const cpx<double>*>(r), static_cast<cpx<double>*>(w),
-                                cnt);
+        Run run{prob, &prob->ws, prob->ctx->stream, nullptr, nullptr};
+        const int its = precond(run, *opts, static_cast<const cpx<double>*>(r), static_cast<cpx<double>*>(w), cnt);
         HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
         if (inner_its) *inner_its = its;
         return MXP_OK;
@@ -1149,7 +1470,128 @@ mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* 
         check_problem(prob);
         check_opts(opts);
         if (!f || !u || f == u) fail(MXP_ERR_INVALID_ARG, "f and u must be distinct non-NULL pointers");
-        return solve(prob, *opts, static_cast<const cpx<double>*>(f), static_cast<cpx<double>*>(u), stats);
+        Run run{prob, &prob->ws, prob->ctx->stream, nullptr, nullptr};
+        return solve(run, *opts, static_cast<const cpx<double>*>(f), static_cast<cpx<double>*>(u), stats);
+    });
+}
+
+mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* problems, const int32_t* nrhs,
+                           const void* const* f, void* const* u, const mxp_solve_opts* opts, int32_t max_resident,
+                           mxp_solve_stats* stats) {
+    return guard([&]() -> mxp_status {
+        if (!ctx || nprob < 1 || !problems || !nrhs || !f || !u || !opts)
+            fail(MXP_ERR_INVALID_ARG, "batch: context, problem, rhs and option arrays must be given");
+        if (max_resident < 0) fail(MXP_ERR_INVALID_ARG, "max_resident must be >= 0");
+        use_device(ctx);
+        struct Item {
+            mxp_problem* P;
+            const mxp_solve_opts* o;
+            const cpx<double>* f;
+            cpx<double>* u;
+            size_t bytes;
+        };
+        std::vector<Item> items;
+        for (int q = 0; q < nprob; ++q) {
+            mxp_problem* P = problems[q];
+            if (!P) fail(MXP_ERR_INVALID_ARG, "batch: problem is NULL");
+            if (P->ctx->device != ctx->device) fail(MXP_ERR_INVALID_ARG, "batch: problem on another device");
+            check_opts(&opts[q]);
+            if (nrhs[q] < 0) fail(MXP_ERR_INVALID_ARG, "batch: nrhs must be >= 0");
+            if (nrhs[q] == 0) continue;
+            if (!f[q] || !u[q] || f[q] == u[q]) fail(MXP_ERR_INVALID_ARG, "batch: f and u must be distinct non-NULL");
+            const mxp_solve_opts& o = opts[q];
+            const int64_t n = npts(P);
+            // everything the right-hand side's solve allocates (workspace estimate)
+            const size_t vec = size_t(n) * sizeof(cpx<double>);
+            size_t bytes = vec * (size_t(2 * o.outer_restart + 2) + size_t(o.inner_restart + 4));
+            bytes += o.precision == MXP_PREC_FP64 ? 7 * vec : 9 * vec / 2;
+            bytes += size_t(reduce_blocks(n)) * 256 * sizeof(cpx<double>) + (1 << 20);
+            // set up once, outside the threads: schedules, diagonal tables and
+            // 2D tiles are shared read-only by every right-hand side of P
+            const Sched& sd = get_sched(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
+            (void)plain_diag(P, 0.0);
+            if (P->g.dim == 2) {
+                if (o.precision == MXP_PREC_FP64 && P->tiles[0].K == 0)
+                    tune_tiles<double>(P, P->ws, sd, P->ctx->stream);
+                if (o.precision == MXP_PREC_MIXED && P->tiles[1].K == 0)
+                    tune_tiles<float>(P, P->ws, sd, P->ctx->stream);
+            }
+            for (int r = 0; r < nrhs[q]; ++r)
+                items.push_back({P, &o, static_cast<const cpx<double>*>(f[q]) + size_t(r) * n,
+                                 static_cast<cpx<double>*>(u[q]) + size_t(r) * n, bytes});
+        }
+        HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        size_t free_b = 0, total_b = 0;
+        HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+        const size_t budget = free_b > (size_t(2) << 30) ? free_b - (size_t(2) << 30) : free_b / 2;
+        const int cap = max_resident > 0 ? max_resident : int(items.size());
+
+        Batcher B(ctx->device, ctx->stream);
+        std::mutex mu;
+        std::condition_variable cv;
+        int running = 0;
+        size_t running_bytes = 0;
+        std::vector<mxp_status> status(items.size(), MXP_OK);
+        std::vector<std::string> msgs(items.size());
+        std::vector<std::thread> threads;
+        const int dev = ctx->device;
+        for (size_t k = 0; k < items.size(); ++k) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] {
+                    return running == 0 || (running < cap && running_bytes + items[k].bytes <= budget);
+                });
+                ++running;
+                running_bytes += items[k].bytes;
+            }
+            B.join();
+            threads.emplace_back([&, k, dev]() {
+                const Item& it = items[k];
+                try {
+                    HIP_CHECK(hipSetDevice(dev));
+                    Workspace W;
+                    hipStream_t s = nullptr;
+                    hipEvent_t ev = nullptr;
+                    HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+                    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                        (void)hipStreamDestroy(s);
+                        fail(MXP_ERR_HIP, "event creation failed");
+                    }
+                    Run run{it.P, &W, s, &B, ev};
+                    try {
+                        status[k] = solve(run, *it.o, it.f, it.u, stats ? &stats[k] : nullptr);
+                    } catch (...) {
+                        (void)hipStreamSynchronize(s);
+                        (void)hipEventDestroy(ev);
+                        (void)hipStreamDestroy(s);
+                        throw;
+                    }
+                    (void)hipEventDestroy(ev);
+                    (void)hipStreamDestroy(s);
+                } catch (const Error& e) {
+                    status[k] = e.status;
+                    msgs[k] = e.what();
+                } catch (const std::exception& e) {
+                    status[k] = MXP_ERR_HIP;
+                    msgs[k] = e.what();
+                }
+                if (stats && status[k] < 0) stats[k].status = status[k];
+                B.leave();
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    --running;
+                    running_bytes -= it.bytes;
+                }
+                cv.notify_all();
+            });
+        }
+        for (auto& th : threads) th.join();
+        mxp_status worst = MXP_OK;
+        for (size_t k = 0; k < items.size(); ++k) {
+            if (status[k] < 0) fail(status[k], "batch right-hand side " + std::to_string(k) + ": " + msgs[k]);
+            if (status[k] == MXP_NOT_CONVERGED) worst = MXP_NOT_CONVERGED;
+        }
+        return worst;
     });
 }
 

@@ -51,6 +51,33 @@ struct StencilArgs {
 template <typename R>
 void launch_stencil(const StencilArgs<R>& a, hipStream_t s);
 
+// Geometry of the 3D sweep: 64 x 4 column tiles, chunks of zc planes.
+struct Sweep3DGeom {
+    int tiles_x, tiles_y, zchunks, zc;
+};
+template <typename R>
+Sweep3DGeom sweep3d_geometry(const StencilArgs<R>& a);
+// Operands present in a sweep: 1 x, 2 b2, 4 b3, 8 D.
+template <typename R>
+int sweep_ops(const StencilArgs<R>& a) {
+    return (a.x ? 1 : 0) | (a.b2 ? 2 : 0) | (a.b3 ? 4 : 0) | (a.D ? 8 : 0);
+}
+
+// One 3D sweep inside a batched launch over grids of different sizes.  Job q
+// owns workgroups [block0, block0 + blocks); block0 is a multiple of 64 and
+// lut[b / 64] (uint32) names the job of workgroup b.
+template <typename R>
+struct Sweep3DJob {
+    StencilArgs<R> a;
+    Sweep3DGeom geom;
+    int64_t block0, blocks;
+};
+// jobs, lut: device arrays; every job has operand set `ops`; total_blocks
+// covers the last job's padded range.
+template <typename R>
+void launch_stencil3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut, int64_t total_blocks, int ops,
+                            hipStream_t s);
+
 // One temporally blocked Clenshaw pass on a 2D grid (vectors below 4 GiB):
 // K consecutive levels
 //   L_l = cx_l x + g_l S(L_{l-1}) - L_{l-2}

@@ -37,9 +37,6 @@ __device__ __forceinline__ cpx<R> cscale(R s, cpx<R> a) {
 constexpr int kBX = 64;
 constexpr int kBY = 4;
 
-struct March3D {
-    int tiles_x, tiles_y, zchunks, zc;
-};
 
 // 2D sweep: one work-item per node, 64 x 4 workgroups.
 template <typename R, int DIM>
@@ -86,6 +83,49 @@ __device__ __forceinline__ cpx<R> sload(const cpx<R>* p, int64_t idx) {
     return {q[2 * idx], q[2 * idx + 1]};
 }
 
+// Loads and stores through the global address space.  Pointers read from
+// memory (the batched job table) are generic to the compiler, which would
+// otherwise emit flat accesses that also count against the LDS counter.
+template <typename R>
+struct vec2_of;
+template <>
+struct vec2_of<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct vec2_of<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <typename R>
+__device__ __forceinline__ cpx<R> gload(const cpx<R>* p, int64_t i) {
+    typedef typename vec2_of<R>::type V;
+    const V v = ((const __attribute__((address_space(1))) V*)(p))[i];
+    return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ R gload(const R* p, int64_t i) {
+    return ((const __attribute__((address_space(1))) R*)(p))[i];
+}
+template <typename R>
+__device__ __forceinline__ void gstore(cpx<R>* p, int64_t i, cpx<R> c) {
+    typedef typename vec2_of<R>::type V;
+    V v;
+    v.x = c.re;
+    v.y = c.im;
+    ((__attribute__((address_space(1))) V*)(p))[i] = v;
+}
+
+// A whole uniform struct through the scalar cache, one dword at a time.
+template <class T>
+__device__ __forceinline__ T sload_words(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized struct expected");
+    const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)(p);
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = q[i];
+    return __builtin_bit_cast(T, w);
+}
+
 // 3D sweep marching along z.  A workgroup owns a 64 x 4 column tile and a
 // chunk of zc planes.  Each work-item carries v at planes k-1 and k in
 // registers and loads plane k+1, so v is fetched about once per chunk and
@@ -99,10 +139,8 @@ __device__ __forceinline__ cpx<R> sload(const cpx<R>* p, int64_t idx) {
 // (at most four wavefronts per SIMD: with the default target of eight the
 // compiler serialises the complex-double loads to save registers)
 template <typename R, int OPS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_stencil3d(StencilArgs<R> a,
-                                                                                             March3D m) {
+__device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGeom& m, int tile) {
     constexpr bool HX = OPS & 1, H2 = OPS & 2, H3 = OPS & 4, HD = OPS & 8;
-    const int tile = blockIdx.x;
     const int tx = tile % m.tiles_x;
     const int rest = tile / m.tiles_x;
     const int ty = rest % m.tiles_y;
@@ -118,25 +156,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const cpx<R> zero{R(0), R(0)};
     const int64_t oxm = i > 0 ? -1 : 0, oxp = i < a.n0 - 1 ? 1 : 0;
     const int64_t oym = j > 0 ? -sy : 0, oyp = j < a.n1 - 1 ? sy : 0;
-    const cpx<R> wxm = keep_if(i > 0, a.alpha[0][i]);
-    const cpx<R> wxp = keep_if(i < a.n0 - 1, a.beta[0][i]);
-    const cpx<R> wym = keep_if(j > 0, a.alpha[1][j]);
-    const cpx<R> wyp = keep_if(j < a.n1 - 1, a.beta[1][j]);
-    const cpx<R> gxy = cadd(a.gamma[0][i], a.gamma[1][j]);
+    const cpx<R> wxm = keep_if(i > 0, gload(a.alpha[0], i));
+    const cpx<R> wxp = keep_if(i < a.n0 - 1, gload(a.beta[0], i));
+    const cpx<R> wym = keep_if(j > 0, gload(a.alpha[1], j));
+    const cpx<R> wyp = keep_if(j < a.n1 - 1, gload(a.beta[1], j));
+    const cpx<R> gxy = cadd(gload(a.gamma[0], i), gload(a.gamma[1], j));
     int64_t p = i + sy * j + sz * z0;
-    cpx<R> vm = v[z0 > 0 ? p - sz : p];
+    cpx<R> vm = gload(v, z0 > 0 ? p - sz : p);
     if (z0 == 0) vm = zero;
-    cpx<R> vc = v[p];
+    cpx<R> vc = gload(v, p);
     for (int64_t k = z0; k < z1; ++k, p += sz) {
         const bool up = k + 1 < a.n2;
-        cpx<R> vp = v[up ? p + sz : p];
-        const cpx<R> vxm = v[p + oxm], vxp = v[p + oxp], vym = v[p + oym], vyp = v[p + oyp];
+        cpx<R> vp = gload(v, up ? p + sz : p);
+        const cpx<R> vxm = gload(v, p + oxm), vxp = gload(v, p + oxp);
+        const cpx<R> vym = gload(v, p + oym), vyp = gload(v, p + oyp);
         R Draw = a.Dconst;
-        if constexpr (HD) Draw = a.D[p];
+        if constexpr (HD) Draw = gload(a.D, p);
         cpx<R> xv = zero, b2v = zero, b3v = zero;
-        if constexpr (HX) xv = a.x[p];
-        if constexpr (H2) b2v = a.b2[p];
-        if constexpr (H3) b3v = a.b3[p];
+        if constexpr (HX) xv = gload(a.x, p);
+        if constexpr (H2) b2v = gload(a.b2, p);
+        if constexpr (H3) b3v = gload(a.b3, p);
         vp = keep_if(up, vp);
         cpx<R> diag = cadd(gxy, sload(a.gamma[2], k));
         diag = cadd(diag, cscale(Draw - a.Dref, a.kD));
@@ -151,21 +190,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         if constexpr (HX) o = cfma(a.cx, xv, o);
         if constexpr (H2) o = cfma(a.e2, b2v, o);
         if constexpr (H3) o = cfma(a.e3, b3v, o);
-        a.out[p] = o;
+        gstore(a.out, p, o);
         vm = vc;
         vc = vp;
     }
 }
 
 template <typename R, int OPS>
-void launch_3d_ops(const StencilArgs<R>& a, const March3D& m, unsigned nb, hipStream_t s) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_stencil3d(StencilArgs<R> a,
+                                                                                             Sweep3DGeom m) {
+    sweep3d<R, OPS>(a, m, blockIdx.x);
+}
+
+// Batched form: the job of a workgroup comes from a lookup table with one
+// entry per 64 workgroups, and its description is read through the scalar
+// cache (uniform across the workgroup).
+template <typename R, int OPS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_stencil3d_batch(
+    const Sweep3DJob<R>* jobs, const uint32_t* lut) {
+    const int b = blockIdx.x;
+    const __attribute__((address_space(4))) uint32_t* lq = (const __attribute__((address_space(4))) uint32_t*)(lut);
+    const int q = lq[b >> 6];
+    const Sweep3DJob<R> job = sload_words(jobs + q);
+    const int64_t local = int64_t(b) - job.block0;
+    if (local >= job.blocks) return;
+    sweep3d<R, OPS>(job.a, job.geom, int(local));
+}
+
+template <typename R, int OPS>
+void launch_3d_ops(const StencilArgs<R>& a, const Sweep3DGeom& m, unsigned nb, hipStream_t s) {
     hipLaunchKernelGGL((k_stencil3d<R, OPS>), dim3(nb), dim3(kBX, kBY, 1), 0, s, a, m);
 }
 
 template <typename R, int... OPS>
-void launch_3d(const StencilArgs<R>& a, const March3D& m, unsigned nb, int ops, hipStream_t s,
+void launch_3d(const StencilArgs<R>& a, const Sweep3DGeom& m, unsigned nb, int ops, hipStream_t s,
                std::integer_sequence<int, OPS...>) {
     ((ops == OPS ? launch_3d_ops<R, OPS>(a, m, nb, s) : void()), ...);
+}
+
+template <typename R, int OPS>
+void launch_3d_batch_ops(const Sweep3DJob<R>* jobs, const uint32_t* lut, unsigned nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_stencil3d_batch<R, OPS>), dim3(nb), dim3(kBX, kBY, 1), 0, s, jobs, lut);
+}
+
+template <typename R, int... OPS>
+void launch_3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut, unsigned nb, int ops, hipStream_t s,
+                     std::integer_sequence<int, OPS...>) {
+    ((ops == OPS ? launch_3d_batch_ops<R, OPS>(jobs, lut, nb, s) : void()), ...);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -324,15 +395,10 @@ template <typename R>
 void launch_stencil(const StencilArgs<R>& a, hipStream_t s) {
     const dim3 block(kBX, kBY, 1);
     if (a.dim == 3) {
-        March3D m;
-        m.tiles_x = int((a.n0 + kBX - 1) / kBX);
-        m.tiles_y = int((a.n1 + kBY - 1) / kBY);
-        m.zc = 8;
-        m.zchunks = int((a.n2 + m.zc - 1) / m.zc);
+        const Sweep3DGeom m = sweep3d_geometry(a);
         const int64_t nb = int64_t(m.tiles_x) * m.tiles_y * m.zchunks;
         if (nb > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "grid too large for the 3D sweep");
-        const int ops = (a.x ? 1 : 0) | (a.b2 ? 2 : 0) | (a.b3 ? 4 : 0) | (a.D ? 8 : 0);
-        launch_3d<R>(a, m, unsigned(nb), ops, s, std::make_integer_sequence<int, 16>{});
+        launch_3d<R>(a, m, unsigned(nb), sweep_ops(a), s, std::make_integer_sequence<int, 16>{});
     } else {
         const dim3 grid(unsigned((a.n0 + kBX - 1) / kBX), unsigned((a.n1 + kBY - 1) / kBY), 1);
         hipLaunchKernelGGL((k_stencil<R, 2>), grid, block, 0, s, a);
@@ -340,6 +406,29 @@ void launch_stencil(const StencilArgs<R>& a, hipStream_t s) {
     check_launch("stencil");
 }
 template void launch_stencil<double>(const StencilArgs<double>&, hipStream_t);
+
+template <typename R>
+Sweep3DGeom sweep3d_geometry(const StencilArgs<R>& a) {
+    Sweep3DGeom m;
+    m.tiles_x = int((a.n0 + kBX - 1) / kBX);
+    m.tiles_y = int((a.n1 + kBY - 1) / kBY);
+    m.zc = 8;
+    m.zchunks = int((a.n2 + m.zc - 1) / m.zc);
+    return m;
+}
+template Sweep3DGeom sweep3d_geometry<double>(const StencilArgs<double>&);
+template Sweep3DGeom sweep3d_geometry<float>(const StencilArgs<float>&);
+
+template <typename R>
+void launch_stencil3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut, int64_t total_blocks, int ops,
+                            hipStream_t s) {
+    if (total_blocks <= 0) return;
+    if (total_blocks > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "batched 3D sweep too large");
+    launch_3d_batch<R>(jobs, lut, unsigned(total_blocks), ops, s, std::make_integer_sequence<int, 16>{});
+    check_launch("batched 3D sweep");
+}
+template void launch_stencil3d_batch<double>(const Sweep3DJob<double>*, const uint32_t*, int64_t, int, hipStream_t);
+template void launch_stencil3d_batch<float>(const Sweep3DJob<float>*, const uint32_t*, int64_t, int, hipStream_t);
 template void launch_stencil<float>(const StencilArgs<float>&, hipStream_t);
 
 int reduce_blocks(int64_t n) {

@@ -23,7 +23,7 @@ import numpy as np
 __all__ = [
     "Problem", "config1", "config2", "config3", "config4_main", "config4_extras",
     "small_problem", "delta_source", "gaussian_source", "grf_speed",
-    "layered_speed", "random_vector",
+    "layered_speed", "random_vector", "config4_sources",
 ]
 
 
@@ -184,6 +184,19 @@ def config4_extras(count: int = 16, seed: int = 44):
         h = 1.0 / (max(n) - 1)
         c = layered_speed(n, 16, 12, 1500.0, 4500.0, 2, seed * 1000 + i)
         out.append(Problem(f"3d-layered-{n[0]}x{n[1]}x{n[2]}", n, h, omega_for(8, h), 16, c))
+    return out
+
+
+def config4_sources(prob: Problem, which, count: int = 32) -> np.ndarray:
+    """Right-hand sides `which` (indices into the line of `count`) of the
+    layered batch: discrete deltas at depth z = L + 2, y at the centre, x
+    equally spaced over the inner region.  Returns (len(which), npts)."""
+    n0, n1, n2 = prob.n
+    L = prob.layer
+    xs = np.linspace(L, n0 - 1 - L, count).round().astype(int)
+    out = np.zeros((len(which), prob.npts), dtype=np.complex128)
+    for k, w in enumerate(which):
+        out[k] = delta_source(prob, (int(xs[w]), n1 // 2, L + 2)).ravel()
     return out
 
 
