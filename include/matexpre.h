@@ -141,6 +141,9 @@ typedef struct {
     mxp_precision precision;
     int32_t cheb_S;         /* > 0 forces the number of Chebyshev substeps (0 = designed) */
     int32_t cheb_m;         /* > 0 forces the series degree per substep    (0 = designed) */
+    int32_t use_learned;    /* 1: learned network first at every outer iteration (see below) */
+    double stall_ratio;     /* learned z_j kept if the residual estimate drops below this
+                               factor times the previous one; default 0.9, in (0, 1] */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per
@@ -160,6 +163,8 @@ typedef struct {
     double seconds;           /* wall time of the call                            */
     int32_t restarts;         /* outer restart cycles after the first             */
     int32_t status;           /* this solve's outcome (mxp_status)                */
+    int32_t learned_its;      /* outer iterations preconditioned by the network   */
+    int32_t fallbacks;        /* network tries rejected (MatExPre used instead)   */
 } mxp_solve_stats;
 
 /* --------------------------------------------------------------- schedule */
@@ -260,6 +265,69 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
                            const int32_t* nrhs, const void* const* f, void* const* u,
                            const mxp_solve_opts* opts, int32_t max_resident,
                            mxp_solve_stats* stats);
+
+/* --------------------------------------------------------- learned stage */
+/* Not in the paper: a small convolutional network trained on (residual,
+ * MatExPre-preconditioned residual) pairs that the method generates, tried
+ * as the flexible-GMRES preconditioner before MatExPre at every outer
+ * iteration.  Network: six 3x3x3 convolutions with zero padding, channels
+ * 3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 2, bias on every layer, ReLU after the
+ * first five; bf16 weights and activations, float accumulation on the
+ * matrix cores.  Parameters (float) are flattened layer by layer as
+ * W[cout][cin][3][3][3] (taps dz, dy, dx with dx fastest) then b[cout].
+ * Network tensors are channels-last: input bf16 [voxel][8] (channels Re r,
+ * Im r, 1/c^2, then zeros), output float [voxel][2] (Re, Im); a shape is nb
+ * volumes of nz x ny x nx voxels, x fastest, each zero-padded on its own.
+ * Every pointer below is device memory unless marked host. */
+typedef struct mxp_cnn mxp_cnn;
+
+/* Number of network parameters. */
+int64_t mxp_cnn_num_params(void);
+/* New network on the context's device and stream, He-normal weights from
+ * the seed, zero biases.  Errors: INVALID_ARG, OOM, HIP. */
+mxp_status mxp_cnn_create(mxp_context* ctx, uint64_t seed, mxp_cnn** out);
+void mxp_cnn_destroy(mxp_cnn* net);
+/* Copy the parameters / the last computed gradients to host memory, or set
+ * the parameters from host memory (resets the Adam state).  Errors:
+ * INVALID_ARG, NONFINITE (set), HIP. */
+mxp_status mxp_cnn_get_params(const mxp_cnn* net, float* host);
+mxp_status mxp_cnn_set_params(mxp_cnn* net, const float* host);
+mxp_status mxp_cnn_get_grads(const mxp_cnn* net, float* host);
+/* out = network(in). */
+mxp_status mxp_cnn_forward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
+                           float* out);
+/* Parameter gradients of sum(gout * network(in)), gout float [voxel][2];
+ * read them with mxp_cnn_get_grads. */
+mxp_status mxp_cnn_backward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
+                            const float* gout);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error
+ * of network(in) against target (float [voxel][2]); *loss (host, may be NULL)
+ * receives the loss before the step.  Errors: INVALID_ARG, NONFINITE, HIP. */
+mxp_status mxp_cnn_train_step(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
+                              const float* target, float lr, double* loss);
+/* Training sample from a pair on the problem's grid: the crop of crop[0..2]
+ * nodes (x, y, z) at offset[0..2]; in (bf16 [crop][8]) = (r * rscale, 1/c^2),
+ * target (float [crop][2]) = z * zscale.  r, z: complex double [size].
+ * Errors: INVALID_ARG (crop outside the grid). */
+mxp_status mxp_cnn_make_sample(mxp_problem* prob, const void* r, const void* z, const int32_t offset[3],
+                               const int32_t crop[3], double rscale, double zscale, void* in, float* target);
+/* mxp_solve that also copies, for each outer iteration, the unit Krylov
+ * vector v_j and its preconditioned vector z_j = M(v_j) (Algorithm 1) into
+ * r_out / z_out (max_pairs complex double vectors each) with their norms in
+ * rnorm / znorm (host); *npairs receives the count.  Returns as mxp_solve. */
+mxp_status mxp_collect_pairs(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
+                             int32_t max_pairs, void* r_out, void* z_out, double* rnorm, double* znorm,
+                             int32_t* npairs, mxp_solve_stats* stats);
+/* Attaches a network (not owned; NULL detaches) to a problem for solves with
+ * opts.use_learned = 1.  The network sees v_j scaled to unit root-mean-square
+ * value and its output, scaled back, is multiplied by out_scale (the typical
+ * ||M(v)|| / ||v|| of the training pairs).  At each outer iteration z_j =
+ * network(v_j) is kept if the Arnoldi residual estimate falls below
+ * stall_ratio times the previous one; otherwise z_j = M(v_j) from MatExPre
+ * (a fallback), and after two fallbacks in a row MatExPre alone finishes the
+ * solve.  Convergence is judged by the complex-double true residual as
+ * always.  Single solves only (mxp_solve_batch rejects use_learned). */
+mxp_status mxp_problem_set_learned(mxp_problem* prob, mxp_cnn* net, double out_scale);
 
 #ifdef __cplusplus
 }

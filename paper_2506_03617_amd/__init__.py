@@ -66,6 +66,8 @@ class mxp_solve_opts(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("cheb_S", ctypes.c_int32),
         ("cheb_m", ctypes.c_int32),
+        ("use_learned", ctypes.c_int32),
+        ("stall_ratio", ctypes.c_double),
     ]
 
 
@@ -81,6 +83,8 @@ class mxp_solve_stats(ctypes.Structure):
         ("seconds", ctypes.c_double),
         ("restarts", ctypes.c_int32),
         ("status", ctypes.c_int32),
+        ("learned_its", ctypes.c_int32),
+        ("fallbacks", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -118,6 +122,9 @@ ABI_SYMBOLS = (
     "mxp_solve_opts_default", "mxp_design_schedule",
     "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_precond", "mxp_solve",
     "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
+    "mxp_cnn_num_params", "mxp_cnn_create", "mxp_cnn_destroy", "mxp_cnn_get_params", "mxp_cnn_set_params",
+    "mxp_cnn_get_grads", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
+    "mxp_collect_pairs", "mxp_problem_set_learned",
 )
 
 
@@ -149,6 +156,22 @@ def _load():
         "mxp_solve_batch": (st, [P, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(mxp_solve_opts),
                                  ctypes.c_int32, ctypes.POINTER(mxp_solve_stats)]),
+        "mxp_cnn_num_params": (ctypes.c_int64, []),
+        "mxp_cnn_create": (st, [P, ctypes.c_uint64, ctypes.POINTER(P)]),
+        "mxp_cnn_destroy": (None, [P]),
+        "mxp_cnn_get_params": (st, [P, P]),
+        "mxp_cnn_set_params": (st, [P, P]),
+        "mxp_cnn_get_grads": (st, [P, P]),
+        "mxp_cnn_forward": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]),
+        "mxp_cnn_backward": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]),
+        "mxp_cnn_train_step": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
+                                    ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
+        "mxp_cnn_make_sample": (st, [P, P, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.c_double, ctypes.c_double, P, P]),
+        "mxp_collect_pairs": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.c_int32, P, P,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mxp_solve_stats)]),
+        "mxp_problem_set_learned": (st, [P, P, ctypes.c_double]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -351,6 +374,88 @@ def mxp_solve_batch(ctx: Context, problems, opts, f_list, u_list, max_resident: 
     status = _check(lib.mxp_solve_batch(ctx.handle, nprob, Parr, Narr, Farr, Uarr, Oarr, max_resident, Sarr),
                     allow_not_converged=True)
     return status, [Sarr[k].as_dict() for k in range(total)]
+
+
+class Network:
+    """mxp_cnn: the learned stage's network on a context's device and stream."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        handle = ctypes.c_void_p()
+        _check(lib.mxp_cnn_create(ctx.handle, seed, ctypes.byref(handle)))
+        self.handle = handle
+        _LIVE_PROBLEMS.add(self)
+
+    @staticmethod
+    def num_params() -> int:
+        return int(lib.mxp_cnn_num_params())
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.num_params(), dtype=np.float32)
+        _check(lib.mxp_cnn_get_params(self.handle, a.ctypes.data))
+        return a
+
+    def set_params(self, a) -> None:
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.size != self.num_params():
+            raise ValueError("wrong parameter count")
+        _check(lib.mxp_cnn_set_params(self.handle, a.ctypes.data))
+
+    def get_grads(self) -> np.ndarray:
+        a = np.empty(self.num_params(), dtype=np.float32)
+        _check(lib.mxp_cnn_get_grads(self.handle, a.ctypes.data))
+        return a
+
+    def forward(self, shape, x, out) -> None:
+        nb, nz, ny, nx = shape
+        _check(lib.mxp_cnn_forward(self.handle, nb, nz, ny, nx, _ptr(x), _ptr(out)))
+
+    def backward(self, shape, x, gout) -> None:
+        nb, nz, ny, nx = shape
+        _check(lib.mxp_cnn_backward(self.handle, nb, nz, ny, nx, _ptr(x), _ptr(gout)))
+
+    def train_step(self, shape, x, target, lr: float) -> float:
+        nb, nz, ny, nx = shape
+        loss = ctypes.c_double()
+        _check(lib.mxp_cnn_train_step(self.handle, nb, nz, ny, nx, _ptr(x), _ptr(target), lr, ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self.handle:
+            lib.mxp_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mxp_cnn_make_sample(prob: Problem, r, z, offset, crop, rscale: float, zscale: float, x, target) -> None:
+    off = (ctypes.c_int32 * 3)(*offset)
+    cr = (ctypes.c_int32 * 3)(*crop)
+    _check(lib.mxp_cnn_make_sample(prob.handle, _ptr(r), _ptr(z), off, cr, rscale, zscale, _ptr(x), _ptr(target)))
+
+
+def mxp_collect_pairs(prob: Problem, opts: mxp_solve_opts, f, u, r_out, z_out, max_pairs: int):
+    """Solve while copying (v_j, M(v_j)) pairs into r_out / z_out (complex128
+    device tensors of max_pairs * size values).  Returns (count, |r| list,
+    |z| list, stats dict)."""
+    rn = (ctypes.c_double * max(max_pairs, 1))()
+    zn = (ctypes.c_double * max(max_pairs, 1))()
+    cnt = ctypes.c_int32()
+    st = mxp_solve_stats()
+    status = _check(lib.mxp_collect_pairs(prob.handle, ctypes.byref(opts), _ptr(f), _ptr(u), max_pairs,
+                                          _ptr(r_out), _ptr(z_out), rn, zn, ctypes.byref(cnt), ctypes.byref(st)),
+                    allow_not_converged=True)
+    out = st.as_dict()
+    out["status"] = status
+    return cnt.value, list(rn[:cnt.value]), list(zn[:cnt.value]), out
+
+
+def mxp_problem_set_learned(prob: Problem, net, out_scale: float) -> None:
+    _check(lib.mxp_problem_set_learned(prob.handle, net.handle if net is not None else None, out_scale))
 
 
 def mxp_set_tiles(prob: Problem, precision: int, K: int, NX: int, Ly: int) -> None:

@@ -29,6 +29,8 @@
 #include <tuple>
 #include <vector>
 
+#include "cnn_net.h"
+#include "devmem.h"
 #include "kernels.h"
 #include "mxp_internal.h"
 
@@ -41,40 +43,6 @@ struct mxp_context {
 namespace mxp {
 
 thread_local std::string g_last_error;
-
-#define HIP_CHECK(expr)                                                                        \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) fail(MXP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-// Owned device allocation.
-struct DevMem {
-    void* p = nullptr;
-    size_t bytes = 0;
-    DevMem() = default;
-    DevMem(const DevMem&) = delete;
-    DevMem& operator=(const DevMem&) = delete;
-    ~DevMem() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    void ensure(size_t want) {
-        if (want <= bytes) return;
-        release();
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            fail(MXP_ERR_OOM, "device allocation of " + std::to_string(want) + " bytes failed");
-        }
-        bytes = want;
-    }
-    template <class T>
-    T* as() const { return static_cast<T*>(p); }
-};
 
 template <typename R>
 struct DevTables {
@@ -121,6 +89,15 @@ struct Workspace {
 
 class Batcher;
 
+// Where a solve copies its (Krylov vector, preconditioned vector) pairs.
+struct PairSink {
+    cpx<double>* r;
+    cpx<double>* z;
+    double* rnorm;  // host
+    double* znorm;  // host
+    int max, count;
+};
+
 // One solve in progress: its problem (read-only while solving), workspace,
 // the stream its Krylov work runs on, and the batcher its matrix-function
 // actions go to (nullptr: run them directly on that stream).
@@ -130,6 +107,7 @@ struct Run {
     hipStream_t s;
     Batcher* batch;
     hipEvent_t ev;  // batched runs: marks the action input ready on s
+    PairSink* pairs = nullptr;
 };
 
 }  // namespace mxp
@@ -146,6 +124,8 @@ struct mxp_problem {
     double Dref = 0.0;  // reference value of D folded into the diagonal tables
     mxp::TileCfg tiles[2];  // per precision (0 = double, 1 = float); K = 0 until tuned
     mxp::Workspace ws;      // workspace of the single-solve calls
+    mxp_cnn* net = nullptr; // learned stage (not owned), with its output scale
+    double net_scale = 1.0;
 };
 
 namespace mxp {
@@ -1034,7 +1014,19 @@ static void action64(Run& run, const Sched& sc, double t, double shift, bool psi
 
 struct Counters {
     int64_t steps = 0, actions = 0;
+    int learned = 0, fallbacks = 0;
 };
+
+// z = learned network applied to v (unit norm), complex double.
+static void learned_apply(Run& run, const cpx<double>* v, double vnorm, cpx<double>* z) {
+    mxp_problem* P = run.P;
+    const int64_t n = npts(P);
+    const ConvShape sh{1, int(P->g.n[2]), int(P->g.n[1]), int(P->g.n[0])};
+    // the network sees the residual at unit root-mean-square value
+    const double rs = std::sqrt(double(n)) / vnorm;
+    const float* D = P->g.homogeneous ? nullptr : P->D32.as<float>();
+    cnn_apply(P->net, sh, v, D, float(P->Dref), rs, P->net_scale / rs, z, run.s);
+}
 
 // Algorithm 1.  r, w: complex double device vectors.
 static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt) {
@@ -1133,6 +1125,8 @@ static void check_opts(const mxp_solve_opts* o) {
     if (o->precision != MXP_PREC_FP64 && o->precision != MXP_PREC_MIXED)
         fail(MXP_ERR_INVALID_ARG, "unknown precision");
     if (o->cheb_S < 0 || o->cheb_m < 0) fail(MXP_ERR_INVALID_ARG, "cheb_S, cheb_m must be >= 0");
+    if (o->use_learned && !(o->stall_ratio > 0 && o->stall_ratio <= 1))
+        fail(MXP_ERR_INVALID_ARG, "stall_ratio must be in (0, 1]");
 }
 
 static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
@@ -1163,25 +1157,66 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
         launch_zero<double>(u, n, s);
         relres = 0.0;
     }
+    if (o.use_learned && !P->net) fail(MXP_ERR_INVALID_ARG, "use_learned needs a network (mxp_problem_set_learned)");
+    if (o.use_learned && run.batch) fail(MXP_ERR_UNSUPPORTED, "the learned stage runs in single solves only");
+    bool use_net = o.use_learned != 0;
+    int misses = 0;
     while (bnorm > 0.0 && beta > o.rtol * bnorm) {
         ++cycles;
         launch_scale({1.0 / beta, 0.0}, r, V, n, s);
         gv.reset(beta);
+        double prev_res = beta;
         int k = 0;
         bool est_ok = false;
         for (int j = 0; j < m; ++j) {
             cpx<double>* vj = V + size_t(j) * n;
             cpx<double>* zj = Z + size_t(j) * n;
             cpx<double>* vn = V + size_t(j + 1) * n;
-            inner.push_back(precond(run, o, vj, zj, cnt));
-            apply_A64(P, s, 0.0, zj, vn, 1.0, nullptr, 0.0);
-            const double hn = cgs2(run, V, n, j + 1, vn, h);
+            // Learned stage: try the network's z_j first and keep it when the
+            // Arnoldi residual estimate falls below stall_ratio times the
+            // previous one; otherwise (and for good after two misses in a
+            // row) the MatExPre preconditioner supplies z_j.
+            double hn = 0.0, res = 0.0;
+            bool accepted = false;
+            if (use_net) {
+                learned_apply(run, vj, 1.0, zj);
+                apply_A64(P, s, 0.0, zj, vn, 1.0, nullptr, 0.0);
+                hn = cgs2(run, V, n, j + 1, vn, h);
+                Givens trial = gv;
+                res = trial.add_column(j, h, hn);
+                if (std::isfinite(res) && res <= o.stall_ratio * prev_res) {
+                    gv = trial;
+                    accepted = true;
+                    cnt.learned++;
+                    misses = 0;
+                } else {
+                    cnt.fallbacks++;
+                    if (++misses >= 2) use_net = false;
+                }
+            }
+            if (!accepted) {
+                inner.push_back(precond(run, o, vj, zj, cnt));
+                if (run.pairs && run.pairs->count < run.pairs->max) {
+                    PairSink& ps = *run.pairs;
+                    HIP_CHECK(hipMemcpyAsync(ps.r + size_t(ps.count) * n, vj, size_t(n) * sizeof(cpx<double>),
+                                             hipMemcpyDeviceToDevice, s));
+                    HIP_CHECK(hipMemcpyAsync(ps.z + size_t(ps.count) * n, zj, size_t(n) * sizeof(cpx<double>),
+                                             hipMemcpyDeviceToDevice, s));
+                    ps.rnorm[ps.count] = 1.0;
+                    ps.znorm[ps.count] = norm2(run, zj);
+                    ps.count++;
+                }
+                apply_A64(P, s, 0.0, zj, vn, 1.0, nullptr, 0.0);
+                hn = cgs2(run, V, n, j + 1, vn, h);
+                res = gv.add_column(j, h, hn);
+            }
             ++its;
-            const double res = gv.add_column(j, h, hn);
+            prev_res = res;
             if (P->ctx->verbose) {
                 const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                std::fprintf(stderr, "[mxp] outer %d: est relres %.3e, inner %d, steps %lld, %.2f s\n", its,
-                             res / bnorm, inner.back(), (long long)cnt.steps, el);
+                std::fprintf(stderr, "[mxp] outer %d: est relres %.3e, %s, steps %lld, %.2f s\n", its,
+                             res / bnorm, accepted ? "learned" : ("inner " + std::to_string(inner.back())).c_str(),
+                             (long long)cnt.steps, el);
                 std::fflush(stderr);
             }
             if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite outer residual estimate");
@@ -1221,6 +1256,8 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
         st->fn_actions = cnt.actions;
         st->true_relres = relres;
         st->restarts = std::max(0, cycles - 1);
+        st->learned_its = cnt.learned;
+        st->fallbacks = cnt.fallbacks;
         st->status = relres <= o.rtol ? MXP_OK : MXP_NOT_CONVERGED;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -1245,6 +1282,11 @@ static mxp_status guard(F&& fn) {
 }
 
 static void use_device(const mxp_context* ctx) { HIP_CHECK(hipSetDevice(ctx->device)); }
+
+void context_info(const mxp_context* ctx, int* device, hipStream_t* stream) {
+    *device = ctx->device;
+    *stream = ctx->stream;
+}
 
 static void check_problem(const mxp_problem* P) {
     if (!P) fail(MXP_ERR_INVALID_ARG, "problem is NULL");
@@ -1349,6 +1391,8 @@ mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out
         out->max_outer = 500;
         out->max_inner = 300;
         out->precision = MXP_PREC_FP64;
+        out->use_learned = 0;
+        out->stall_ratio = 0.9;
         return MXP_OK;
     });
 }
@@ -1592,6 +1636,52 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             if (status[k] == MXP_NOT_CONVERGED) worst = MXP_NOT_CONVERGED;
         }
         return worst;
+    });
+}
+
+mxp_status mxp_problem_set_learned(mxp_problem* prob, mxp_cnn* net, double out_scale) {
+    return guard([&]() {
+        check_problem(prob);
+        if (net && !(out_scale > 0 && std::isfinite(out_scale)))
+            fail(MXP_ERR_INVALID_ARG, "out_scale must be positive");
+        prob->net = net;
+        prob->net_scale = net ? out_scale : 1.0;
+        return MXP_OK;
+    });
+}
+
+mxp_status mxp_collect_pairs(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
+                             int32_t max_pairs, void* r_out, void* z_out, double* rnorm, double* znorm,
+                             int32_t* npairs, mxp_solve_stats* stats) {
+    return guard([&]() {
+        check_problem(prob);
+        check_opts(opts);
+        if (!f || !u || f == u) fail(MXP_ERR_INVALID_ARG, "f and u must be distinct non-NULL pointers");
+        if (max_pairs < 0 || (max_pairs > 0 && (!r_out || !z_out || !rnorm || !znorm)))
+            fail(MXP_ERR_INVALID_ARG, "pair buffers must be given for max_pairs > 0");
+        if (opts->use_learned) fail(MXP_ERR_INVALID_ARG, "pairs come from the MatExPre preconditioner alone");
+        PairSink ps{static_cast<cpx<double>*>(r_out), static_cast<cpx<double>*>(z_out), rnorm, znorm, max_pairs, 0};
+        Run run{prob, &prob->ws, prob->ctx->stream, nullptr, nullptr, &ps};
+        const mxp_status st = solve(run, *opts, static_cast<const cpx<double>*>(f), static_cast<cpx<double>*>(u), stats);
+        if (npairs) *npairs = ps.count;
+        return st;
+    });
+}
+
+mxp_status mxp_cnn_make_sample(mxp_problem* prob, const void* r, const void* z, const int32_t offset[3],
+                               const int32_t crop[3], double rscale, double zscale, void* in, float* target) {
+    return guard([&]() {
+        check_problem(prob);
+        if (!r || !z || !offset || !crop || !in || !target) fail(MXP_ERR_INVALID_ARG, "NULL argument");
+        for (int d = 0; d < 3; ++d)
+            if (crop[d] < 1 || offset[d] < 0 || offset[d] + crop[d] > prob->g.n[d])
+                fail(MXP_ERR_INVALID_ARG, "crop outside the grid");
+        const float* D = prob->g.homogeneous ? nullptr : prob->D32.as<float>();
+        launch_cnn_crop(r, z, D, float(prob->Dref), prob->g.n[0], prob->g.n[1], offset[0], offset[1], offset[2],
+                        crop[0], crop[1], crop[2], rscale, zscale, static_cast<uint16_t*>(in), target,
+                        prob->ctx->stream);
+        HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
+        return MXP_OK;
     });
 }
 

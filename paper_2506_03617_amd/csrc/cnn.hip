@@ -1,0 +1,540 @@
+// Learned preconditioner stage: 3x3x3 convolutions on the bf16 matrix cores
+// of gfx950 (v_mfma_f32_32x32x16_bf16, float accumulation), and the small
+// kernels of training (loss, bias gradient, Adam, weight packing) and of
+// moving residuals in and out of the network.
+//
+// Convolution as an implicit GEMM: a wavefront owns 32 consecutive x voxels
+// of one output row and all 32 output channels (one 32 x 32 MFMA tile); the
+// K dimension runs over (tap, input channel).  A workgroup (four wavefronts)
+// computes a brick of 32 x 4 x 2 voxels from a zero-padded 34 x 6 x 4 input
+// halo and the layer's 27 x 32 x cin weights, both staged in LDS with a
+// padded channel stride so that the 16-byte operand reads of neighbouring
+// lanes fall in different banks.  MFMA lane layout (checked on the device):
+// A row i = lane % 32 with k = 8 (lane / 32) .. +7, B column j = lane % 32
+// with the same k, result register r holds row 8 (r / 4) + 4 (lane / 32) +
+// r % 4 of column lane % 32.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "cnn.h"
+#include "mxp_internal.h"
+
+namespace mxp {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+__device__ __forceinline__ uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __builtin_bit_cast(float, uint32_t(h) << 16); }
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+inline void check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(MXP_ERR_HIP, std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------- convolution
+
+constexpr int BX = 32, BY = 4, BZ = 2;
+constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
+
+struct Bricks {
+    int bx, by, bz;
+};
+
+template <int CIN, int MODE>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
+                                             const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                             void* __restrict__ out, ConvShape s, Bricks nbk) {
+    constexpr int CS = CIN + 8;  // padded channel stride (16 bytes of spread)
+    constexpr int CH = CIN / 8;  // 16-byte chunks per voxel
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[HZ * HY * HX * CS];
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[27 * 32 * CS];
+    const int tid = threadIdx.x;
+    int b = blockIdx.x;
+    const int bxi = b % nbk.bx;
+    b /= nbk.bx;
+    const int byi = b % nbk.by;
+    b /= nbk.by;
+    const int bzi = b % nbk.bz;
+    const int vol = b / nbk.bz;
+    const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
+    const int64_t vbase = int64_t(vol) * s.nz * s.ny * s.nx;
+    for (int c = tid; c < HZ * HY * HX * CH; c += 256) {
+        const int ch = c % CH;
+        int v = c / CH;
+        const int hx = v % HX;
+        v /= HX;
+        const int hy = v % HY;
+        const int hz = v / HY;
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+        uint4 val = make_uint4(0u, 0u, 0u, 0u);
+        if (gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny && gz >= 0 && gz < s.nz)
+            val = *reinterpret_cast<const uint4*>(in + (vbase + (int64_t(gz) * s.ny + gy) * s.nx + gx) * CIN +
+                                                  ch * 8);
+        *reinterpret_cast<uint4*>(&s_in[((hz * HY + hy) * HX + hx) * CS + ch * 8]) = val;
+    }
+    for (int c = tid; c < 27 * 32 * CH; c += 256) {
+        const int ch = c % CH;
+        const int row = c / CH;  // tap * 32 + output channel
+        *reinterpret_cast<uint4*>(&s_w[row * CS + ch * 8]) =
+            *reinterpret_cast<const uint4*>(w + int64_t(row) * CIN + ch * 8);
+    }
+    __syncthreads();
+    const int lane = tid & 63;
+    const int wv = tid >> 6;  // output row y0 + wv of the brick
+    const int i = lane & 31;
+    const int kh = lane >> 5;
+    f32x16 acc0 = {}, acc1 = {};
+    if constexpr (CIN == 32) {
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
+            const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS + 8 * kh];
+            const uint16_t* a1p = a0p + HY * HX * CS;
+            const uint16_t* bp = &s_w[(tap * 32 + i) * CS + 8 * kh];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 bw = ld8(bp + 16 * kb);
+                acc0 = mfma(ld8(a0p + 16 * kb), bw, acc0);
+                acc1 = mfma(ld8(a1p + 16 * kb), bw, acc1);
+            }
+        }
+    } else {
+        // eight channels: the two half-wavefronts take consecutive taps
+        for (int p = 0; p < 14; ++p) {
+            const int tap = 2 * p + kh;
+            bf16x8 bw = {}, a0 = {}, a1 = {};
+            if (tap < 27) {
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
+                const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS];
+                bw = ld8(&s_w[(tap * 32 + i) * CS]);
+                a0 = ld8(a0p);
+                a1 = ld8(a0p + HY * HX * CS);
+            }
+            acc0 = mfma(a0, bw, acc0);
+            acc1 = mfma(a1, bw, acc1);
+        }
+    }
+    const int co = i;
+    const int y = y0 + wv;
+    if (y >= s.ny) return;
+    float bco = 0.0f;
+    if constexpr (MODE != CONV_MASK) bco = bias[co];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int z = z0 + t;
+        if (z >= s.nz) break;
+        const f32x16 acc = t ? acc1 : acc0;
+        const int64_t rowbase = vbase + (int64_t(z) * s.ny + y) * s.nx;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int x = x0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+            if (x >= s.nx) continue;
+            const int64_t vox = rowbase + x;
+            if constexpr (MODE == CONV_BIAS_RELU) {
+                const float v = acc[r] + bco;
+                static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(v > 0.0f ? v : 0.0f);
+            } else if constexpr (MODE == CONV_BIAS_F32) {
+                if (co < 2) static_cast<float*>(out)[vox * 2 + co] = acc[r] + bco;
+            } else {
+                const bool on = bf16_value(mask[vox * 32 + co]) > 0.0f;
+                static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(on ? acc[r] : 0.0f);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------- weight gradient
+
+constexpr int WX = 32, WY = 2, WZ = 2;
+constexpr int WROWS_H = (WZ + 2) * (WY + 2);  // halo rows of H per brick
+constexpr int WROWS_G = WZ * WY;
+constexpr int SG_STRIDE = WROWS_G * WX + 8;   // per output channel (odd multiple of 16 bytes)
+constexpr int SH_STRIDE = WROWS_H * WX + 8;   // per input channel
+constexpr int kWgradGroups = 512;
+
+// H transposed into x-contiguous rows, one copy per x shift dx so that every
+// 8-voxel operand read is 16-byte aligned; G transposed likewise.  Each
+// wavefront accumulates the taps tap = wave + 4j in registers over all the
+// bricks its workgroup visits, then writes its partial sums.
+template <int CG, int CHN>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ G, const uint16_t* __restrict__ H,
+                                                   float* __restrict__ partial, ConvShape s, Bricks nbk,
+                                                   int nbricks) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_g[32 * SG_STRIDE];
+    __shared__ __attribute__((aligned(16))) uint16_t s_h[3 * 32 * SH_STRIDE];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int i = lane & 31;
+    const int kh = lane >> 5;
+    // channels past CG / CHN stay zero for the whole kernel
+    for (int c = tid; c < 32 * SG_STRIDE; c += 256) s_g[c] = 0;
+    for (int c = tid; c < 3 * 32 * SH_STRIDE; c += 256) s_h[c] = 0;
+    f32x16 acc[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) acc[j] = f32x16{};
+    for (int brick = blockIdx.x; brick < nbricks; brick += gridDim.x) {
+        int b = brick;
+        const int bxi = b % nbk.bx;
+        b /= nbk.bx;
+        const int byi = b % nbk.by;
+        b /= nbk.by;
+        const int bzi = b % nbk.bz;
+        const int vol = b / nbk.bz;
+        const int x0 = bxi * WX, y0 = byi * WY, z0 = bzi * WZ;
+        const int64_t vbase = int64_t(vol) * s.nz * s.ny * s.nx;
+        __syncthreads();  // the previous brick's operands are consumed
+        // G rows: (z, y) in the brick, x0 .. x0 + 31
+        for (int c = tid; c < WROWS_G * WX * (CG / 8); c += 256) {
+            const int ch = c % (CG / 8);
+            int v = c / (CG / 8);
+            const int xi = v % WX;
+            const int row = v / WX;  // z * WY + y
+            const int gx = x0 + xi, gy = y0 + row % WY, gz = z0 + row / WY;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (gx < s.nx && gy < s.ny && gz < s.nz)
+                val = *reinterpret_cast<const uint4*>(G + (vbase + (int64_t(gz) * s.ny + gy) * s.nx + gx) * CG +
+                                                      ch * 8);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&val);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s_g[(ch * 8 + q) * SG_STRIDE + row * WX + xi] = e[q];
+        }
+        // H halo rows: (z, y) in -1 .. brick + 1, x0 - 1 .. x0 + 32, stored
+        // for every dx whose window holds the voxel
+        for (int c = tid; c < WROWS_H * (WX + 2) * (CHN / 8); c += 256) {
+            const int ch = c % (CHN / 8);
+            int v = c / (CHN / 8);
+            const int hx = v % (WX + 2);
+            const int row = v / (WX + 2);  // hz * (WY + 2) + hy
+            const int gx = x0 - 1 + hx, gy = y0 - 1 + row % (WY + 2), gz = z0 - 1 + row / (WY + 2);
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny && gz >= 0 && gz < s.nz)
+                val = *reinterpret_cast<const uint4*>(H + (vbase + (int64_t(gz) * s.ny + gy) * s.nx + gx) * CHN +
+                                                      ch * 8);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&val);
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int xi = hx - dx;
+                if (xi < 0 || xi >= WX) continue;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    s_h[(dx * 32 + ch * 8 + q) * SH_STRIDE + row * WX + xi] = e[q];
+            }
+        }
+        __syncthreads();
+        // A operands (G^T: output channel x 8 voxels) for the 4 rows x 2 x-halves
+        bf16x8 ga[WROWS_G][2];
+#pragma unroll
+        for (int row = 0; row < WROWS_G; ++row)
+#pragma unroll
+            for (int xb = 0; xb < 2; ++xb) ga[row][xb] = ld8(&s_g[i * SG_STRIDE + row * WX + 16 * xb + 8 * kh]);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const int tap = wv + 4 * j;
+            if (tap >= 27) break;
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
+            const uint16_t* hb = &s_h[(dx * 32 + i) * SH_STRIDE + 8 * kh];
+#pragma unroll
+            for (int zz = 0; zz < WZ; ++zz)
+#pragma unroll
+                for (int yy = 0; yy < WY; ++yy) {
+                    const int hrow = (zz + dz) * (WY + 2) + (yy + dy);
+#pragma unroll
+                    for (int xb = 0; xb < 2; ++xb)
+                        acc[j] = mfma(ga[zz * WY + yy][xb], ld8(hb + hrow * WX + 16 * xb), acc[j]);
+                }
+        }
+    }
+    // partial[group][tap][co][ci]: register r is output channel co = 8 (r/4) + 4 kh + r%4, input channel i
+    float* pg = partial + int64_t(blockIdx.x) * 27 * 32 * 32;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const int tap = wv + 4 * j;
+        if (tap >= 27) break;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int co = 8 * (r >> 2) + 4 * kh + (r & 3);
+            pg[(tap * 32 + co) * 32 + i] = acc[j][r];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int groups, int cout,
+                                                      int cin, float* __restrict__ gW) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;  // (co, ci, tap) in the master layout
+    if (idx >= cout * cin * 27) return;
+    const int tap = idx % 27;
+    const int ci = (idx / 27) % cin;
+    const int co = idx / (27 * cin);
+    double acc = 0.0;
+    for (int g = 0; g < groups; ++g) acc += partial[(int64_t(g) * 27 * 32 + tap * 32 + co) * 32 + ci];
+    gW[idx] = float(acc);
+}
+
+// ------------------------------------------------------ small training kernels
+
+constexpr int kRedGroups = 1024;
+
+__global__ __launch_bounds__(256) void k_bias_partial(const uint16_t* __restrict__ G, int cg, int64_t V,
+                                                     float* __restrict__ partial) {
+    __shared__ float red[8][32];
+    const int co = threadIdx.x & 31;
+    const int sub = threadIdx.x >> 5;  // 8 voxel lanes per channel
+    float acc = 0.0f;
+    if (co < cg)
+        for (int64_t v = int64_t(blockIdx.x) * 8 + sub; v < V; v += int64_t(gridDim.x) * 8)
+            acc += bf16_value(G[v * cg + co]);
+    red[sub][co] = acc;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float t = 0.0f;
+        for (int q = 0; q < 8; ++q) t += red[q][threadIdx.x];
+        partial[blockIdx.x * 32 + threadIdx.x] = t;
+    }
+}
+
+__global__ void k_bias_reduce(const float* __restrict__ partial, int groups, int cout, float* __restrict__ gb) {
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    double acc = 0.0;
+    for (int g = 0; g < groups; ++g) acc += partial[g * 32 + co];
+    gb[co] = float(acc);
+}
+
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, const float* __restrict__ target,
+                                            int64_t V, float scale, uint16_t* __restrict__ gout,
+                                            double* __restrict__ partial) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x; v < V; v += int64_t(gridDim.x) * 256) {
+        const float d0 = out[2 * v] - target[2 * v];
+        const float d1 = out[2 * v + 1] - target[2 * v + 1];
+        acc += double(d0) * d0 + double(d1) * d1;
+        uint4 g = make_uint4(0u, 0u, 0u, 0u);
+        g.x = uint32_t(bf16_bits(scale * d0)) | (uint32_t(bf16_bits(scale * d1)) << 16);
+        reinterpret_cast<uint4*>(gout)[v] = g;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_doubles(const double* __restrict__ partial, int n, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    for (int g = 0; g < n; ++g) acc += partial[g];
+    out[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_grad_to_bf16(const float* __restrict__ g, int64_t V,
+                                                     uint16_t* __restrict__ gout) {
+    const int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (v >= V) return;
+    uint4 o = make_uint4(0u, 0u, 0u, 0u);
+    o.x = uint32_t(bf16_bits(g[2 * v])) | (uint32_t(bf16_bits(g[2 * v + 1])) << 16);
+    reinterpret_cast<uint4*>(gout)[v] = o;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                             const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
+                                             float eps, float bc1, float bc2) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    w[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_pack_weights(const float* __restrict__ W, int cout, int cin, int cinp,
+                                                     int coutp, uint16_t* __restrict__ wf, uint16_t* __restrict__ wb) {
+    // wf: [27][32][cinp]; wb: [27][32][coutp]
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int nf = 27 * 32 * cinp;
+    if (idx < nf) {
+        const int ci = idx % cinp;
+        const int co = (idx / cinp) % 32;
+        const int tap = idx / (cinp * 32);
+        const float val = (co < cout && ci < cin) ? W[(co * cin + ci) * 27 + tap] : 0.0f;
+        wf[idx] = bf16_bits(val);
+    }
+    if (wb && idx < 27 * 32 * coutp) {
+        const int co = idx % coutp;
+        const int ci = (idx / coutp) % 32;
+        const int tap = idx / (coutp * 32);
+        const float val = (co < cout && ci < cin) ? W[(co * cin + ci) * 27 + (26 - tap)] : 0.0f;
+        wb[idx] = bf16_bits(val);
+    }
+}
+
+struct cd2 {
+    double re, im;
+};
+
+__global__ __launch_bounds__(256) void k_cnn_input(const cd2* __restrict__ r, const float* __restrict__ D, float Dc,
+                                                  const double* __restrict__ scale, int64_t V,
+                                                  uint16_t* __restrict__ in) {
+    const int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (v >= V) return;
+    const double sc = scale[0];
+    const cd2 x = r[v];
+    const float d = D ? D[v] : Dc;
+    uint4 o = make_uint4(0u, 0u, 0u, 0u);
+    o.x = uint32_t(bf16_bits(float(x.re * sc))) | (uint32_t(bf16_bits(float(x.im * sc))) << 16);
+    o.y = uint32_t(bf16_bits(d));
+    reinterpret_cast<uint4*>(in)[v] = o;
+}
+
+__global__ __launch_bounds__(256) void k_cnn_output(const float* __restrict__ out, const double* __restrict__ scale,
+                                                   int64_t V, cd2* __restrict__ z) {
+    const int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (v >= V) return;
+    const double sc = scale[0];
+    z[v] = {sc * out[2 * v], sc * out[2 * v + 1]};
+}
+
+__global__ __launch_bounds__(256) void k_cnn_crop(const cd2* __restrict__ r, const cd2* __restrict__ zv,
+                                                 const float* __restrict__ D, float Dc, int64_t g0, int64_t g1,
+                                                 int o0, int o1, int o2, int c0, int c1, int c2, double rs, double zs,
+                                                 uint16_t* __restrict__ in, float* __restrict__ target) {
+    const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t n = int64_t(c0) * c1 * c2;
+    if (q >= n) return;
+    const int i0 = int(q % c0), i1 = int((q / c0) % c1), i2 = int(q / (int64_t(c0) * c1));
+    const int64_t p = (o0 + i0) + g0 * ((o1 + i1) + g1 * int64_t(o2 + i2));
+    const cd2 x = r[p];
+    const float d = D ? D[p] : Dc;
+    uint4 o = make_uint4(0u, 0u, 0u, 0u);
+    o.x = uint32_t(bf16_bits(float(x.re * rs))) | (uint32_t(bf16_bits(float(x.im * rs))) << 16);
+    o.y = uint32_t(bf16_bits(d));
+    reinterpret_cast<uint4*>(in)[q] = o;
+    const cd2 t = zv[p];
+    target[2 * q] = float(t.re * zs);
+    target[2 * q + 1] = float(t.im * zs);
+}
+
+inline unsigned grid_for(int64_t n) { return unsigned((n + 255) / 256); }
+
+}  // namespace
+
+void launch_conv(int cin, ConvMode mode, const uint16_t* in, const uint16_t* w, const float* bias,
+                 const uint16_t* mask, void* out, const ConvShape& s, hipStream_t st) {
+    Bricks nbk{(s.nx + BX - 1) / BX, (s.ny + BY - 1) / BY, (s.nz + BZ - 1) / BZ};
+    const int64_t nb = int64_t(nbk.bx) * nbk.by * nbk.bz * s.nb;
+    if (nb <= 0) return;
+    if (nb > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "convolution grid too large");
+    const dim3 grid = dim3(unsigned(nb)), block = dim3(256);
+#define MXP_CONV(C, M) hipLaunchKernelGGL((k_conv<C, M>), grid, block, 0, st, in, w, bias, mask, out, s, nbk)
+    if (cin == 32) {
+        if (mode == CONV_BIAS_RELU) MXP_CONV(32, CONV_BIAS_RELU);
+        else if (mode == CONV_BIAS_F32) MXP_CONV(32, CONV_BIAS_F32);
+        else MXP_CONV(32, CONV_MASK);
+    } else if (cin == 8) {
+        if (mode == CONV_BIAS_RELU) MXP_CONV(8, CONV_BIAS_RELU);
+        else if (mode == CONV_BIAS_F32) MXP_CONV(8, CONV_BIAS_F32);
+        else MXP_CONV(8, CONV_MASK);
+    } else {
+        fail(MXP_ERR_INVALID_ARG, "convolution input channels must be 8 or 32");
+    }
+#undef MXP_CONV
+    check_launch("conv");
+}
+
+int conv_wgrad_max_groups() { return kWgradGroups; }
+
+int launch_conv_wgrad(int cg, int ch, const uint16_t* G, const uint16_t* H, float* partial, const ConvShape& s,
+                      hipStream_t st) {
+    Bricks nbk{(s.nx + WX - 1) / WX, (s.ny + WY - 1) / WY, (s.nz + WZ - 1) / WZ};
+    const int64_t nbr = int64_t(nbk.bx) * nbk.by * nbk.bz * s.nb;
+    if (nbr <= 0) return 0;
+    if (nbr > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "weight-gradient grid too large");
+    const int groups = int(nbr < kWgradGroups ? nbr : kWgradGroups);
+    const dim3 grid(groups), block(256);
+#define MXP_WG(A, B) hipLaunchKernelGGL((k_conv_wgrad<A, B>), grid, block, 0, st, G, H, partial, s, nbk, int(nbr))
+    if (cg == 32 && ch == 32) MXP_WG(32, 32);
+    else if (cg == 32 && ch == 8) MXP_WG(32, 8);
+    else if (cg == 8 && ch == 32) MXP_WG(8, 32);
+    else if (cg == 8 && ch == 8) MXP_WG(8, 8);
+    else fail(MXP_ERR_INVALID_ARG, "weight gradient channels must be 8 or 32");
+#undef MXP_WG
+    check_launch("conv weight gradient");
+    return groups;
+}
+
+void launch_wgrad_reduce(const float* partial, int groups, int cout, int cin, float* gW, hipStream_t st) {
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_for(int64_t(cout) * cin * 27)), dim3(256), 0, st, partial, groups,
+                       cout, cin, gW);
+    check_launch("weight gradient reduction");
+}
+
+void launch_bias_grad(const uint16_t* G, int cg, int cout, int64_t V, float* partial, float* gb, hipStream_t st) {
+    const int groups = int(V / 8 + 1 < kRedGroups ? V / 8 + 1 : kRedGroups);
+    hipLaunchKernelGGL(k_bias_partial, dim3(groups), dim3(256), 0, st, G, cg, V, partial);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(32), 0, st, partial, groups, cout, gb);
+    check_launch("bias gradient");
+}
+
+void launch_mse(const float* out, const float* target, int64_t V, uint16_t* gout, double* partial, double* lsum,
+                hipStream_t st) {
+    const int groups = int(V / 256 + 1 < kRedGroups ? V / 256 + 1 : kRedGroups);
+    const float scale = float(2.0 / (2.0 * double(V)));
+    hipLaunchKernelGGL(k_mse, dim3(groups), dim3(256), 0, st, out, target, V, scale, gout, partial);
+    hipLaunchKernelGGL(k_sum_doubles, dim3(1), dim3(1), 0, st, partial, groups, lsum);
+    check_launch("mse");
+}
+
+void launch_grad_to_bf16(const float* g, int64_t V, uint16_t* gout, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_to_bf16, dim3(grid_for(V)), dim3(256), 0, st, g, V, gout);
+    check_launch("gradient cast");
+}
+
+void launch_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                 float bc1, float bc2, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, st, w, m, v, g, n, lr, b1, b2, eps, bc1, bc2);
+    check_launch("adam");
+}
+
+void launch_pack_weights(const float* W, int cout, int cin, int cinp, int coutp, uint16_t* wf, uint16_t* wb,
+                         hipStream_t st) {
+    const int64_t n = 27 * 32 * int64_t(cinp > coutp ? cinp : coutp);
+    hipLaunchKernelGGL(k_pack_weights, dim3(grid_for(n)), dim3(256), 0, st, W, cout, cin, cinp, coutp, wf, wb);
+    check_launch("pack weights");
+}
+
+void launch_cnn_input(const void* r, const float* D, float Dc, const double* scale, int64_t V, uint16_t* in,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_cnn_input, dim3(grid_for(V)), dim3(256), 0, st, static_cast<const cd2*>(r), D, Dc, scale, V,
+                       in);
+    check_launch("network input");
+}
+
+void launch_cnn_output(const float* out, const double* scale, int64_t V, void* z, hipStream_t st) {
+    hipLaunchKernelGGL(k_cnn_output, dim3(grid_for(V)), dim3(256), 0, st, out, scale, V, static_cast<cd2*>(z));
+    check_launch("network output");
+}
+
+void launch_cnn_crop(const void* r, const void* z, const float* D, float Dc, int64_t g0, int64_t g1, int o0, int o1,
+                     int o2, int c0, int c1, int c2, double rs, double zs, uint16_t* in, float* target,
+                     hipStream_t st) {
+    const int64_t n = int64_t(c0) * c1 * c2;
+    hipLaunchKernelGGL(k_cnn_crop, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const cd2*>(r),
+                       static_cast<const cd2*>(z), D, Dc, g0, g1, o0, o1, o2, c0, c1, c2, rs, zs, in, target);
+    check_launch("training crop");
+}
+
+}  // namespace mxp

@@ -1,0 +1,234 @@
+"""GPU tests of the learned stage: the bf16 matrix-core network kernels against
+the float64 oracle (oracle/conv.py), training steps, and solves that use the
+network with the MatExPre fallback.
+
+Tolerance.  The kernels store weights, activations and activation gradients
+in bfloat16 and accumulate in float.  The comparisons below hand the oracle
+exactly the bfloat16 weights and inputs and round the oracle's activations
+and gradients to bfloat16 at the same points the kernels do, so what remains
+is float-versus-double accumulation (about 1e-6 relative for the fan-ins
+here) and the rare element whose rounding lands on the other side of a
+bfloat16 boundary (2^-8 relative each, a small fraction of the elements).
+2e-3 relative in the 2-norm covers both with margin; a wrong tap, channel,
+transpose or mask is an O(1) error.  Without the rounding emulation the
+difference is the bfloat16 error itself (about 1e-2), checked separately
+against a looser bound."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import conv, krylov
+
+from gpu_util import announce, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_03617_amd as mxp  # noqa: E402
+
+CH = conv.CHANNELS
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mxp.Context(0)
+    yield c
+    c.close()
+
+
+def bf16_bits(a):
+    f = conv.to_bf16(a).astype(np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def make_input(shape, seed):
+    nb, nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    x = np.zeros((nb, nz, ny, nx, 8))
+    x[..., 0:2] = rng.uniform(-1.0, 1.0, (nb, nz, ny, nx, 2))
+    x[..., 2] = rng.uniform(1.0 / 9.0, 1.0, (nb, nz, ny, nx))
+    x = conv.to_bf16(x)
+    return x, bf16_bits(x)
+
+
+def layers_of(flat):
+    out, off = [], 0
+    for cin, cout in zip(CH[:-1], CH[1:]):
+        nw = cout * cin * 27
+        w = flat[off:off + nw].astype(np.float64).reshape(cout, cin, 3, 3, 3)
+        off += nw
+        b = flat[off:off + cout].astype(np.float64)
+        off += cout
+        out.append({"w": w, "b": b})
+    return out
+
+
+def flat_of(layers):
+    return np.concatenate([np.concatenate([p["w"].ravel(), p["b"].ravel()]) for p in layers]).astype(np.float32)
+
+
+def emulated_forward(layers, x):
+    """Oracle forward on one volume with the kernels' bfloat16 roundings."""
+    h = x[..., :3]
+    acts = [h]
+    for l, p in enumerate(layers):
+        y = conv.conv3d(h, conv.to_bf16(p["w"]), p["b"])
+        if l < len(layers) - 1:
+            y = conv.to_bf16(np.maximum(y, 0.0))
+        acts.append(y)
+        h = y
+    return h, acts
+
+
+def emulated_backward(layers, acts, gout):
+    g = conv.to_bf16(gout)
+    grads = [None] * len(layers)
+    for l in range(len(layers) - 1, -1, -1):
+        gx, gw, gb = conv.conv3d_backward(acts[l], conv.to_bf16(layers[l]["w"]), g)
+        grads[l] = {"w": gw, "b": gb}
+        if l > 0:
+            g = conv.to_bf16(gx * (acts[l] > 0))
+    return grads
+
+
+SHAPE = (2, 5, 7, 45)  # two volumes; x spans two 32-wide tiles, y and z ragged
+
+
+def random_params(seed):
+    layers = conv.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    for p in layers:
+        p["b"] = rng.normal(0.0, 0.05, p["b"].shape)
+    return flat_of(layers)
+
+
+def test_forward_matches_oracle(ctx):
+    announce("cnn forward")
+    net = mxp.Network(ctx, 1)
+    flat = random_params(3)
+    net.set_params(flat)
+    assert np.array_equal(net.get_params(), flat)
+    x, bits = make_input(SHAPE, 4)
+    xd = torch.from_numpy(bits.view(np.int16)).to("cuda:0")
+    out = torch.empty(int(np.prod(SHAPE[:4])) * 2, dtype=torch.float32, device="cuda:0")
+    net.forward(SHAPE, xd, out)
+    y = out.cpu().numpy().astype(np.float64).reshape(SHAPE + (2,))
+    layers = layers_of(flat)
+    for b in range(SHAPE[0]):
+        ref, _ = emulated_forward(layers, x[b])
+        assert rel(y[b], ref) <= 2e-3
+        plain, _ = conv.forward(layers, x[b][..., :3])
+        assert rel(y[b], plain) <= 3e-2
+    net.close()
+
+
+def test_backward_matches_oracle(ctx):
+    announce("cnn backward")
+    net = mxp.Network(ctx, 1)
+    flat = random_params(5)
+    net.set_params(flat)
+    x, bits = make_input(SHAPE, 6)
+    rng = np.random.default_rng(7)
+    gout = rng.standard_normal(SHAPE + (2,)).astype(np.float32)
+    net.backward(SHAPE, torch.from_numpy(bits.view(np.int16)).to("cuda:0"),
+                 torch.from_numpy(gout.ravel()).to("cuda:0"))
+    g = layers_of(net.get_grads())
+    layers = layers_of(flat)
+    ref = None
+    for b in range(SHAPE[0]):
+        _, acts = emulated_forward(layers, x[b])
+        gb = emulated_backward(layers, acts, gout[b].astype(np.float64))
+        ref = gb if ref is None else [{k: r[k] + q[k] for k in r} for r, q in zip(ref, gb)]
+    for l in range(len(layers)):
+        assert rel(g[l]["w"], ref[l]["w"]) <= 2e-3, l
+        assert rel(g[l]["b"], ref[l]["b"]) <= 2e-3, l
+    net.close()
+
+
+def test_training_steps_match_oracle_adam(ctx):
+    announce("cnn train")
+    net = mxp.Network(ctx, 1)
+    flat = random_params(8)
+    net.set_params(flat)
+    x, bits = make_input(SHAPE, 9)
+    rng = np.random.default_rng(10)
+    target = rng.standard_normal(SHAPE + (2,)).astype(np.float32) * 0.1
+    xd = torch.from_numpy(bits.view(np.int16)).to("cuda:0")
+    td = torch.from_numpy(target.ravel()).to("cuda:0")
+    layers = layers_of(flat)
+    state = {}
+    lr = 1e-3
+    V = int(np.prod(SHAPE))
+    for step in range(3):
+        loss = net.train_step(SHAPE, xd, td, lr)
+        # oracle: the same step in float64 from the same parameters
+        grads, lsum = None, 0.0
+        for b in range(SHAPE[0]):
+            y, acts = emulated_forward(layers, x[b])
+            d = y - target[b]
+            lsum += float(np.sum(d * d))
+            gb = emulated_backward(layers, acts, 2.0 * d / (2 * V))
+            grads = gb if grads is None else [{k: r[k] + q[k] for k in r} for r, q in zip(grads, gb)]
+        assert abs(loss - lsum / (2 * V)) <= 2e-3 * lsum / (2 * V), step
+        before = flat_of(layers)
+        conv.adam_step(layers, grads, state, lr)
+        after_gpu = net.get_params()
+        delta_ref = flat_of(layers) - before
+        delta_gpu = after_gpu - before
+        # Adam's steps are +-lr wherever the gradient is not tiny; entries
+        # whose gradient is near zero may take either sign
+        assert np.linalg.norm(delta_gpu - delta_ref) <= 0.1 * np.linalg.norm(delta_ref), step
+        layers = layers_of(after_gpu)  # continue both from the kernel's parameters
+    net.close()
+
+
+def test_learned_solve_converges_to_the_solution(ctx):
+    # pairs from one source, a short training run, then a solve of another
+    # source with the network tried first: the answer must be the FP64 one
+    prob = wl.small_problem((28, 26, 24), layer=4, ppw=10, inhomogeneous=True, seed=11, name="learn")
+    announce("learned solve")
+    P = mxp.Problem(ctx, prob)
+    n = prob.npts
+    o = P.default_opts()
+    o.precision = mxp.MXP_PREC_MIXED
+    f1 = to_dev(wl.delta_source(prob, (10, 12, 9)).ravel())
+    u1 = torch.zeros_like(f1)
+    maxp = 40
+    R = torch.zeros(maxp * n, dtype=torch.complex128, device="cuda:0")
+    Z = torch.zeros_like(R)
+    cnt, rn, zn, st = mxp.mxp_collect_pairs(P, o, f1, u1, R, Z, maxp)
+    assert st["status"] == mxp.MXP_OK and cnt == st["outer_its"] and cnt > 3
+    kappa = float(np.median(np.array(zn) / np.array(rn)))
+    rs = np.sqrt(n)
+    crop = (prob.n[0], prob.n[1], prob.n[2])
+    X = torch.empty(cnt * n * 8, dtype=torch.int16, device="cuda:0")
+    T = torch.empty(cnt * n * 2, dtype=torch.float32, device="cuda:0")
+    for k in range(cnt):
+        mxp.mxp_cnn_make_sample(P, R[k * n:(k + 1) * n], Z[k * n:(k + 1) * n], (0, 0, 0), crop, rs, rs / kappa,
+                                X[k * n * 8:(k + 1) * n * 8], T[k * n * 2:(k + 1) * n * 2])
+    net = mxp.Network(ctx, 12)
+    shape = (cnt, prob.n[2], prob.n[1], prob.n[0])
+    losses = [net.train_step(shape, X, T, 2e-3) for _ in range(60)]
+    assert losses[-1] < losses[0]
+    mxp.mxp_problem_set_learned(P, net, kappa)
+    f2 = wl.delta_source(prob, (17, 13, 14)).ravel()
+    f2d = to_dev(f2)
+    o.use_learned = 1
+    o.stall_ratio = 0.9
+    u2 = torch.zeros_like(f2d)
+    st = mxp.mxp_solve(P, o, f2d, u2)
+    assert st["status"] == mxp.MXP_OK and st["true_relres"] <= o.rtol
+    assert st["learned_its"] + st["fallbacks"] >= 1
+    # the learned form still reaches the complex-double solution
+    o.rtol = 1e-12
+    o.precision = mxp.MXP_PREC_FP64
+    u2.zero_()
+    st = mxp.mxp_solve(P, o, f2d, u2)
+    assert st["status"] == mxp.MXP_OK
+    assert rel(to_host(u2), krylov.direct_solve(prob, f2)) <= 1e-10
+    mxp.mxp_problem_set_learned(P, None, 1.0)
+    net.close()
+    P.close()
