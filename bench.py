@@ -191,13 +191,160 @@ def bench_layered_batch(args, torch, mxp, wl):
     ctx.close()
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def layered_model(wl, n, layer, seed):
+    h = 1.0 / (max(n) - 1)
+    c = wl.layered_speed(n, layer, 12, 1500.0, 4500.0, 2, seed)
+    return wl.Problem(f"3d-layered-{n[0]}", n, h, wl.omega_for(8, h), layer, c)
+
+
+def bench_learned(args, torch, mxp, wl):
+    """The learned stage: (residual, preconditioned residual) pairs from
+    MatExPre solves on seeded 128^3 layered models, 64^3 bf16 crops, Adam
+    training on the matrix-core kernels, then an unseen 256^3 layered model
+    solved with and without the network (mixed form, FGMRES(20))."""
+    rng = np.random.default_rng(55)
+    os.environ.setdefault("MXP_VERBOSE", "1")   # one line per outer iteration: progress
+    ctx = mxp.Context(0)
+    t_start = time.perf_counter()
+    # --- pairs
+    crops_in, crops_t = [], []
+    n_pairs = 0
+    crop = (64, 64, 64)
+    kappas = []
+    for mdl in range(args.train_models):
+        prob = layered_model(wl, (128, 128, 128), 16, 5000 + mdl)
+        P = mxp.Problem(ctx, prob)
+        o = P.default_opts()
+        o.precision = mxp.MXP_PREC_MIXED
+        o.outer_restart = 20
+        n = prob.npts
+        for src in range(2):
+            x = int(rng.integers(20, 108))
+            f = torch.from_numpy(wl.delta_source(prob, (x, 64, 18 + 40 * src)).ravel()).to("cuda:0")
+            u = torch.zeros_like(f)
+            maxp = 24
+            R = torch.zeros(maxp * n, dtype=torch.complex128, device="cuda:0")
+            Z = torch.zeros_like(R)
+            cnt, rn, zn, st = mxp.mxp_collect_pairs(P, o, f, u, R, Z, maxp)
+            kappas += [z / r for r, z in zip(rn, zn)]
+            kap = float(np.median(kappas))
+            rs = np.sqrt(n)
+            for k in range(cnt):
+                for _ in range(2):
+                    off = tuple(int(rng.integers(0, 128 - 64 + 1)) for _ in range(3))
+                    X = torch.empty(64 ** 3 * 8, dtype=torch.int16, device="cuda:0")
+                    T = torch.empty(64 ** 3 * 2, dtype=torch.float32, device="cuda:0")
+                    mxp.mxp_cnn_make_sample(P, R[k * n:(k + 1) * n], Z[k * n:(k + 1) * n], off, crop, rs, rs / kap,
+                                            X, T)
+                    crops_in.append(X)
+                    crops_t.append(T)
+            n_pairs += cnt
+            print(f"[bench] model {mdl} source {src}: {cnt} pairs, outer {st['outer_its']}, "
+                  f"{time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
+            del R, Z
+        P.close()
+    kappa = float(np.median(kappas))
+    t_data = time.perf_counter() - t_start
+    # --- training (batches of 4 crops)
+    X_all = torch.stack(crops_in)
+    T_all = torch.stack(crops_t)
+    net = mxp.Network(ctx, 7)
+    B = 4
+    shape = (B, 64, 64, 64)
+    losses = []
+    t1 = time.perf_counter()
+    for step in range(args.train_steps):
+        idx = torch.from_numpy(rng.choice(len(crops_in), size=B, replace=False)).to("cuda:0")
+        xb = X_all.index_select(0, idx).contiguous().view(-1)
+        tb = T_all.index_select(0, idx).contiguous().view(-1)
+        lr = 2e-3 if step < args.train_steps // 2 else 5e-4
+        losses.append(net.train_step(shape, xb, tb, lr))
+        if step % 50 == 0:
+            print(f"[bench] train step {step}: loss {losses[-1]:.4e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del X_all, T_all, crops_in, crops_t
+    # --- conv throughput at the evaluation size (inference forward)
+    test = layered_model(wl, (256, 256, 256), 20, 9999)
+    V = test.npts
+    xin = torch.zeros(V * 8, dtype=torch.int16, device="cuda:0")
+    out = torch.empty(V * 2, dtype=torch.float32, device="cuda:0")
+    vshape = (1, 256, 256, 256)
+    net.forward(vshape, xin, out)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(3):
+        net.forward(vshape, xin, out)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_fwd = ev0.elapsed_time(ev1) * 1e-3 / 3
+    # every layer runs as a 32-output-channel GEMM; algorithmic flops count the real channels
+    chans = (3, 32, 32, 32, 32, 32, 2)
+    flops = 2.0 * V * 27 * sum(a * b for a, b in zip(chans[:-1], chans[1:]))
+    del xin, out
+    # --- evaluation: plain mixed vs learned on the unseen model
+    P = mxp.Problem(ctx, test)
+    f = torch.from_numpy(wl.delta_source(test, (128, 128, 22)).ravel()).to("cuda:0")
+    u = torch.zeros_like(f)
+    o = P.default_opts()
+    o.precision = mxp.MXP_PREC_MIXED
+    o.outer_restart = 20
+    res = {}
+    print(f"[bench] network forward at 256^3: {t_fwd * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    for mode in ("plain", "learned"):
+        o.use_learned = 1 if mode == "learned" else 0
+        o.stall_ratio = 0.9
+        if mode == "learned":
+            mxp.mxp_problem_set_learned(P, net, kappa)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = mxp.mxp_solve(P, o, f, u)
+        torch.cuda.synchronize()
+        st["wall"] = time.perf_counter() - t0
+        res[mode] = st
+        print(f"[bench] {mode}: {st['wall']:.2f} s, outer {st['outer_its']}, learned {st['learned_its']}, "
+              f"fallbacks {st['fallbacks']}, relres {st['true_relres']:.2e}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "s to 1e-6 rel. residual (plain vs FP32/learned); stencil HBM GB/s vs peak",
+        "value": round(res["learned"]["wall"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(res["learned"]["wall"] * 1e3, 1), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 network + c64 stepping + c128 Krylov",
+        "data": "synthetic (seeded layered models, point sources); pairs generated by the solver",
+        "config": {"workload": "3d-learned", "train_grid": [128, 128, 128], "train_models": args.train_models,
+                   "pairs": n_pairs, "crops": 2 * n_pairs, "crop": list(crop), "train_steps": args.train_steps,
+                   "batch": B, "eval_grid": [256, 256, 256], "precision": "mixed", "outer_restart": 20,
+                   "stall_ratio": 0.9},
+        "learned": {k: res["learned"][k] for k in ("wall", "outer_its", "learned_its", "fallbacks", "inner_mean",
+                                                     "stencil_steps", "true_relres")},
+        "plain_mixed": {k: res["plain"][k] for k in ("wall", "outer_its", "inner_mean", "stencil_steps",
+                                                     "true_relres")},
+        "training": {"data_seconds": round(t_data, 1), "train_seconds": round(t_train, 1),
+                     "loss_first": losses[0], "loss_last": float(np.mean(losses[-20:])), "kappa": kappa},
+        "roofline": {"bound": "mfma", "achieved": round(flops / t_fwd / 1e12, 1), "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(flops / t_fwd / 1e12 / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_conv<32,*> (network forward, 6 layers, 256^3)",
+                     "forward_ms": round(t_fwd * 1e3, 3)},
+    }
+    print(json.dumps(line), flush=True)
+    mxp.mxp_problem_set_learned(P, None, 1.0)
+    net.close()
+    P.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d-grf-2048",
-                    choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256", "3d-layered-batch"])
+                    choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256", "3d-layered-batch", "3d-learned"])
+    ap.add_argument("--train-models", type=int, default=6, help="3d-learned: 128^3 training models")
+    ap.add_argument("--train-steps", type=int, default=400, help="3d-learned: Adam steps")
     ap.add_argument("--rhs", type=int, default=2,
                     help="3d-layered-batch: surface sources on the 512x512x256 grid (of 32)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
@@ -220,6 +367,9 @@ def main():
 
     if args.workload == "3d-layered-batch":
         bench_layered_batch(args, torch, mxp, wl)
+        return
+    if args.workload == "3d-learned":
+        bench_learned(args, torch, mxp, wl)
         return
     prob = {"2d-grf-2048": wl.config2, "2d-homog-128": wl.config1, "3d-homog-256": wl.config3}[args.workload]()
     centre = tuple(m // 2 for m in prob.n)

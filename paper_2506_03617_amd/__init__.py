@@ -131,6 +131,10 @@ ABI_SYMBOLS = (
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2506_03617_amd/build.py`")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch
+    # first makes the library bind to that one; loaded the other way round a
+    # process holds two HIP/HSA runtimes and the second one finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     st = ctypes.c_int

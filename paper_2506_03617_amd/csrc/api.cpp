@@ -1308,9 +1308,11 @@ mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out) {
         if (!out) fail(MXP_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
         int count = 0;
-        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        const hipError_t ce = hipGetDeviceCount(&count);
+        if (ce != hipSuccess || count <= 0) {
             (void)hipGetLastError();
-            fail(MXP_ERR_INVALID_ARG, "no HIP device available");
+            fail(MXP_ERR_INVALID_ARG, std::string("no HIP device available (") + hipGetErrorString(ce) +
+                                          ", count " + std::to_string(count) + ")");
         }
         if (device < 0 || device >= count) fail(MXP_ERR_INVALID_ARG, "no such device");
         HIP_CHECK(hipSetDevice(device));
