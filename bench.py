@@ -260,9 +260,9 @@ def bench_learned(args, torch, mxp, wl):
         idx = torch.from_numpy(rng.choice(len(crops_in), size=B, replace=False)).to("cuda:0")
         xb = X_all.index_select(0, idx).contiguous().view(-1)
         tb = T_all.index_select(0, idx).contiguous().view(-1)
-        lr = 2e-3 if step < args.train_steps // 2 else 5e-4
+        lr = 2e-3 if step < args.train_steps // 2 else (5e-4 if step < 3 * args.train_steps // 4 else 1.25e-4)
         losses.append(net.train_step(shape, xb, tb, lr))
-        if step % 50 == 0:
+        if step % 100 == 0:
             print(f"[bench] train step {step}: loss {losses[-1]:.4e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
@@ -291,12 +291,12 @@ def bench_learned(args, torch, mxp, wl):
     u = torch.zeros_like(f)
     o = P.default_opts()
     o.precision = mxp.MXP_PREC_MIXED
-    o.outer_restart = 20
+    o.outer_restart = args.eval_restart
     res = {}
     print(f"[bench] network forward at 256^3: {t_fwd * 1e3:.2f} ms", file=sys.stderr, flush=True)
     for mode in ("plain", "learned"):
         o.use_learned = 1 if mode == "learned" else 0
-        o.stall_ratio = 0.9
+        o.stall_ratio = 0.0   # cost-aware acceptance
         if mode == "learned":
             mxp.mxp_problem_set_learned(P, net, kappa)
         u.zero_()
@@ -316,8 +316,8 @@ def bench_learned(args, torch, mxp, wl):
         "data": "synthetic (seeded layered models, point sources); pairs generated by the solver",
         "config": {"workload": "3d-learned", "train_grid": [128, 128, 128], "train_models": args.train_models,
                    "pairs": n_pairs, "crops": 2 * n_pairs, "crop": list(crop), "train_steps": args.train_steps,
-                   "batch": B, "eval_grid": [256, 256, 256], "precision": "mixed", "outer_restart": 20,
-                   "stall_ratio": 0.9},
+                   "batch": B, "eval_grid": [256, 256, 256], "precision": "mixed", "outer_restart": args.eval_restart,
+                   "stall_ratio": "adaptive (0)"},
         "learned": {k: res["learned"][k] for k in ("wall", "outer_its", "learned_its", "fallbacks", "inner_mean",
                                                      "stencil_steps", "true_relres")},
         "plain_mixed": {k: res["plain"][k] for k in ("wall", "outer_its", "inner_mean", "stencil_steps",
@@ -344,7 +344,8 @@ def main():
     ap.add_argument("--workload", default="2d-grf-2048",
                     choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256", "3d-layered-batch", "3d-learned"])
     ap.add_argument("--train-models", type=int, default=6, help="3d-learned: 128^3 training models")
-    ap.add_argument("--train-steps", type=int, default=400, help="3d-learned: Adam steps")
+    ap.add_argument("--train-steps", type=int, default=1500, help="3d-learned: Adam steps")
+    ap.add_argument("--eval-restart", type=int, default=60, help="3d-learned: FGMRES restart of the evaluation")
     ap.add_argument("--rhs", type=int, default=2,
                     help="3d-layered-batch: surface sources on the 512x512x256 grid (of 32)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")

@@ -141,9 +141,10 @@ typedef struct {
     mxp_precision precision;
     int32_t cheb_S;         /* > 0 forces the number of Chebyshev substeps (0 = designed) */
     int32_t cheb_m;         /* > 0 forces the series degree per substep    (0 = designed) */
-    int32_t use_learned;    /* 1: learned network first at every outer iteration (see below) */
-    double stall_ratio;     /* learned z_j kept if the residual estimate drops below this
-                               factor times the previous one; default 0.9, in (0, 1] */
+    int32_t use_learned;    /* 1: learned network tried first at outer iterations (see below) */
+    double stall_ratio;     /* in [0, 1]: > 0 keeps a learned z_j if the residual estimate drops
+                               below this factor times the previous one; 0 (default) sets the
+                               factor from MatExPre's own reduction per second (see below) */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per
@@ -321,12 +322,16 @@ mxp_status mxp_collect_pairs(mxp_problem* prob, const mxp_solve_opts* opts, cons
 /* Attaches a network (not owned; NULL detaches) to a problem for solves with
  * opts.use_learned = 1.  The network sees v_j scaled to unit root-mean-square
  * value and its output, scaled back, is multiplied by out_scale (the typical
- * ||M(v)|| / ||v|| of the training pairs).  At each outer iteration z_j =
- * network(v_j) is kept if the Arnoldi residual estimate falls below
- * stall_ratio times the previous one; otherwise z_j = M(v_j) from MatExPre
- * (a fallback), and after two fallbacks in a row MatExPre alone finishes the
- * solve.  Convergence is judged by the complex-double true residual as
- * always.  Single solves only (mxp_solve_batch rejects use_learned). */
+ * ||M(v)|| / ||v|| of the training pairs).  At an outer iteration z_j =
+ * network(v_j) is kept if the Arnoldi residual estimate falls below a
+ * threshold times the previous one: stall_ratio if > 0, else exp(rate * T),
+ * rate = the mean log reduction per second of the MatExPre iterations so far
+ * and T = the time of the network try (a try is kept when it is at least as
+ * cost-effective as MatExPre).  Otherwise z_j = M(v_j) from MatExPre (a
+ * fallback); after two fallbacks in a row MatExPre alone is used until the
+ * next restart cycle.  The first outer iteration always uses MatExPre.
+ * Convergence is judged by the complex-double true residual as always.
+ * Single solves only (mxp_solve_batch rejects use_learned). */
 mxp_status mxp_problem_set_learned(mxp_problem* prob, mxp_cnn* net, double out_scale);
 
 #ifdef __cplusplus

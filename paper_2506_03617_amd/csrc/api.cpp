@@ -1125,8 +1125,8 @@ static void check_opts(const mxp_solve_opts* o) {
     if (o->precision != MXP_PREC_FP64 && o->precision != MXP_PREC_MIXED)
         fail(MXP_ERR_INVALID_ARG, "unknown precision");
     if (o->cheb_S < 0 || o->cheb_m < 0) fail(MXP_ERR_INVALID_ARG, "cheb_S, cheb_m must be >= 0");
-    if (o->use_learned && !(o->stall_ratio > 0 && o->stall_ratio <= 1))
-        fail(MXP_ERR_INVALID_ARG, "stall_ratio must be in (0, 1]");
+    if (o->use_learned && !(o->stall_ratio >= 0 && o->stall_ratio <= 1))
+        fail(MXP_ERR_INVALID_ARG, "stall_ratio must be in [0, 1]");
 }
 
 static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
@@ -1159,13 +1159,23 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
     }
     if (o.use_learned && !P->net) fail(MXP_ERR_INVALID_ARG, "use_learned needs a network (mxp_problem_set_learned)");
     if (o.use_learned && run.batch) fail(MXP_ERR_UNSUPPORTED, "the learned stage runs in single solves only");
-    bool use_net = o.use_learned != 0;
     int misses = 0;
+    // cost-aware acceptance: mean log residual reduction and wall time of the
+    // MatExPre iterations so far, wall time of the last network try
+    double m_log = 0.0, m_sec = 0.0, n_sec = 0.0;
+    int m_count = 0;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto secs = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+        return std::chrono::duration<double>(b - a).count();
+    };
     while (bnorm > 0.0 && beta > o.rtol * bnorm) {
         ++cycles;
         launch_scale({1.0 / beta, 0.0}, r, V, n, s);
         gv.reset(beta);
         double prev_res = beta;
+        // the network gets a fresh chance in every restart cycle
+        bool use_net = o.use_learned != 0;
+        misses = 0;
         int k = 0;
         bool est_ok = false;
         for (int j = 0; j < m; ++j) {
@@ -1173,18 +1183,31 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
             cpx<double>* zj = Z + size_t(j) * n;
             cpx<double>* vn = V + size_t(j + 1) * n;
             // Learned stage: try the network's z_j first and keep it when the
-            // Arnoldi residual estimate falls below stall_ratio times the
-            // previous one; otherwise (and for good after two misses in a
-            // row) the MatExPre preconditioner supplies z_j.
+            // Arnoldi residual estimate falls below a threshold times the
+            // previous one: stall_ratio when it is > 0, else the reduction
+            // that MatExPre's own iterations achieve on average in the time
+            // one network try takes (so a try is kept when it is at least as
+            // cost-effective).  Otherwise the MatExPre preconditioner
+            // supplies z_j; after two misses in a row it does so until the
+            // next restart cycle.  The first iteration of a solve always
+            // uses MatExPre (it calibrates the adaptive threshold).
             double hn = 0.0, res = 0.0;
             bool accepted = false;
-            if (use_net) {
+            const bool calibrated = o.stall_ratio > 0 || m_count > 0;
+            if (use_net && calibrated) {
+                const auto a0 = now();
                 learned_apply(run, vj, 1.0, zj);
                 apply_A64(P, s, 0.0, zj, vn, 1.0, nullptr, 0.0);
                 hn = cgs2(run, V, n, j + 1, vn, h);
+                n_sec = secs(a0, now());
                 Givens trial = gv;
                 res = trial.add_column(j, h, hn);
-                if (std::isfinite(res) && res <= o.stall_ratio * prev_res) {
+                double thr = o.stall_ratio;
+                if (thr <= 0) {
+                    const double rate = m_log / m_count / std::max(m_sec / m_count, 1e-9);  // log reduction per second
+                    thr = std::min(1.0, std::exp(rate * n_sec));
+                }
+                if (std::isfinite(res) && res <= thr * prev_res) {
                     gv = trial;
                     accepted = true;
                     cnt.learned++;
@@ -1195,6 +1218,7 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
                 }
             }
             if (!accepted) {
+                const auto a0 = now();
                 inner.push_back(precond(run, o, vj, zj, cnt));
                 if (run.pairs && run.pairs->count < run.pairs->max) {
                     PairSink& ps = *run.pairs;
@@ -1209,6 +1233,11 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
                 apply_A64(P, s, 0.0, zj, vn, 1.0, nullptr, 0.0);
                 hn = cgs2(run, V, n, j + 1, vn, h);
                 res = gv.add_column(j, h, hn);
+                if (res > 0 && prev_res > 0 && std::isfinite(res)) {
+                    m_log += std::log(res / prev_res);
+                    m_sec += secs(a0, now());
+                    ++m_count;
+                }
             }
             ++its;
             prev_res = res;
@@ -1394,7 +1423,7 @@ mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out
         out->max_inner = 300;
         out->precision = MXP_PREC_FP64;
         out->use_learned = 0;
-        out->stall_ratio = 0.9;
+        out->stall_ratio = 0.0;
         return MXP_OK;
     });
 }
