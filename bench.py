@@ -26,9 +26,17 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def kernel_source_hash() -> str:
+# Sources that determine each profiled kernel's code: a counter summary is
+# used only while these files are unchanged.
+KERNEL_SOURCES = {
+    "cheb2d": ("cheb2d.hip", "kernels.h"),
+    "stencil3d": ("kernels.hip", "kernels.h"),
+}
+
+
+def kernel_source_hash(family: str) -> str:
     h = hashlib.sha256()
-    for name in ("kernels.hip", "kernels.h", "cheb2d.hip"):
+    for name in KERNEL_SOURCES[family]:
         with open(os.path.join(ROOT, "paper_2506_03617_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -43,7 +51,8 @@ def load_traffic(kernel: str, workload: str):
     with open(path) as fh:
         data = json.load(fh)
     rec = data.get(f"{kernel}@{workload}")
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    family = kernel.split("_")[0]
+    if not rec or family not in KERNEL_SOURCES or rec.get("source_hash") != kernel_source_hash(family):
         return None
     return rec.get("bytes_per_launch")
 
@@ -200,6 +209,56 @@ def layered_model(wl, n, layer, seed):
     return wl.Problem(f"3d-layered-{n[0]}", n, h, wl.omega_for(8, h), layer, c)
 
 
+def network_flops(voxels: int) -> float:
+    """Algorithmic flops of one network forward (real channel counts)."""
+    chans = (3, 32, 32, 32, 32, 32, 2)
+    return 2.0 * voxels * 27 * sum(a * b for a, b in zip(chans[:-1], chans[1:]))
+
+
+def bench_network(args, torch, mxp):
+    """The network alone: forward passes at 256^3 and training steps on
+    4 x 64^3 crops (random weights and inputs), timed with HIP events on the
+    library's stream."""
+    ctx = mxp.Context(0)
+    net = mxp.Network(ctx, 3)
+    V = 256 ** 3
+    xin = torch.randint(0, 1 << 14, (V * 8,), dtype=torch.int16, device="cuda:0")
+    out = torch.empty(V * 2, dtype=torch.float32, device="cuda:0")
+    shape = (1, 256, 256, 256)
+    net.forward(shape, xin, out)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(args.roofline_reps, 1)
+    ev0.record()
+    for _ in range(reps):
+        net.forward(shape, xin, out)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_fwd = ev0.elapsed_time(ev1) * 1e-3 / reps
+    del xin, out
+    B = 4
+    tshape = (B, 64, 64, 64)
+    Vt = B * 64 ** 3
+    xt = torch.randint(0, 1 << 14, (Vt * 8,), dtype=torch.int16, device="cuda:0")
+    tt = torch.randn(Vt * 2, dtype=torch.float32, device="cuda:0")
+    net.train_step(tshape, xt, tt, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(tshape, xt, tt, 1e-4)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / reps
+    fl = network_flops(V)
+    line = {"workload": "network", "forward_256cube_ms": round(t_fwd * 1e3, 3),
+            "forward_TFLOPs": round(fl / t_fwd / 1e12, 1),
+            "train_step_4x64cube_ms": round(t_step * 1e3, 3),
+            "train_TFLOPs": round(3 * network_flops(Vt) / t_step / 1e12, 1),
+            "roofline": {"bound": "mfma", "achieved": round(fl / t_fwd / 1e12, 1), "peak": PEAK_BF16_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(fl / t_fwd / 1e12 / PEAK_BF16_TFLOPS, 4)}}
+    print(json.dumps(line), flush=True)
+    net.close()
+    ctx.close()
+
+
 def bench_learned(args, torch, mxp, wl):
     """The learned stage: (residual, preconditioned residual) pairs from
     MatExPre solves on seeded 128^3 layered models, 64^3 bf16 crops, Adam
@@ -207,6 +266,9 @@ def bench_learned(args, torch, mxp, wl):
     solved with and without the network (mixed form, FGMRES(20))."""
     rng = np.random.default_rng(55)
     os.environ.setdefault("MXP_VERBOSE", "1")   # one line per outer iteration: progress
+    if args.conv_only:
+        bench_network(args, torch, mxp)
+        return
     ctx = mxp.Context(0)
     t_start = time.perf_counter()
     # --- pairs
@@ -282,8 +344,7 @@ def bench_learned(args, torch, mxp, wl):
     torch.cuda.synchronize()
     t_fwd = ev0.elapsed_time(ev1) * 1e-3 / 3
     # every layer runs as a 32-output-channel GEMM; algorithmic flops count the real channels
-    chans = (3, 32, 32, 32, 32, 32, 2)
-    flops = 2.0 * V * 27 * sum(a * b for a, b in zip(chans[:-1], chans[1:]))
+    flops = network_flops(V)
     del xin, out
     # --- evaluation: plain mixed vs learned on the unseen model
     P = mxp.Problem(ctx, test)
@@ -346,6 +407,8 @@ def main():
     ap.add_argument("--train-models", type=int, default=6, help="3d-learned: 128^3 training models")
     ap.add_argument("--train-steps", type=int, default=1500, help="3d-learned: Adam steps")
     ap.add_argument("--eval-restart", type=int, default=60, help="3d-learned: FGMRES restart of the evaluation")
+    ap.add_argument("--conv-only", action="store_true",
+                    help="3d-learned: time the network alone (forward at 256^3, training steps on 4 x 64^3)")
     ap.add_argument("--rhs", type=int, default=2,
                     help="3d-layered-batch: surface sources on the 512x512x256 grid (of 32)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")

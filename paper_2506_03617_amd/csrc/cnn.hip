@@ -6,10 +6,10 @@
 // Convolution as an implicit GEMM: a wavefront owns 32 consecutive x voxels
 // of one output row and all 32 output channels (one 32 x 32 MFMA tile); the
 // K dimension runs over (tap, input channel).  A workgroup (four wavefronts)
-// computes a brick of 32 x 4 x 2 voxels from a zero-padded 34 x 6 x 4 input
-// halo and the layer's 27 x 32 x cin weights, both staged in LDS with a
-// padded channel stride so that the 16-byte operand reads of neighbouring
-// lanes fall in different banks.  MFMA lane layout (checked on the device):
+// computes bricks of 32 x 4 x 2 voxels from a zero-padded 34 x 6 x 4 input
+// halo; the layer's 27 x 32 x cin weights are staged in LDS once per
+// (persistent) workgroup.  Both use a padded channel stride so that the
+// 16-byte operand reads of neighbouring lanes fall in different banks.  MFMA lane layout (checked on the device):
 // A row i = lane % 32 with k = 8 (lane / 32) .. +7, B column j = lane % 32
 // with the same k, result register r holds row 8 (r / 4) + 4 (lane / 32) +
 // r % 4 of column lane % 32.
@@ -53,100 +53,106 @@ struct Bricks {
 template <int CIN, int MODE>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                              const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                             void* __restrict__ out, ConvShape s, Bricks nbk) {
+                                             void* __restrict__ out, ConvShape s, Bricks nbk, int nbricks) {
     constexpr int CS = CIN + 8;  // padded channel stride (16 bytes of spread)
     constexpr int CH = CIN / 8;  // 16-byte chunks per voxel
     __shared__ __attribute__((aligned(16))) uint16_t s_in[HZ * HY * HX * CS];
     __shared__ __attribute__((aligned(16))) uint16_t s_w[27 * 32 * CS];
     const int tid = threadIdx.x;
-    int b = blockIdx.x;
-    const int bxi = b % nbk.bx;
-    b /= nbk.bx;
-    const int byi = b % nbk.by;
-    b /= nbk.by;
-    const int bzi = b % nbk.bz;
-    const int vol = b / nbk.bz;
-    const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
-    const int64_t vbase = int64_t(vol) * s.nz * s.ny * s.nx;
-    for (int c = tid; c < HZ * HY * HX * CH; c += 256) {
-        const int ch = c % CH;
-        int v = c / CH;
-        const int hx = v % HX;
-        v /= HX;
-        const int hy = v % HY;
-        const int hz = v / HY;
-        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-        uint4 val = make_uint4(0u, 0u, 0u, 0u);
-        if (gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny && gz >= 0 && gz < s.nz)
-            val = *reinterpret_cast<const uint4*>(in + (vbase + (int64_t(gz) * s.ny + gy) * s.nx + gx) * CIN +
-                                                  ch * 8);
-        *reinterpret_cast<uint4*>(&s_in[((hz * HY + hy) * HX + hx) * CS + ch * 8]) = val;
-    }
+    // persistent: the weights are staged once, then the workgroup visits
+    // bricks blockIdx.x, blockIdx.x + gridDim.x, ...
     for (int c = tid; c < 27 * 32 * CH; c += 256) {
         const int ch = c % CH;
         const int row = c / CH;  // tap * 32 + output channel
         *reinterpret_cast<uint4*>(&s_w[row * CS + ch * 8]) =
             *reinterpret_cast<const uint4*>(w + int64_t(row) * CIN + ch * 8);
     }
-    __syncthreads();
     const int lane = tid & 63;
     const int wv = tid >> 6;  // output row y0 + wv of the brick
     const int i = lane & 31;
     const int kh = lane >> 5;
-    f32x16 acc0 = {}, acc1 = {};
-    if constexpr (CIN == 32) {
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
-            const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS + 8 * kh];
-            const uint16_t* a1p = a0p + HY * HX * CS;
-            const uint16_t* bp = &s_w[(tap * 32 + i) * CS + 8 * kh];
-#pragma unroll
-            for (int kb = 0; kb < 2; ++kb) {
-                const bf16x8 bw = ld8(bp + 16 * kb);
-                acc0 = mfma(ld8(a0p + 16 * kb), bw, acc0);
-                acc1 = mfma(ld8(a1p + 16 * kb), bw, acc1);
-            }
-        }
-    } else {
-        // eight channels: the two half-wavefronts take consecutive taps
-        for (int p = 0; p < 14; ++p) {
-            const int tap = 2 * p + kh;
-            bf16x8 bw = {}, a0 = {}, a1 = {};
-            if (tap < 27) {
-                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
-                const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS];
-                bw = ld8(&s_w[(tap * 32 + i) * CS]);
-                a0 = ld8(a0p);
-                a1 = ld8(a0p + HY * HX * CS);
-            }
-            acc0 = mfma(a0, bw, acc0);
-            acc1 = mfma(a1, bw, acc1);
-        }
-    }
     const int co = i;
-    const int y = y0 + wv;
-    if (y >= s.ny) return;
     float bco = 0.0f;
     if constexpr (MODE != CONV_MASK) bco = bias[co];
+    for (int brick = blockIdx.x; brick < nbricks; brick += gridDim.x) {
+        int b = brick;
+        const int bxi = b % nbk.bx;
+        b /= nbk.bx;
+        const int byi = b % nbk.by;
+        b /= nbk.by;
+        const int bzi = b % nbk.bz;
+        const int vol = b / nbk.bz;
+        const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
+        const int64_t vbase = int64_t(vol) * s.nz * s.ny * s.nx;
+        __syncthreads();  // the previous brick's operands are consumed
+        for (int c = tid; c < HZ * HY * HX * CH; c += 256) {
+            const int ch = c % CH;
+            int v = c / CH;
+            const int hx = v % HX;
+            v /= HX;
+            const int hy = v % HY;
+            const int hz = v / HY;
+            const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny && gz >= 0 && gz < s.nz)
+                val = *reinterpret_cast<const uint4*>(in + (vbase + (int64_t(gz) * s.ny + gy) * s.nx + gx) * CIN +
+                                                      ch * 8);
+            *reinterpret_cast<uint4*>(&s_in[((hz * HY + hy) * HX + hx) * CS + ch * 8]) = val;
+        }
+        __syncthreads();
+        f32x16 acc0 = {}, acc1 = {};
+        if constexpr (CIN == 32) {
+            for (int tap = 0; tap < 27; ++tap) {
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
+                const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS + 8 * kh];
+                const uint16_t* a1p = a0p + HY * HX * CS;
+                const uint16_t* bp = &s_w[(tap * 32 + i) * CS + 8 * kh];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int z = z0 + t;
-        if (z >= s.nz) break;
-        const f32x16 acc = t ? acc1 : acc0;
-        const int64_t rowbase = vbase + (int64_t(z) * s.ny + y) * s.nx;
+                for (int kb = 0; kb < 2; ++kb) {
+                    const bf16x8 bw = ld8(bp + 16 * kb);
+                    acc0 = mfma(ld8(a0p + 16 * kb), bw, acc0);
+                    acc1 = mfma(ld8(a1p + 16 * kb), bw, acc1);
+                }
+            }
+        } else {
+            // eight channels: the two half-wavefronts take consecutive taps
+            for (int p = 0; p < 14; ++p) {
+                const int tap = 2 * p + kh;
+                bf16x8 bw = {}, a0 = {}, a1 = {};
+                if (tap < 27) {
+                    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
+                    const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS];
+                    bw = ld8(&s_w[(tap * 32 + i) * CS]);
+                    a0 = ld8(a0p);
+                    a1 = ld8(a0p + HY * HX * CS);
+                }
+                acc0 = mfma(a0, bw, acc0);
+                acc1 = mfma(a1, bw, acc1);
+            }
+        }
+        const int y = y0 + wv;
+        if (y < s.ny) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int x = x0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-            if (x >= s.nx) continue;
-            const int64_t vox = rowbase + x;
-            if constexpr (MODE == CONV_BIAS_RELU) {
-                const float v = acc[r] + bco;
-                static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(v > 0.0f ? v : 0.0f);
-            } else if constexpr (MODE == CONV_BIAS_F32) {
-                if (co < 2) static_cast<float*>(out)[vox * 2 + co] = acc[r] + bco;
-            } else {
-                const bool on = bf16_value(mask[vox * 32 + co]) > 0.0f;
-                static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(on ? acc[r] : 0.0f);
+            for (int t = 0; t < 2; ++t) {
+                const int z = z0 + t;
+                if (z >= s.nz) break;
+                const f32x16 acc = t ? acc1 : acc0;
+                const int64_t rowbase = vbase + (int64_t(z) * s.ny + y) * s.nx;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int x = x0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                    if (x >= s.nx) continue;
+                    const int64_t vox = rowbase + x;
+                    if constexpr (MODE == CONV_BIAS_RELU) {
+                        const float v = acc[r] + bco;
+                        static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(v > 0.0f ? v : 0.0f);
+                    } else if constexpr (MODE == CONV_BIAS_F32) {
+                        if (co < 2) static_cast<float*>(out)[vox * 2 + co] = acc[r] + bco;
+                    } else {
+                        const bool on = bf16_value(mask[vox * 32 + co]) > 0.0f;
+                        static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(on ? acc[r] : 0.0f);
+                    }
+                }
             }
         }
     }
@@ -432,14 +438,31 @@ inline unsigned grid_for(int64_t n) { return unsigned((n + 255) / 256); }
 
 }  // namespace
 
+// Resident workgroups of the persistent convolution: one per CU (its LDS
+// footprint allows no more), a few rounds so that uneven brick costs even out.
+static int conv_groups() {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+            (void)hipGetLastError();
+            cus = 256;
+        }
+        cached = 2 * cus;
+    }
+    return cached;
+}
+
 void launch_conv(int cin, ConvMode mode, const uint16_t* in, const uint16_t* w, const float* bias,
                  const uint16_t* mask, void* out, const ConvShape& s, hipStream_t st) {
     Bricks nbk{(s.nx + BX - 1) / BX, (s.ny + BY - 1) / BY, (s.nz + BZ - 1) / BZ};
     const int64_t nb = int64_t(nbk.bx) * nbk.by * nbk.bz * s.nb;
     if (nb <= 0) return;
     if (nb > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "convolution grid too large");
-    const dim3 grid = dim3(unsigned(nb)), block = dim3(256);
-#define MXP_CONV(C, M) hipLaunchKernelGGL((k_conv<C, M>), grid, block, 0, st, in, w, bias, mask, out, s, nbk)
+    const int groups = int(nb < conv_groups() ? nb : conv_groups());
+    const dim3 grid = dim3(unsigned(groups)), block = dim3(256);
+    const int nbr = int(nb);
+#define MXP_CONV(C, M) hipLaunchKernelGGL((k_conv<C, M>), grid, block, 0, st, in, w, bias, mask, out, s, nbk, nbr)
     if (cin == 32) {
         if (mode == CONV_BIAS_RELU) MXP_CONV(32, CONV_BIAS_RELU);
         else if (mode == CONV_BIAS_F32) MXP_CONV(32, CONV_BIAS_F32);
