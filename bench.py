@@ -31,6 +31,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = {
     "cheb2d": ("cheb2d.hip", "kernels.h"),
     "stencil3d": ("kernels.hip", "kernels.h"),
+    "cheb3d": ("cheb3d.hip", "cheb3d.h", "kernels.h"),
 }
 
 
@@ -98,6 +99,7 @@ def measure_roofline(mxp, torch, P, prob, o, reps):
     ev1.record()
     torch.cuda.synchronize()
     t_action = ev0.elapsed_time(ev1) * 1e-3 / reps
+    t_full = t_action  # whole action (every launch)
     rd_D = 0 if prob.c is None else 4
     m = sch.m
     if prob.dim == 2:
@@ -117,26 +119,37 @@ def measure_roofline(mxp, torch, P, prob, o, reps):
         key = f"cheb2d_c64_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}"
         extra = {"levels_per_launch": K}
     else:
-        # unfused Clenshaw step k_stencil<float, 3>: one level per launch.  Per
-        # point: the first step reads x and writes b_{m-1}; the second reads
-        # b_{m-1}, x; every later step reads b_{k+1}, b_{k+2}, x; each reads D
-        # and writes one level (8 B per complex-float value)
+        # single-level z-marching sweep k_stencil3d<float, OPS>: one level per
+        # launch.  Per point: the first sweep reads x and writes b_{m-1}; the
+        # second reads b_{m-1}, x; every later one reads b_{k+1}, b_{k+2}, x;
+        # each reads D and writes one level (8 B per complex-float value).
         per_series = (16 + rd_D) + (24 + rd_D) + (m - 2) * (32 + rd_D)
         launches_per_series = m
         kernel = "k_stencil3d<float,OPS> (z-marching Clenshaw step)"
         key = "stencil3d_c64"
         extra = {"levels_per_launch": 1}
+        # the two-level pass (mxp_set_tiles K = 2) timed beside it
+        mxp.mxp_set_tiles(P, mxp.MXP_PREC_MIXED, 2, 1, 1)
+        mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)
+        ev0.record()
+        for _ in range(reps):
+            mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)
+        ev1.record()
+        torch.cuda.synchronize()
+        extra["two_level_pass_action_ms"] = round(ev0.elapsed_time(ev1) / reps, 3)
+        extra["single_level_action_ms"] = round(t_full * 1e3, 3)
+        mxp.mxp_set_tiles(P, mxp.MXP_PREC_MIXED, 0, 1, 32)
     launches = sch.S * launches_per_series
     bytes_per_launch = per_series * prob.npts / launches_per_series
     avg_launch_s = t_action / launches
     achieved = bytes_per_launch / avg_launch_s / 1e9
     # the same work as unfused Clenshaw steps (32 / 36 B per point per step)
-    unfused_equiv = (32 + rd_D) * prob.npts * sch.S * m / t_action / 1e9
+    unfused_equiv = (32 + rd_D) * prob.npts * sch.S * m / t_full / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(key, prob.name),
             "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "bytes_per_launch": round(bytes_per_launch), **extra,
-            "us_per_clenshaw_level": round(t_action / (sch.S * m) * 1e6, 3),
+            "us_per_clenshaw_level": round(t_full / (sch.S * m) * 1e6, 3),
             "unfused_step_equivalent_GBps": round(unfused_equiv, 1),
             "schedule_c64": {"S": sch.S, "m": m, "m_psi": sch.m_psi}}
 

@@ -232,7 +232,10 @@ mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, cons
  * next action); mxp_get_tiles reports it (K = 0 if not tuned yet) with the
  * measured microseconds per Clenshaw level (0 if fixed by the caller).
  * precision selects the complex-double (MXP_PREC_FP64) or complex-float
- * (MXP_PREC_MIXED) kernels.  Errors: INVALID_ARG. */
+ * (MXP_PREC_MIXED) kernels.  On 3D grids K = 2 selects passes of two
+ * Clenshaw levels (k_cheb3d) and any other value single-level z-marching
+ * sweeps, the default (measured faster at 256^3); NX and Ly are unused there.
+ * Errors: INVALID_ARG. */
 mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, int32_t NX, int32_t Ly);
 mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32_t* K, int32_t* NX,
                          int32_t* Ly, double* us_per_level);

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmatexpre.so")
 
-SOURCES = ["kernels.hip", "cheb2d.hip", "cnn.hip", "schedule.cpp", "api.cpp", "network.cpp"]
+SOURCES = ["kernels.hip", "cheb2d.hip", "cheb3d.hip", "cnn.hip", "schedule.cpp", "api.cpp", "network.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

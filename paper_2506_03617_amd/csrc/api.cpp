@@ -29,6 +29,7 @@
 #include <tuple>
 #include <vector>
 
+#include "cheb3d.h"
 #include "cnn_net.h"
 #include "devmem.h"
 #include "kernels.h"
@@ -313,9 +314,10 @@ static cd coef_at(const double* c, int k) { return cd(c[2 * k], c[2 * k + 1]); }
 // or into a list that a batched solve replays in lockstep with other actions.
 template <typename R>
 struct StepRec {
-    int kind;  // 0: stencil sweep (st); 1: temporally blocked 2D pass (cp, K, NX)
+    int kind;  // 0: stencil sweep (st); 1: temporally blocked 2D pass (cp, K, NX); 2: two-level 3D pass (c3)
     StencilArgs<R> st;
     ChebPassArgs<R> cp;
+    ChebPass3DArgs<R> c3;
     int K, NX;
 };
 
@@ -343,6 +345,16 @@ struct Emit {
             rec->push_back(r);
         } else {
             launch_cheb2d<R>(a, K, NX, s);
+        }
+    }
+    void pass3d(const ChebPass3DArgs<R>& a) const {
+        if (rec) {
+            StepRec<R> r{};
+            r.kind = 2;
+            r.c3 = a;
+            rec->push_back(r);
+        } else {
+            launch_cheb3d<R>(a, s);
         }
     }
 };
@@ -392,6 +404,77 @@ static void cheb_series(const Emit<R>& em, const StencilArgs<R>& base, const mxp
     a.e3 = to_cpx<R>(post);
     a.out = out;
     em.sweep(a);
+    *steps += m;
+}
+
+// The same series on a 3D grid with two Clenshaw levels per pass: levels
+// 0 .. m-1 in pairs (level q: c_{m-q} x + (q ? 2/hw : 0) S(L_{q-1}) - L_{q-2}),
+// an odd one left over and the final level (post, add) as single sweeps.
+// bufs: four scratch vectors distinct from x, add and out.
+template <typename R>
+static void cheb_series3d(const Emit<R>& em, const StencilArgs<R>& base, const mxp_schedule& sc, const double* coef,
+                          int m, const cpx<R>* x, cpx<R>* out, cpx<R>* const bufs[4], cd post, const cpx<R>* add,
+                          int64_t* steps) {
+    const double hw = sc.half_width;
+    ChebPass3DArgs<R> a{};
+    a.n0 = base.n0;
+    a.n1 = base.n1;
+    a.n2 = base.n2;
+    for (int d = 0; d < 3; ++d) {
+        a.alpha[d] = base.alpha[d];
+        a.beta[d] = base.beta[d];
+        a.gamma[d] = base.gamma[d];
+    }
+    a.D = base.D;
+    a.Dconst = base.Dconst;
+    a.Dref = base.Dref;
+    a.kD = base.kD;
+    a.x = x;
+    cheb3d_geometry<R>(a);
+    const cpx<R>* prevA = nullptr;  // L_{q-2}
+    const cpx<R>* prevB = nullptr;  // L_{q-1}
+    int q = 0, pair = 0;
+    while (q + 1 <= m - 1) {
+        a.cx[0] = to_cpx<R>(coef_at(coef, m - q));
+        a.g[0] = R(q == 0 ? 0.0 : 2.0 / hw);
+        a.cx[1] = to_cpx<R>(coef_at(coef, m - q - 1));
+        a.g[1] = R(2.0 / hw);
+        a.in0 = prevA;
+        a.in1 = prevB;
+        a.outA = bufs[2 * pair];
+        a.outB = bufs[2 * pair + 1];
+        em.pass3d(a);
+        prevA = a.outA;
+        prevB = a.outB;
+        pair ^= 1;
+        q += 2;
+    }
+    StencilArgs<R> st = base;
+    st.x = x;
+    if (q == m - 1) {
+        // one more plain level: c_{m-q} x + (q ? 2/hw : 0) S(L_{q-1}) - L_{q-2}
+        st.b1 = prevB ? prevB : x;
+        st.g = to_cpx<R>(cd(q == 0 ? 0.0 : 2.0 / hw, 0.0));
+        st.cx = to_cpx<R>(coef_at(coef, m - q));
+        st.b2 = prevA;
+        st.e2 = {R(-1), R(0)};
+        st.b3 = nullptr;
+        st.e3 = {R(0), R(0)};
+        st.out = bufs[2 * pair];
+        em.sweep(st);
+        prevA = prevB;
+        prevB = st.out;
+    }
+    // final level: post * (c_0 x + (1/hw) S(L_{m-1}) - L_{m-2}) + post * add
+    st.b1 = prevB ? prevB : x;
+    st.g = to_cpx<R>(prevB ? post / hw : cd(0.0, 0.0));
+    st.cx = to_cpx<R>(post * coef_at(coef, 0));
+    st.b2 = prevA;
+    st.e2 = to_cpx<R>(-post);
+    st.b3 = add;
+    st.e3 = to_cpx<R>(post);
+    st.out = out;
+    em.sweep(st);
     *steps += m;
 }
 
@@ -519,6 +602,8 @@ static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched
         pick(xin, b, &spare);
         if (fused) {
             cheb_series_fused<R>(P, em, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
+        } else if (P->g.dim == 3 && P->tiles[sizeof(R) == 4 ? 1 : 0].K == 2) {
+            cheb_series3d<R>(em, base, sc, coef, m, xin, out, b, post, add, steps);
         } else {
             cheb_series<R>(em, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
         }
@@ -855,28 +940,26 @@ class Batcher {
 
     struct Group {  // one batched 3D launch
         int prec;   // 0 double, 1 float
-        int ops;
+        int kind;   // 0 sweeps, 2 two-level passes
+        int ops;    // operand set / variant
         size_t jobs_off, lut_off;
         int64_t blocks;
     };
 
-    template <typename R>
-    static void add_jobs(std::vector<unsigned char>& buf, Group& g, const std::vector<const StencilArgs<R>*>& sw) {
-        // jobs, then the lookup table (one uint32 per 64 workgroups)
+    // jobs of one batched launch over grids of different sizes: the job
+    // array, then the lookup table with one uint32 per 64 workgroups
+    template <typename Job>
+    static void add_table(std::vector<unsigned char>& buf, Group& g, std::vector<Job>& jobs) {
         auto align = [&](size_t a) { buf.resize((buf.size() + a - 1) / a * a); };
-        align(256);
-        g.jobs_off = buf.size();
-        std::vector<Sweep3DJob<R>> jobs(sw.size());
         int64_t b0 = 0;
-        for (size_t q = 0; q < sw.size(); ++q) {
-            jobs[q].a = *sw[q];
-            jobs[q].geom = sweep3d_geometry(*sw[q]);
-            jobs[q].block0 = b0;
-            jobs[q].blocks = int64_t(jobs[q].geom.tiles_x) * jobs[q].geom.tiles_y * jobs[q].geom.zchunks;
-            b0 += (jobs[q].blocks + 63) / 64 * 64;
+        for (auto& j : jobs) {
+            j.block0 = b0;
+            b0 += (j.blocks + 63) / 64 * 64;
         }
         g.blocks = b0;
-        const size_t jb = jobs.size() * sizeof(Sweep3DJob<R>);
+        align(256);
+        g.jobs_off = buf.size();
+        const size_t jb = jobs.size() * sizeof(Job);
         buf.resize(buf.size() + jb);
         std::memcpy(buf.data() + g.jobs_off, jobs.data(), jb);
         align(256);
@@ -887,6 +970,27 @@ class Batcher {
                 lut[size_t(c)] = uint32_t(q);
         buf.resize(buf.size() + lut.size() * sizeof(uint32_t));
         std::memcpy(buf.data() + g.lut_off, lut.data(), lut.size() * sizeof(uint32_t));
+    }
+
+    template <typename R>
+    static void add_passes(std::vector<unsigned char>& buf, Group& g, const std::vector<const ChebPass3DArgs<R>*>& ps) {
+        std::vector<Cheb3DJob<R>> jobs(ps.size());
+        for (size_t q = 0; q < ps.size(); ++q) {
+            jobs[q].a = *ps[q];
+            jobs[q].blocks = int64_t(ps[q]->tiles_x) * ps[q]->tiles_y * ps[q]->zchunks;
+        }
+        add_table(buf, g, jobs);
+    }
+
+    template <typename R>
+    static void add_jobs(std::vector<unsigned char>& buf, Group& g, const std::vector<const StencilArgs<R>*>& sw) {
+        std::vector<Sweep3DJob<R>> jobs(sw.size());
+        for (size_t q = 0; q < sw.size(); ++q) {
+            jobs[q].a = *sw[q];
+            jobs[q].geom = sweep3d_geometry(*sw[q]);
+            jobs[q].blocks = int64_t(jobs[q].geom.tiles_x) * jobs[q].geom.tiles_y * jobs[q].geom.zchunks;
+        }
+        add_table(buf, g, jobs);
     }
 
     void execute(std::vector<ActionReq*>& reqs) {
@@ -912,20 +1016,36 @@ class Batcher {
         for (size_t k = 0; k < L; ++k) {
             std::map<int, std::vector<const StencilArgs<double>*>> g64;
             std::map<int, std::vector<const StencilArgs<float>*>> g32;
+            std::map<int, std::vector<const ChebPass3DArgs<double>*>> p64;
+            std::map<int, std::vector<const ChebPass3DArgs<float>*>> p32;
             for (size_t i = 0; i < nq; ++i) {
                 if (k < r64[i].size() && r64[i][k].kind == 0 && r64[i][k].st.dim == 3)
                     g64[sweep_ops(r64[i][k].st)].push_back(&r64[i][k].st);
                 if (k < r32[i].size() && r32[i][k].kind == 0 && r32[i][k].st.dim == 3)
                     g32[sweep_ops(r32[i][k].st)].push_back(&r32[i][k].st);
+                if (k < r64[i].size() && r64[i][k].kind == 2)
+                    p64[cheb3d_variant(r64[i][k].c3)].push_back(&r64[i][k].c3);
+                if (k < r32[i].size() && r32[i][k].kind == 2)
+                    p32[cheb3d_variant(r32[i][k].c3)].push_back(&r32[i][k].c3);
             }
             for (auto& kv : g64) {
-                Group g{0, kv.first, 0, 0, 0};
+                Group g{0, 0, kv.first, 0, 0, 0};
                 add_jobs<double>(buf, g, kv.second);
                 plan[k].push_back(g);
             }
             for (auto& kv : g32) {
-                Group g{1, kv.first, 0, 0, 0};
+                Group g{1, 0, kv.first, 0, 0, 0};
                 add_jobs<float>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+            for (auto& kv : p64) {
+                Group g{0, 2, kv.first, 0, 0, 0};
+                add_passes<double>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+            for (auto& kv : p32) {
+                Group g{1, 2, kv.first, 0, 0, 0};
+                add_passes<float>(buf, g, kv.second);
                 plan[k].push_back(g);
             }
         }
@@ -944,28 +1064,34 @@ class Batcher {
         }
         const unsigned char* dev = table_.as<unsigned char>();
         for (size_t k = 0; k < L; ++k) {
-            // launches that are not batched: 2D passes and 2D sweeps
+            // launches that are not batched: 2D passes and 2D sweeps (3D
+            // sweeps and 3D passes go out in the grouped launches below)
             for (size_t i = 0; i < nq; ++i) {
                 if (k < r64[i].size()) {
                     const StepRec<double>& r = r64[i][k];
                     if (r.kind == 1) launch_cheb2d<double>(r.cp, r.K, r.NX, s_);
-                    else if (r.st.dim != 3) launch_stencil(r.st, s_);
+                    else if (r.kind == 0 && r.st.dim != 3) launch_stencil(r.st, s_);
                 }
                 if (k < r32[i].size()) {
                     const StepRec<float>& r = r32[i][k];
                     if (r.kind == 1) launch_cheb2d<float>(r.cp, r.K, r.NX, s_);
-                    else if (r.st.dim != 3) launch_stencil(r.st, s_);
+                    else if (r.kind == 0 && r.st.dim != 3) launch_stencil(r.st, s_);
                 }
             }
             for (const Group& g : plan[k]) {
-                if (g.prec == 0)
+                const uint32_t* lut = reinterpret_cast<const uint32_t*>(dev + g.lut_off);
+                if (g.kind == 2 && g.prec == 0)
+                    launch_cheb3d_batch<double>(reinterpret_cast<const Cheb3DJob<double>*>(dev + g.jobs_off), lut,
+                                                g.blocks, g.ops, s_);
+                else if (g.kind == 2)
+                    launch_cheb3d_batch<float>(reinterpret_cast<const Cheb3DJob<float>*>(dev + g.jobs_off), lut,
+                                               g.blocks, g.ops, s_);
+                else if (g.prec == 0)
                     launch_stencil3d_batch<double>(reinterpret_cast<const Sweep3DJob<double>*>(dev + g.jobs_off),
-                                                   reinterpret_cast<const uint32_t*>(dev + g.lut_off), g.blocks,
-                                                   g.ops, s_);
+                                                   lut, g.blocks, g.ops, s_);
                 else
-                    launch_stencil3d_batch<float>(reinterpret_cast<const Sweep3DJob<float>*>(dev + g.jobs_off),
-                                                  reinterpret_cast<const uint32_t*>(dev + g.lut_off), g.blocks,
-                                                  g.ops, s_);
+                    launch_stencil3d_batch<float>(reinterpret_cast<const Sweep3DJob<float>*>(dev + g.jobs_off), lut,
+                                                  g.blocks, g.ops, s_);
                 ++launches_;
             }
         }

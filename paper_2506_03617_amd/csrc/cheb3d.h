@@ -1,0 +1,50 @@
+// Two-level Clenshaw passes on 3D grids (internal).
+#pragma once
+
+#include "kernels.h"
+
+namespace mxp {
+
+// Two consecutive Clenshaw levels in one pass over a 3D grid:
+//   L_0 = cx[0] x + g[0] S(in1) - in0,   L_1 = cx[1] x + g[1] S(L_0) - in1,
+// S the stencil of StencilArgs (unscaled tables, the centre folded into
+// gamma, kD (D - Dref) per node); in0 / in1 = nullptr read as zero.  Writes
+// L_0 to outA and L_1 to outB; outputs must not alias any input.  Geometry
+// (cheb3d_geometry): tiles of 62 x 8 output columns x rows, chunks of zc
+// planes; a workgroup of ten wavefronts also recomputes L_0 on a one-node
+// halo in x and y and one plane in z on each side.
+template <typename R>
+struct ChebPass3DArgs {
+    int64_t n0, n1, n2;
+    const cpx<R>* alpha[3];
+    const cpx<R>* beta[3];
+    const cpx<R>* gamma[3];
+    const R* D;
+    R Dconst, Dref;
+    cpx<R> kD;
+    const cpx<R>* x;
+    const cpx<R>* in0;
+    const cpx<R>* in1;
+    cpx<R>* outA;
+    cpx<R>* outB;
+    cpx<R> cx[2];
+    R g[2];
+    int tiles_x, tiles_y, zchunks, zc;
+};
+template <typename R>
+void cheb3d_geometry(ChebPass3DArgs<R>& a);
+template <typename R>
+int cheb3d_variant(const ChebPass3DArgs<R>& a);  // 1: D present, 2: in0, 4: in1
+template <typename R>
+void launch_cheb3d(const ChebPass3DArgs<R>& a, hipStream_t s);
+// Batched form over grids of different sizes (same variant): as Sweep3DJob.
+template <typename R>
+struct Cheb3DJob {
+    ChebPass3DArgs<R> a;
+    int64_t block0, blocks;
+};
+template <typename R>
+void launch_cheb3d_batch(const Cheb3DJob<R>* jobs, const uint32_t* lut, int64_t total_blocks, int variant,
+                         hipStream_t s);
+
+}  // namespace mxp

@@ -58,11 +58,16 @@ def run_batch(ctx, handles, opts, rhs, max_resident=0):
     return status, stats, [to_host(u).reshape(f.shape) for u, f in zip(u_list, rhs)]
 
 
+@pytest.mark.parametrize("two_level", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_equals_separate_solves_bit_for_bit(ctx, prec):
+def test_batch_equals_separate_solves_bit_for_bit(ctx, prec, two_level):
     probs, rhs = uneven_set()
-    announce("batch vs separate", prec)
+    announce("batch vs separate", prec, two_level)
     handles = [mxp.Problem(ctx, p) for p in probs]
+    if two_level:  # the 3D grids run two-level passes (batched k_cheb3d)
+        for h, p in zip(handles, probs):
+            if p.dim == 3:
+                mxp.mxp_set_tiles(h, prec, 2, 1, 1)
     opts = []
     for h in handles:
         o = h.default_opts()

@@ -253,3 +253,25 @@ def test_autotuned_tiles_are_recorded(ctx):
     mxp.mxp_apply_exp(P, prob.default_t(), prob.default_shift(), xd, yd)
     tiles = mxp.mxp_get_tiles(P, 1)
     assert 1 <= tiles["K"] <= 8 and tiles["NX"] in (1, 2) and tiles["us_per_level"] > 0
+
+
+@pytest.mark.parametrize("name", ["3d-homog", "3d-inh", "3d-ragged"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_level_3d_passes(ctx, name, prec):
+    # the two-level 3D pass (tiles K = 2): chunks of 16 planes, 62 x 8 tiles
+    # with ragged edges, odd and even series degrees through exp and psi_1
+    prob = make(name)
+    announce("3d two-level passes", name, prec)
+    P = mxp.Problem(ctx, prob)
+    mxp.mxp_set_tiles(P, prec, 2, 1, 1)
+    t, s = prob.default_t(), prob.default_shift()
+    x = wl.random_vector(prob.npts, 9)
+    tdt = torch.complex128 if prec == 0 else torch.complex64
+    xd = to_dev(x, tdt)
+    yd = torch.empty_like(xd)
+    As = op.helmholtz(prob, s)
+    tol = 1e-11 if prec == 0 else 1e-5
+    mxp.mxp_apply_exp(P, t, s, xd, yd)
+    assert rel(to_host(yd), matfun.exp_action(As, t, to_host(xd))) <= tol
+    mxp.mxp_apply_psi1(P, t, s, xd, yd)
+    assert rel(to_host(yd), matfun.phi1_action(As, t, to_host(xd))) <= tol
