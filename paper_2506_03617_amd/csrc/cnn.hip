@@ -274,6 +274,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
     }
 }
 
+// gW = sum over groups of the partials, in a fixed order: eight interleaved
+// double partial sums per element (independent loads in flight), combined
+// in order.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int groups, int cout,
                                                       int cin, float* __restrict__ gW) {
     const int idx = blockIdx.x * 256 + threadIdx.x;  // (co, ci, tap) in the master layout
@@ -281,9 +284,19 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     const int tap = idx % 27;
     const int ci = (idx / 27) % cin;
     const int co = idx / (27 * cin);
-    double acc = 0.0;
-    for (int g = 0; g < groups; ++g) acc += partial[(int64_t(g) * 27 * 32 + tap * 32 + co) * 32 + ci];
-    gW[idx] = float(acc);
+    const int64_t off = (int64_t(tap) * 32 + co) * 32 + ci;
+    const int64_t stride = int64_t(27) * 32 * 32;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int g = 0;
+    for (; g + 8 <= groups; g += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += partial[(g + q) * stride + off];
+    }
+    for (int q = 0; g + q < groups; ++q) acc[q] += partial[(g + q) * stride + off];
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += acc[q];
+    gW[idx] = float(t);
 }
 
 // ------------------------------------------------------ small training kernels
@@ -308,12 +321,21 @@ __global__ __launch_bounds__(256) void k_bias_partial(const uint16_t* __restrict
     }
 }
 
-__global__ void k_bias_reduce(const float* __restrict__ partial, int groups, int cout, float* __restrict__ gb) {
-    const int co = threadIdx.x;
-    if (co >= cout) return;
+// gb[co] = sum over groups of the partials: one workgroup per channel, a
+// fixed-order tree over 256 strided partial sums.
+__global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ partial, int groups, int cout,
+                                                     float* __restrict__ gb) {
+    __shared__ double red[256];
+    const int co = blockIdx.x;
     double acc = 0.0;
-    for (int g = 0; g < groups; ++g) acc += partial[g * 32 + co];
-    gb[co] = float(acc);
+    for (int g = threadIdx.x; g < groups; g += 256) acc += partial[g * 32 + co];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && co < cout) gb[co] = float(red[0]);
 }
 
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, const float* __restrict__ target,
@@ -508,7 +530,7 @@ void launch_wgrad_reduce(const float* partial, int groups, int cout, int cin, fl
 void launch_bias_grad(const uint16_t* G, int cg, int cout, int64_t V, float* partial, float* gb, hipStream_t st) {
     const int groups = int(V / 8 + 1 < kRedGroups ? V / 8 + 1 : kRedGroups);
     hipLaunchKernelGGL(k_bias_partial, dim3(groups), dim3(256), 0, st, G, cg, V, partial);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(32), 0, st, partial, groups, cout, gb);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(cout), dim3(256), 0, st, partial, groups, cout, gb);
     check_launch("bias gradient");
 }
 
