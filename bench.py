@@ -427,6 +427,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-reps", type=int, default=3)
+    ap.add_argument("--graphs", action="store_true", help="replay matrix-function actions from HIP graphs")
     ap.add_argument("--tiles", default=None,
                     help="K,NX,Ly of the fused 2D passes for both precisions (default: autotuned)")
     ap.add_argument("--roofline-only", action="store_true",
@@ -461,6 +462,7 @@ def main():
     ud = torch.zeros_like(fd)
     o_mixed = P.default_opts()
     o_mixed.precision = mxp.MXP_PREC_MIXED
+    o_mixed.use_graphs = 1 if args.graphs else 0
     if prob.dim == 3:
         o_mixed.outer_restart = 20   # FGMRES(20) for the 3D workloads
     if args.tiles:
@@ -535,7 +537,8 @@ def main():
         "config": {"workload": prob.name, "grid": list(prob.n), "omega": round(prob.omega, 3),
                    "layer": prob.layer, "t": o_mixed.t, "shift": o_mixed.shift, "fprtol": o_mixed.fprtol,
                    "rtol": o_mixed.rtol, "outer_restart": o_mixed.outer_restart,
-                   "inner_restart": o_mixed.inner_restart, "precision": "mixed"},
+                   "inner_restart": o_mixed.inner_restart, "precision": "mixed",
+                   "graphs": bool(args.graphs)},
         "solve": {k: st[k] for k in ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions",
                                      "true_relres")} if st else None,
         "plain_fp64": fp64,

@@ -145,6 +145,9 @@ typedef struct {
     double stall_ratio;     /* in [0, 1]: > 0 keeps a learned z_j if the residual estimate drops
                                below this factor times the previous one; 0 (default) sets the
                                factor from MatExPre's own reduction per second (see below) */
+    int32_t use_graphs;     /* 1: each exp / psi_1 action is captured into a HIP graph on its
+                               second use and replayed afterwards (single solves; the
+                               results are identical); 0 (default): launched directly */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per

@@ -68,6 +68,7 @@ class mxp_solve_opts(ctypes.Structure):
         ("cheb_m", ctypes.c_int32),
         ("use_learned", ctypes.c_int32),
         ("stall_ratio", ctypes.c_double),
+        ("use_graphs", ctypes.c_int32),
     ]
 
 

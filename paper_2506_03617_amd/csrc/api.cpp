@@ -80,12 +80,47 @@ struct TileCfg {
 // Device workspace of one solve: Krylov bases, matrix-function buffers and
 // reduction scratch.  A problem owns one for its single-solve calls; a
 // batched solve gives every right-hand side its own.
+// A matrix-function action captured into a HIP graph (fixed input and
+// output buffers of the workspace), replayed on the workspace's own stream.
+struct GraphEntry {
+    int uses = 0;  // the first use runs eagerly (allocations, tile tuning)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t steps = 0;  // Clenshaw levels per replay
+};
+
 struct Workspace {
-    DevMem act64[8], act32[10];  // [0..5] pass/substep buffers, [6] psi addend, (f32) [7..8] casts
+    // [0..5] pass/substep buffers, [6] psi addend, (f64) [7..8] graph input /
+    // output, (f32) [7..8] casts
+    DevMem act64[9], act32[10];
     DevMem innerV, innerRh, innerTmp, innerRr;
     DevMem outerV, outerZ, outerR;
     DevMem partial, small;
     std::vector<cpx<double>> host_small;
+    // captured actions, keyed by (schedule, psi, precision); the stream they
+    // replay on and the events that order it with the solve's stream
+    std::map<std::tuple<const void*, int, int>, GraphEntry> graphs;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    Workspace() = default;
+    Workspace(const Workspace&) = delete;
+    Workspace& operator=(const Workspace&) = delete;
+    void drop_graphs() {
+        for (auto& kv : graphs) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+        }
+        graphs.clear();
+    }
+    ~Workspace() {
+        drop_graphs();
+        if (gstream) {
+            (void)hipStreamSynchronize(gstream);
+            (void)hipStreamDestroy(gstream);
+        }
+        for (hipEvent_t e : gev)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 class Batcher;
@@ -109,6 +144,7 @@ struct Run {
     Batcher* batch;
     hipEvent_t ev;  // batched runs: marks the action input ready on s
     PairSink* pairs = nullptr;
+    bool graphs = false;  // replay matrix-function actions from captured HIP graphs
 };
 
 }  // namespace mxp
@@ -667,8 +703,9 @@ static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
-    const int Ks[] = {2, 3, 4, 6, 8};
-    const int Lys[] = {16, 32, 64, 128};
+    // short segments and single levels give small grids enough wavefronts
+    const int Ks[] = {1, 2, 3, 4, 6, 8};
+    const int Lys[] = {4, 8, 16, 32, 64, 128};
     for (int NX = 1; NX <= 2; ++NX) {
         for (int K : Ks) {
             if (sizeof(R) == 8 && NX == 2 && K > 3) continue;  // register-limited
@@ -849,6 +886,68 @@ static void action64_on(mxp_problem* P, Workspace& ws, hipStream_t s, const Sche
 
 static void action64(Run& run, const Sched& sc, double t, double shift, bool psi, mxp_precision prec,
                      const cpx<double>* x, cpx<double>* y, int64_t* steps);
+
+// The same action from a captured HIP graph.  The graph reads a fixed input
+// buffer and writes a fixed output buffer of the workspace (the mixed form's
+// cast buffers, or two complex-double staging buffers), so one capture per
+// (schedule, psi, precision) serves every call: the input is staged, the
+// graph replays on the workspace's stream (ordered after and before the
+// caller's stream by events) and the output is copied out.  The first use of
+// a key runs eagerly (it allocates the buffers and tunes the tiles), the
+// second captures.  Kernels only: nothing in an action is a memset or a copy.
+static void action64_graph(mxp_problem* P, Workspace& ws, hipStream_t s, const Sched& sc, double t, double shift,
+                           bool psi, mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps) {
+    const int64_t n = npts(P);
+    const bool f32 = prec != MXP_PREC_FP64;
+    DevMem* in = f32 ? &ws.act32[7] : &ws.act64[7];
+    DevMem* out = f32 ? &ws.act32[8] : &ws.act64[8];
+    const size_t bytes = size_t(n) * (f32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
+    in->ensure(bytes);
+    out->ensure(bytes);
+    if (f32) launch_to_c64(x, in->as<cpx<float>>(), n, s);
+    else launch_scale({1.0, 0.0}, x, in->as<cpx<double>>(), n, s);
+    auto run_action = [&](hipStream_t st, int64_t* cnt) {
+        if (f32)
+            action<float>(P, ws, Emit<float>{st, nullptr}, sc, t, shift, psi, in->as<cpx<float>>(),
+                          out->as<cpx<float>>(), cnt);
+        else
+            action<double>(P, ws, Emit<double>{st, nullptr}, sc, t, shift, psi, in->as<cpx<double>>(),
+                           out->as<cpx<double>>(), cnt);
+    };
+    GraphEntry& ge = ws.graphs[std::make_tuple(static_cast<const void*>(&sc), int(psi), int(prec))];
+    if (ge.uses++ == 0) {
+        run_action(s, steps);
+    } else {
+        if (!ws.gstream) {
+            HIP_CHECK(hipStreamCreateWithFlags(&ws.gstream, hipStreamNonBlocking));
+            HIP_CHECK(hipEventCreateWithFlags(&ws.gev[0], hipEventDisableTiming));
+            HIP_CHECK(hipEventCreateWithFlags(&ws.gev[1], hipEventDisableTiming));
+        }
+        HIP_CHECK(hipEventRecord(ws.gev[0], s));
+        HIP_CHECK(hipStreamWaitEvent(ws.gstream, ws.gev[0], 0));
+        if (!ge.exec) {
+            int64_t cnt = 0;
+            HIP_CHECK(hipStreamBeginCapture(ws.gstream, hipStreamCaptureModeThreadLocal));
+            try {
+                run_action(ws.gstream, &cnt);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(ws.gstream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HIP_CHECK(hipStreamEndCapture(ws.gstream, &ge.graph));
+            HIP_CHECK(hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+            ge.steps = cnt;
+        }
+        HIP_CHECK(hipGraphLaunch(ge.exec, ws.gstream));
+        *steps += ge.steps;
+        HIP_CHECK(hipEventRecord(ws.gev[1], ws.gstream));
+        HIP_CHECK(hipStreamWaitEvent(s, ws.gev[1], 0));
+    }
+    if (f32) launch_to_c128(out->as<cpx<float>>(), y, n, s);
+    else launch_scale({1.0, 0.0}, out->as<cpx<double>>(), y, n, s);
+}
 
 // ------------------------------------------------------------ batched actions
 //
@@ -1122,7 +1221,10 @@ class Batcher {
 static void action64(Run& run, const Sched& sc, double t, double shift, bool psi, mxp_precision prec,
                      const cpx<double>* x, cpx<double>* y, int64_t* steps) {
     if (!run.batch) {
-        action64_on(run.P, *run.W, run.s, sc, t, shift, psi, prec, x, y, steps);
+        if (run.graphs)
+            action64_graph(run.P, *run.W, run.s, sc, t, shift, psi, prec, x, y, steps);
+        else
+            action64_on(run.P, *run.W, run.s, sc, t, shift, psi, prec, x, y, steps);
         return;
     }
     ActionReq r;
@@ -1157,6 +1259,7 @@ static void learned_apply(Run& run, const cpx<double>* v, double vnorm, cpx<doub
 // Algorithm 1.  r, w: complex double device vectors.
 static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt) {
     mxp_problem* P = run.P;
+    run.graphs = o.use_graphs != 0 && !run.batch;
     Workspace& WS = *run.W;
     const int64_t n = npts(P);
     hipStream_t s = run.s;
@@ -1550,6 +1653,7 @@ mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out
         out->precision = MXP_PREC_FP64;
         out->use_learned = 0;
         out->stall_ratio = 0.0;
+        out->use_graphs = 0;
         return MXP_OK;
     });
 }
@@ -1643,6 +1747,8 @@ mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, 
         if (K < 0 || K > kMaxFused || (NX != 1 && NX != 2) || Ly < 1 || (K > 0 && NX * 64 - 2 * K <= 0))
             fail(MXP_ERR_INVALID_ARG, "tiles: K in 0..8, NX in {1, 2}, Ly >= 1");
         TileCfg& t = prob->tiles[precision == MXP_PREC_MIXED ? 1 : 0];
+        (void)hipStreamSynchronize(prob->ctx->stream);
+        prob->ws.drop_graphs();  // captured actions bake in the tile shape
         t.K = K;
         t.NX = NX;
         t.Ly = Ly;

@@ -275,3 +275,36 @@ def test_two_level_3d_passes(ctx, name, prec):
     assert rel(to_host(yd), matfun.exp_action(As, t, to_host(xd))) <= tol
     mxp.mxp_apply_psi1(P, t, s, xd, yd)
     assert rel(to_host(yd), matfun.phi1_action(As, t, to_host(xd))) <= tol
+
+
+@pytest.mark.parametrize("name", ["2d-inh", "3d-inh"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replayed_actions_match_direct_launches(ctx, name, prec):
+    # every exp / psi_1 action after the first of its kind replays a captured
+    # HIP graph, with the solver's own eager kernels and synchronisations in
+    # between; solutions and statistics must equal the directly launched solve
+    prob = make(name)
+    announce("graphs", name, prec)
+    P = mxp.Problem(ctx, prob)
+    centre = tuple(m // 2 for m in prob.n)
+    fd = to_dev(wl.delta_source(prob, centre).ravel())
+    o = P.default_opts()
+    o.precision = prec
+    ud = torch.zeros_like(fd)
+    ref = mxp.mxp_solve(P, o, fd, ud)
+    u_ref = ud.clone()
+    o.use_graphs = 1
+    for _ in range(2):
+        ud.zero_()
+        st = mxp.mxp_solve(P, o, fd, ud)
+        assert torch.equal(ud, u_ref)
+        for key in ("outer_its", "inner_its_total", "stencil_steps", "fn_actions", "true_relres"):
+            assert st[key] == ref[key], key
+    r = to_dev(wl.random_vector(prob.npts, 21))
+    w_ref = torch.empty_like(r)
+    o.use_graphs = 0
+    its = mxp.mxp_apply_precond(P, o, r, w_ref)
+    o.use_graphs = 1
+    w = torch.empty_like(r)
+    assert mxp.mxp_apply_precond(P, o, r, w) == its
+    assert torch.equal(w, w_ref)
