@@ -300,6 +300,14 @@ void mxp_cnn_destroy(mxp_cnn* net);
 mxp_status mxp_cnn_get_params(const mxp_cnn* net, float* host);
 mxp_status mxp_cnn_set_params(mxp_cnn* net, const float* host);
 mxp_status mxp_cnn_get_grads(const mxp_cnn* net, float* host);
+/* Checkpoint: writes the parameters and the Adam state (step count and both
+ * moments) to the host file path, or reads them back into a network, so that
+ * training resumes exactly where it stopped.  The file starts with a tag and
+ * the channel list; load rejects another architecture, a short or long file
+ * (INVALID_ARG) and non-finite values (NONFINITE) before it touches the
+ * network.  Errors: INVALID_ARG (also an unopenable path), NONFINITE, HIP. */
+mxp_status mxp_cnn_save(const mxp_cnn* net, const char* path);
+mxp_status mxp_cnn_load(mxp_cnn* net, const char* path);
 /* out = network(in). */
 mxp_status mxp_cnn_forward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
                            float* out);

@@ -125,7 +125,7 @@ ABI_SYMBOLS = (
     "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
     "mxp_cnn_num_params", "mxp_cnn_create", "mxp_cnn_destroy", "mxp_cnn_get_params", "mxp_cnn_set_params",
     "mxp_cnn_get_grads", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
-    "mxp_collect_pairs", "mxp_problem_set_learned",
+    "mxp_collect_pairs", "mxp_problem_set_learned", "mxp_cnn_save", "mxp_cnn_load",
 )
 
 
@@ -167,6 +167,8 @@ def _load():
         "mxp_cnn_get_params": (st, [P, P]),
         "mxp_cnn_set_params": (st, [P, P]),
         "mxp_cnn_get_grads": (st, [P, P]),
+        "mxp_cnn_save": (st, [P, ctypes.c_char_p]),
+        "mxp_cnn_load": (st, [P, ctypes.c_char_p]),
         "mxp_cnn_forward": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]),
         "mxp_cnn_backward": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]),
         "mxp_cnn_train_step": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
@@ -410,6 +412,14 @@ class Network:
         a = np.empty(self.num_params(), dtype=np.float32)
         _check(lib.mxp_cnn_get_grads(self.handle, a.ctypes.data))
         return a
+
+    def save(self, path) -> None:
+        """Parameters and Adam state to a checkpoint file."""
+        _check(lib.mxp_cnn_save(self.handle, os.fsencode(path)))
+
+    def load(self, path) -> None:
+        """Parameters and Adam state from a checkpoint file."""
+        _check(lib.mxp_cnn_load(self.handle, os.fsencode(path)))
 
     def forward(self, shape, x, out) -> None:
         nb, nz, ny, nx = shape

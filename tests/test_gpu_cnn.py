@@ -185,6 +185,41 @@ def test_training_steps_match_oracle_adam(ctx):
     net.close()
 
 
+def test_checkpoint_resumes_training_exactly(ctx, tmp_path):
+    announce("cnn checkpoint")
+    x, bits = make_input(SHAPE, 21)
+    rng = np.random.default_rng(22)
+    target = rng.standard_normal(SHAPE + (2,)).astype(np.float32) * 0.1
+    xd = torch.from_numpy(bits.view(np.int16)).to("cuda:0")
+    td = torch.from_numpy(target.ravel()).to("cuda:0")
+    a = mxp.Network(ctx, 31)
+    for _ in range(2):
+        a.train_step(SHAPE, xd, td, 1e-3)
+    path = tmp_path / "net.ckpt"
+    a.save(path)
+    b = mxp.Network(ctx, 32)
+    before = b.get_params()
+    # damaged files are rejected and leave the network as it was
+    raw = path.read_bytes()
+    for bad in (raw[:-4], raw + b"\0", b"XXXXXXXX" + raw[8:]):
+        (tmp_path / "bad.ckpt").write_bytes(bad)
+        with pytest.raises(mxp.MxpError):
+            b.load(tmp_path / "bad.ckpt")
+    assert np.array_equal(b.get_params(), before)
+    with pytest.raises(mxp.MxpError):
+        b.load(tmp_path / "missing.ckpt")
+    b.load(path)
+    assert np.array_equal(b.get_params(), a.get_params())
+    # the Adam state travels too: the next steps agree bit for bit
+    for _ in range(2):
+        la = a.train_step(SHAPE, xd, td, 1e-3)
+        lb = b.train_step(SHAPE, xd, td, 1e-3)
+        assert la == lb
+        assert np.array_equal(a.get_params(), b.get_params())
+    a.close()
+    b.close()
+
+
 def test_learned_solve_converges_to_the_solution(ctx):
     # pairs from one source, a short training run, then a solve of another
     # source with the network tried first: the answer must be the FP64 one
