@@ -73,7 +73,8 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
     const int kh = lane >> 5;
     const int co = i;
     float bco = 0.0f;
-    if constexpr (MODE != CONV_MASK) bco = bias[co];
+    if constexpr (MODE == CONV_BIAS_RELU) bco = bias[co];
+    if constexpr (MODE == CONV_BIAS_F32) bco = co < 2 ? bias[co < 2 ? co : 0] : 0.0f;  // two output channels
     for (int brick = blockIdx.x; brick < nbricks; brick += gridDim.x) {
         int b = brick;
         const int bxi = b % nbk.bx;
@@ -154,6 +155,234 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
                     }
                 }
             }
+        }
+    }
+}
+
+// ------------------------------------- z-marching convolution, 32 input channels
+//
+// A workgroup of four wavefronts owns a column of 32 x 8 output voxels (x, y)
+// over a segment of z planes and marches along z.  Input plane p, with a
+// one-voxel halo in x and y (34 x 10 voxels), is staged in LDS, double
+// buffered: the next plane's loads are issued before the current plane's
+// products and written to the other buffer after them.  Input plane p feeds
+// output planes p + 1, p and p - 1 (taps dz = 0, 1, 2), held in three
+// accumulators that rotate with the plane (the plane loop is unrolled by
+// three, so the rotation is compile-time); after plane p, output plane p - 1
+// is complete.  Wavefront w computes output rows 2w and 2w + 1, one 32 x 32
+// tile each (output channels x voxels): the weights are the MFMA A operand
+// and the activations B.  Per plane it reads its 24 activation fragments
+// (input rows 2w .. 2w + 3, three x shifts, two 16-channel halves) once and
+// streams the 54 weight fragments, each used for both rows, so the LDS
+// operand traffic is 78 reads per 108 products.  The weights (27 x 32 x 32)
+// stay in LDS for all the segments a (persistent) workgroup visits.
+constexpr int ZX = 32, ZY = 8;                  // output voxels per column
+constexpr int ZHX = ZX + 2, ZHY = ZY + 2;       // staged plane with halo
+constexpr int ZCS = 40;                         // padded channel stride (bf16)
+constexpr int ZPLANE = ZHX * ZHY * ZCS;         // bf16 per staged plane
+constexpr int ZCHUNKS = ZHX * ZHY * 4;          // 16-byte chunks per plane
+constexpr int ZLOADS = (ZCHUNKS + 255) / 256;   // chunks per thread
+
+struct ZMarch {
+    int tx, ty, zsegs, Lz;  // columns in x and y, segments per volume, planes per segment
+};
+
+template <int MODE>
+struct ZConv {
+    const uint16_t* in;
+    ConvShape s;
+    int x0, y0, vol, za, zb;
+    int64_t vbase;
+    int lane, wv, j, kh;
+    f32x16 acc[2][3];
+    uint4 stg[ZLOADS];
+
+    // Loads of input plane p (zero outside the volume); every address is
+    // clamped into the volume, so the loads are unconditional.
+    __device__ __forceinline__ void issue(int p, int tid) {
+        const bool pin = p >= 0 && p < s.nz;
+        const int pc = p < 0 ? 0 : (p >= s.nz ? s.nz - 1 : p);
+#pragma unroll
+        for (int q = 0; q < ZLOADS; ++q) {
+            const int c = tid + 256 * q;
+            const int cc = c < ZCHUNKS ? c : ZCHUNKS - 1;
+            const int ch = cc & 3, v = cc >> 2;
+            const int hx = v % ZHX, hy = v / ZHX;
+            const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+            const bool ok = pin && gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny;
+            const int gxc = gx < 0 ? 0 : (gx >= s.nx ? s.nx - 1 : gx);
+            const int gyc = gy < 0 ? 0 : (gy >= s.ny ? s.ny - 1 : gy);
+            const uint4 val =
+                *reinterpret_cast<const uint4*>(in + (vbase + (int64_t(pc) * s.ny + gyc) * s.nx + gxc) * 32 + ch * 8);
+            stg[q] = ok ? val : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+    __device__ __forceinline__ void commit(uint16_t* slot, int tid) {
+#pragma unroll
+        for (int q = 0; q < ZLOADS; ++q) {
+            const int c = tid + 256 * q;
+            if (c < ZCHUNKS) {
+                const int ch = c & 3, v = c >> 2;
+                *reinterpret_cast<uint4*>(&slot[v * ZCS + ch * 8]) = stg[q];
+            }
+        }
+    }
+
+    // Products of one tap plane dz with the staged activations B: output
+    // plane p + 1 - dz, accumulator slot (PH - dz) mod 3.
+    template <int PH, int DZ>
+    __device__ __forceinline__ void tap_plane(const bf16x8 (&B)[4][3][2], const uint16_t* s_w) {
+        constexpr int SL = (PH - DZ + 3) % 3;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    const int tap = DZ * 9 + dy * 3 + dx;
+                    const bf16x8 a = ld8(s_w + (tap * 32 + j) * ZCS + 16 * kb + 8 * kh);
+                    acc[0][SL] = mfma(a, B[dy][dx][kb], acc[0][SL]);
+                    acc[1][SL] = mfma(a, B[dy + 1][dx][kb], acc[1][SL]);
+                }
+    }
+
+    // Products of the staged plane in `slot` (phase PH of the rotation).
+    template <int PH>
+    __device__ __forceinline__ void products(const uint16_t* slot, const uint16_t* s_w) {
+        bf16x8 B[4][3][2];
+#pragma unroll
+        for (int hr = 0; hr < 4; ++hr)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+                    B[hr][dx][kb] = ld8(slot + ((2 * wv + hr) * ZHX + j + dx) * ZCS + 16 * kb + 8 * kh);
+        tap_plane<PH, 0>(B, s_w);
+        tap_plane<PH, 1>(B, s_w);
+        tap_plane<PH, 2>(B, s_w);
+    }
+
+    // Output plane z from accumulator slot SL, then the slot is cleared.
+    template <int SL>
+    __device__ __forceinline__ void emit(int z, const float (&bco)[16], const uint16_t* mask, void* out) {
+        if (z >= za && z < zb) {
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+                const int y = y0 + 2 * wv + rr, x = x0 + j;
+                if (y < s.ny && x < s.nx) {
+                    const int64_t vox = vbase + (int64_t(z) * s.ny + y) * s.nx + x;
+                    const f32x16& a = acc[rr][SL];
+                    if constexpr (MODE == CONV_BIAS_F32) {
+                        if (kh == 0) {
+                            float2 o;
+                            o.x = a[0] + bco[0];
+                            o.y = a[1] + bco[1];
+                            *reinterpret_cast<float2*>(static_cast<float*>(out) + vox * 2) = o;
+                        }
+                    } else {
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int64_t off = vox * 32 + 8 * g + 4 * kh;
+                            uint16_t h[4];
+                            if constexpr (MODE == CONV_BIAS_RELU) {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const float v = a[4 * g + e] + bco[4 * g + e];
+                                    h[e] = bf16_bits(v > 0.0f ? v : 0.0f);
+                                }
+                            } else {
+                                const uint2 mk = *reinterpret_cast<const uint2*>(mask + off);
+                                const uint16_t m[4] = {uint16_t(mk.x & 0xffffu), uint16_t(mk.x >> 16),
+                                                       uint16_t(mk.y & 0xffffu), uint16_t(mk.y >> 16)};
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    h[e] = bf16_bits(bf16_value(m[e]) > 0.0f ? a[4 * g + e] : 0.0f);
+                            }
+                            uint2 pk;
+                            pk.x = uint32_t(h[0]) | (uint32_t(h[1]) << 16);
+                            pk.y = uint32_t(h[2]) | (uint32_t(h[3]) << 16);
+                            *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + off) = pk;
+                        }
+                    }
+                }
+            }
+        }
+        acc[0][SL] = f32x16{};
+        acc[1][SL] = f32x16{};
+    }
+
+    // Input plane p = za - 1 + t (phase PH = t mod 3): issue the next plane's
+    // loads, take the products, emit output plane p - 1, stage the next plane.
+    template <int PH>
+    __device__ __forceinline__ void plane(int t, int T, uint16_t* s_in, const uint16_t* s_w, const float (&bco)[16],
+                                          const uint16_t* mask, void* out, int tid) {
+        const int p = za - 1 + t;
+        const bool more = t + 1 < T;
+        if (more) issue(p + 1, tid);
+        products<PH>(s_in + (t & 1) * ZPLANE, s_w);
+        emit<(PH + 1) % 3>(p - 1, bco, mask, out);
+        if (more) commit(s_in + ((t + 1) & 1) * ZPLANE, tid);
+        __syncthreads();
+    }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv_zm(
+    const uint16_t* __restrict__ in, const uint16_t* __restrict__ w, const float* __restrict__ bias,
+    const uint16_t* __restrict__ mask, void* __restrict__ out, ConvShape s, ZMarch zm, int nseg) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[27 * 32 * ZCS];
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[2 * ZPLANE];
+    const int tid = threadIdx.x;
+    for (int c = tid; c < 27 * 32 * 4; c += 256) {
+        const int ch = c & 3, row = c >> 2;
+        *reinterpret_cast<uint4*>(&s_w[row * ZCS + ch * 8]) =
+            *reinterpret_cast<const uint4*>(w + int64_t(row) * 32 + ch * 8);
+    }
+    ZConv<MODE> zc;
+    zc.in = in;
+    zc.s = s;
+    zc.lane = tid & 63;
+    zc.wv = tid >> 6;
+    zc.j = zc.lane & 31;
+    zc.kh = zc.lane >> 5;
+    // bias of the output channels this lane holds, 8 (r / 4) + 4 kh + r % 4
+    // (the last layer has two)
+    float bco[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int co = 8 * (r >> 2) + 4 * zc.kh + (r & 3);
+        bco[r] = 0.0f;
+        if constexpr (MODE == CONV_BIAS_RELU) bco[r] = bias[co];
+        if constexpr (MODE == CONV_BIAS_F32) bco[r] = co < 2 ? bias[co < 2 ? co : 0] : 0.0f;
+    }
+    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        int b = seg;
+        const int bx = b % zm.tx;
+        b /= zm.tx;
+        const int by = b % zm.ty;
+        b /= zm.ty;
+        const int zs = b % zm.zsegs;
+        zc.vol = b / zm.zsegs;
+        zc.x0 = bx * ZX;
+        zc.y0 = by * ZY;
+        zc.za = zs * zm.Lz;
+        zc.zb = zc.za + zm.Lz < s.nz ? zc.za + zm.Lz : s.nz;
+        zc.vbase = int64_t(zc.vol) * s.nz * s.ny * s.nx;
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) zc.acc[rr][q] = f32x16{};
+        // input planes za - 1 .. zb
+        const int T = zc.zb - zc.za + 2;
+        zc.issue(zc.za - 1, tid);
+        zc.commit(s_in, tid);
+        __syncthreads();
+        for (int t = 0; t < T; t += 3) {
+            zc.template plane<0>(t, T, s_in, s_w, bco, mask, out, tid);
+            if (t + 1 >= T) break;
+            zc.template plane<1>(t + 1, T, s_in, s_w, bco, mask, out, tid);
+            if (t + 2 >= T) break;
+            zc.template plane<2>(t + 2, T, s_in, s_w, bco, mask, out, tid);
         }
     }
 }
@@ -475,6 +704,34 @@ static int conv_groups() {
     return cached;
 }
 
+// Columns of 32 x 8 voxels, each split along z into as few segments as give
+// every compute unit one (the kernel's LDS allows one workgroup per unit).
+static void launch_conv_zm(ConvMode mode, const uint16_t* in, const uint16_t* w, const float* bias, const uint16_t* mask,
+                           void* out, const ConvShape& s, hipStream_t st) {
+    ZMarch zm;
+    zm.tx = (s.nx + ZX - 1) / ZX;
+    zm.ty = (s.ny + ZY - 1) / ZY;
+    const int64_t cols = int64_t(zm.tx) * zm.ty * s.nb;
+    if (cols <= 0 || s.nz <= 0) return;
+    const int units = conv_groups() / 2;
+    int64_t zsegs = (units + cols - 1) / cols;
+    const int64_t zmax = (s.nz + 3) / 4;  // at least four planes per segment
+    if (zsegs > zmax) zsegs = zmax;
+    if (zsegs < 1) zsegs = 1;
+    zm.Lz = int((s.nz + zsegs - 1) / zsegs);
+    zm.zsegs = (s.nz + zm.Lz - 1) / zm.Lz;
+    const int64_t nseg = cols * zm.zsegs;
+    if (nseg > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "convolution grid too large");
+    const dim3 grid(unsigned(nseg < units ? nseg : units)), block(256);
+    const int ns = int(nseg);
+    if (mode == CONV_BIAS_RELU)
+        hipLaunchKernelGGL((k_conv_zm<CONV_BIAS_RELU>), grid, block, 0, st, in, w, bias, mask, out, s, zm, ns);
+    else if (mode == CONV_BIAS_F32)
+        hipLaunchKernelGGL((k_conv_zm<CONV_BIAS_F32>), grid, block, 0, st, in, w, bias, mask, out, s, zm, ns);
+    else
+        hipLaunchKernelGGL((k_conv_zm<CONV_MASK>), grid, block, 0, st, in, w, bias, mask, out, s, zm, ns);
+}
+
 void launch_conv(int cin, ConvMode mode, const uint16_t* in, const uint16_t* w, const float* bias,
                  const uint16_t* mask, void* out, const ConvShape& s, hipStream_t st) {
     Bricks nbk{(s.nx + BX - 1) / BX, (s.ny + BY - 1) / BY, (s.nz + BZ - 1) / BZ};
@@ -486,9 +743,7 @@ void launch_conv(int cin, ConvMode mode, const uint16_t* in, const uint16_t* w, 
     const int nbr = int(nb);
 #define MXP_CONV(C, M) hipLaunchKernelGGL((k_conv<C, M>), grid, block, 0, st, in, w, bias, mask, out, s, nbk, nbr)
     if (cin == 32) {
-        if (mode == CONV_BIAS_RELU) MXP_CONV(32, CONV_BIAS_RELU);
-        else if (mode == CONV_BIAS_F32) MXP_CONV(32, CONV_BIAS_F32);
-        else MXP_CONV(32, CONV_MASK);
+        launch_conv_zm(mode, in, w, bias, mask, out, s, st);
     } else if (cin == 8) {
         if (mode == CONV_BIAS_RELU) MXP_CONV(8, CONV_BIAS_RELU);
         else if (mode == CONV_BIAS_F32) MXP_CONV(8, CONV_BIAS_F32);

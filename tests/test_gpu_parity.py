@@ -219,18 +219,20 @@ def test_argument_errors(ctx):
         mxp.mxp_apply_exp(P, -1.0, 0.1, xd, torch.zeros_like(xd))
 
 
+@pytest.mark.parametrize("Ly", [13, 4])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("NX", [1, 2])
 @pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 6, 7, 8])
-def test_fused_passes_every_tile_shape(ctx, K, NX, prec):
+def test_fused_passes_every_tile_shape(ctx, K, NX, prec, Ly):
     # every level count a final pass can have, both lane widths, segments that
-    # do not divide the grid (67 x 45 with Ly = 13), against the oracle
+    # do not divide the grid (67 x 45 with Ly = 13) and segments shorter than
+    # the halo (Ly = 4), against the oracle
     if prec == 0 and NX == 2 and K > 3:
         pytest.skip("register-limited shape, never selected")
     prob = make("2d-inh")
-    announce("fused tiles", K, NX, prec)
+    announce("fused tiles", K, NX, prec, Ly)
     P = mxp.Problem(ctx, prob)
-    mxp.mxp_set_tiles(P, prec, K, NX, 13)
+    mxp.mxp_set_tiles(P, prec, K, NX, Ly)
     t, s = prob.default_t(), prob.default_shift()
     x = wl.random_vector(prob.npts, 8)
     tdt = torch.complex128 if prec == 0 else torch.complex64
