@@ -3,16 +3,11 @@
 // kernels of training (loss, bias gradient, Adam, weight packing) and of
 // moving residuals in and out of the network.
 //
-// Convolution as an implicit GEMM: a wavefront owns 32 consecutive x voxels
-// of one output row and all 32 output channels (one 32 x 32 MFMA tile); the
-// K dimension runs over (tap, input channel).  A workgroup (four wavefronts)
-// computes bricks of 32 x 4 x 2 voxels from a zero-padded 34 x 6 x 4 input
-// halo; the layer's 27 x 32 x cin weights are staged in LDS once per
-// (persistent) workgroup.  Both use a padded channel stride so that the
-// 16-byte operand reads of neighbouring lanes fall in different banks.  MFMA lane layout (checked on the device):
-// A row i = lane % 32 with k = 8 (lane / 32) .. +7, B column j = lane % 32
-// with the same k, result register r holds row 8 (r / 4) + 4 (lane / 32) +
-// r % 4 of column lane % 32.
+// Convolution as an implicit GEMM over (tap, input channel), marching along z
+// (k_conv_zm below).  MFMA lane layout (checked on the device): A row i =
+// lane % 32 with k = 8 (lane / 32) .. +7, B column j = lane % 32 with the
+// same k, result register r holds row 8 (r / 4) + 4 (lane / 32) + r % 4 of
+// column lane % 32.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -41,125 +36,7 @@ inline void check_launch(const char* what) {
     if (e != hipSuccess) fail(MXP_ERR_HIP, std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
 }
 
-// ------------------------------------------------------------- convolution
-
-constexpr int BX = 32, BY = 4, BZ = 2;
-constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
-
-struct Bricks {
-    int bx, by, bz;
-};
-
-template <int CIN, int MODE>
-__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
-                                             const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                             void* __restrict__ out, ConvShape s, Bricks nbk, int nbricks) {
-    constexpr int CS = CIN + 8;  // padded channel stride (16 bytes of spread)
-    constexpr int CH = CIN / 8;  // 16-byte chunks per voxel
-    __shared__ __attribute__((aligned(16))) uint16_t s_in[HZ * HY * HX * CS];
-    __shared__ __attribute__((aligned(16))) uint16_t s_w[27 * 32 * CS];
-    const int tid = threadIdx.x;
-    // persistent: the weights are staged once, then the workgroup visits
-    // bricks blockIdx.x, blockIdx.x + gridDim.x, ...
-    for (int c = tid; c < 27 * 32 * CH; c += 256) {
-        const int ch = c % CH;
-        const int row = c / CH;  // tap * 32 + output channel
-        *reinterpret_cast<uint4*>(&s_w[row * CS + ch * 8]) =
-            *reinterpret_cast<const uint4*>(w + int64_t(row) * CIN + ch * 8);
-    }
-    const int lane = tid & 63;
-    const int wv = tid >> 6;  // output row y0 + wv of the brick
-    const int i = lane & 31;
-    const int kh = lane >> 5;
-    const int co = i;
-    float bco = 0.0f;
-    if constexpr (MODE == CONV_BIAS_RELU) bco = bias[co];
-    if constexpr (MODE == CONV_BIAS_F32) bco = co < 2 ? bias[co < 2 ? co : 0] : 0.0f;  // two output channels
-    for (int brick = blockIdx.x; brick < nbricks; brick += gridDim.x) {
-        int b = brick;
-        const int bxi = b % nbk.bx;
-        b /= nbk.bx;
-        const int byi = b % nbk.by;
-        b /= nbk.by;
-        const int bzi = b % nbk.bz;
-        const int vol = b / nbk.bz;
-        const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
-        const int64_t vbase = int64_t(vol) * s.nz * s.ny * s.nx;
-        __syncthreads();  // the previous brick's operands are consumed
-        for (int c = tid; c < HZ * HY * HX * CH; c += 256) {
-            const int ch = c % CH;
-            int v = c / CH;
-            const int hx = v % HX;
-            v /= HX;
-            const int hy = v % HY;
-            const int hz = v / HY;
-            const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-            uint4 val = make_uint4(0u, 0u, 0u, 0u);
-            if (gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny && gz >= 0 && gz < s.nz)
-                val = *reinterpret_cast<const uint4*>(in + (vbase + (int64_t(gz) * s.ny + gy) * s.nx + gx) * CIN +
-                                                      ch * 8);
-            *reinterpret_cast<uint4*>(&s_in[((hz * HY + hy) * HX + hx) * CS + ch * 8]) = val;
-        }
-        __syncthreads();
-        f32x16 acc0 = {}, acc1 = {};
-        if constexpr (CIN == 32) {
-            for (int tap = 0; tap < 27; ++tap) {
-                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
-                const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS + 8 * kh];
-                const uint16_t* a1p = a0p + HY * HX * CS;
-                const uint16_t* bp = &s_w[(tap * 32 + i) * CS + 8 * kh];
-#pragma unroll
-                for (int kb = 0; kb < 2; ++kb) {
-                    const bf16x8 bw = ld8(bp + 16 * kb);
-                    acc0 = mfma(ld8(a0p + 16 * kb), bw, acc0);
-                    acc1 = mfma(ld8(a1p + 16 * kb), bw, acc1);
-                }
-            }
-        } else {
-            // eight channels: the two half-wavefronts take consecutive taps
-            for (int p = 0; p < 14; ++p) {
-                const int tap = 2 * p + kh;
-                bf16x8 bw = {}, a0 = {}, a1 = {};
-                if (tap < 27) {
-                    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap - 3 * (tap / 3);
-                    const uint16_t* a0p = &s_in[((dz * HY + wv + dy) * HX + i + dx) * CS];
-                    bw = ld8(&s_w[(tap * 32 + i) * CS]);
-                    a0 = ld8(a0p);
-                    a1 = ld8(a0p + HY * HX * CS);
-                }
-                acc0 = mfma(a0, bw, acc0);
-                acc1 = mfma(a1, bw, acc1);
-            }
-        }
-        const int y = y0 + wv;
-        if (y < s.ny) {
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int z = z0 + t;
-                if (z >= s.nz) break;
-                const f32x16 acc = t ? acc1 : acc0;
-                const int64_t rowbase = vbase + (int64_t(z) * s.ny + y) * s.nx;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int x = x0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                    if (x >= s.nx) continue;
-                    const int64_t vox = rowbase + x;
-                    if constexpr (MODE == CONV_BIAS_RELU) {
-                        const float v = acc[r] + bco;
-                        static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(v > 0.0f ? v : 0.0f);
-                    } else if constexpr (MODE == CONV_BIAS_F32) {
-                        if (co < 2) static_cast<float*>(out)[vox * 2 + co] = acc[r] + bco;
-                    } else {
-                        const bool on = bf16_value(mask[vox * 32 + co]) > 0.0f;
-                        static_cast<uint16_t*>(out)[vox * 32 + co] = bf16_bits(on ? acc[r] : 0.0f);
-                    }
-                }
-            }
-        }
-    }
-}
-
-// ------------------------------------- z-marching convolution, 32 input channels
+// ------------------------------------------------- z-marching convolution
 //
 // A workgroup of four wavefronts owns a column of 32 x 8 output voxels (x, y)
 // over a segment of z planes and marches along z.  Input plane p, with a
@@ -174,21 +51,32 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 // and the activations B.  Per plane it reads its 24 activation fragments
 // (input rows 2w .. 2w + 3, three x shifts, two 16-channel halves) once and
 // streams the 54 weight fragments, each used for both rows, so the LDS
-// operand traffic is 78 reads per 108 products.  The weights (27 x 32 x 32)
+// operand traffic is 78 reads per 108 products.  With eight input channels
+// (the first layer, and the data gradient of the last) one product covers two
+// taps of the same dz: half-wavefront kh takes tap 2q + kh of the nine, the
+// ninth paired with zero weights, so a plane costs 30 products from 10
+// activation and 15 weight reads per wavefront.  The weights (27 x 32 x cin)
 // stay in LDS for all the segments a (persistent) workgroup visits.
 constexpr int ZX = 32, ZY = 8;                  // output voxels per column
 constexpr int ZHX = ZX + 2, ZHY = ZY + 2;       // staged plane with halo
-constexpr int ZCS = 40;                         // padded channel stride (bf16)
-constexpr int ZPLANE = ZHX * ZHY * ZCS;         // bf16 per staged plane
-constexpr int ZCHUNKS = ZHX * ZHY * 4;          // 16-byte chunks per plane
-constexpr int ZLOADS = (ZCHUNKS + 255) / 256;   // chunks per thread
+
+template <int CIN>
+struct ZLayout {
+    static constexpr int CS = CIN == 32 ? 40 : 8;         // channel stride (bf16), padded for 32
+    static constexpr int CH = CIN / 8;                    // 16-byte chunks per voxel
+    static constexpr int PLANE = ZHX * ZHY * CS;          // bf16 per staged plane
+    static constexpr int CHUNKS = ZHX * ZHY * CH;         // 16-byte chunks per plane
+    static constexpr int LOADS = (CHUNKS + 255) / 256;    // chunks per thread
+};
 
 struct ZMarch {
     int tx, ty, zsegs, Lz;  // columns in x and y, segments per volume, planes per segment
 };
 
-template <int MODE>
+template <int CIN, int MODE>
 struct ZConv {
+    using L = ZLayout<CIN>;
+    static constexpr int ZCS = L::CS, ZPLANE = L::PLANE, ZCHUNKS = L::CHUNKS, ZLOADS = L::LOADS;
     const uint16_t* in;
     ConvShape s;
     int x0, y0, vol, za, zb;
@@ -206,14 +94,14 @@ struct ZConv {
         for (int q = 0; q < ZLOADS; ++q) {
             const int c = tid + 256 * q;
             const int cc = c < ZCHUNKS ? c : ZCHUNKS - 1;
-            const int ch = cc & 3, v = cc >> 2;
+            const int ch = cc % L::CH, v = cc / L::CH;
             const int hx = v % ZHX, hy = v / ZHX;
             const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
             const bool ok = pin && gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny;
             const int gxc = gx < 0 ? 0 : (gx >= s.nx ? s.nx - 1 : gx);
             const int gyc = gy < 0 ? 0 : (gy >= s.ny ? s.ny - 1 : gy);
             const uint4 val =
-                *reinterpret_cast<const uint4*>(in + (vbase + (int64_t(pc) * s.ny + gyc) * s.nx + gxc) * 32 + ch * 8);
+                *reinterpret_cast<const uint4*>(in + (vbase + (int64_t(pc) * s.ny + gyc) * s.nx + gxc) * CIN + ch * 8);
             stg[q] = ok ? val : make_uint4(0u, 0u, 0u, 0u);
         }
     }
@@ -222,7 +110,7 @@ struct ZConv {
         for (int q = 0; q < ZLOADS; ++q) {
             const int c = tid + 256 * q;
             if (c < ZCHUNKS) {
-                const int ch = c & 3, v = c >> 2;
+                const int ch = c % L::CH, v = c / L::CH;
                 *reinterpret_cast<uint4*>(&slot[v * ZCS + ch * 8]) = stg[q];
             }
         }
@@ -246,20 +134,48 @@ struct ZConv {
                 }
     }
 
+    // Eight input channels: tap pairs (2q, 2q + 1) of one dz.
+    template <int PH, int DZ>
+    __device__ __forceinline__ void tap_pairs(const bf16x8 (&B)[5][2], const uint16_t* s_w) {
+        constexpr int SL = (PH - DZ + 3) % 3;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int t9 = 2 * q + kh;  // tap of this half-wavefront within the dz plane
+            bf16x8 a = ld8(s_w + ((DZ * 9 + (t9 < 9 ? t9 : 8)) * 32 + j) * 8);
+            if (t9 >= 9) a = bf16x8{};
+            acc[0][SL] = mfma(a, B[q][0], acc[0][SL]);
+            acc[1][SL] = mfma(a, B[q][1], acc[1][SL]);
+        }
+    }
+
     // Products of the staged plane in `slot` (phase PH of the rotation).
     template <int PH>
     __device__ __forceinline__ void products(const uint16_t* slot, const uint16_t* s_w) {
-        bf16x8 B[4][3][2];
+        if constexpr (CIN == 8) {
+            bf16x8 B[5][2];
 #pragma unroll
-        for (int hr = 0; hr < 4; ++hr)
+            for (int q = 0; q < 5; ++q) {
+                const int t9 = 2 * q + kh < 9 ? 2 * q + kh : 8;
+                const int dy = t9 / 3, dx = t9 % 3;
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
+                for (int rr = 0; rr < 2; ++rr) B[q][rr] = ld8(slot + ((2 * wv + rr + dy) * ZHX + j + dx) * ZCS);
+            }
+            tap_pairs<PH, 0>(B, s_w);
+            tap_pairs<PH, 1>(B, s_w);
+            tap_pairs<PH, 2>(B, s_w);
+        } else {
+            bf16x8 B[4][3][2];
 #pragma unroll
-                for (int kb = 0; kb < 2; ++kb)
-                    B[hr][dx][kb] = ld8(slot + ((2 * wv + hr) * ZHX + j + dx) * ZCS + 16 * kb + 8 * kh);
-        tap_plane<PH, 0>(B, s_w);
-        tap_plane<PH, 1>(B, s_w);
-        tap_plane<PH, 2>(B, s_w);
+            for (int hr = 0; hr < 4; ++hr)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb)
+                        B[hr][dx][kb] = ld8(slot + ((2 * wv + hr) * ZHX + j + dx) * ZCS + 16 * kb + 8 * kh);
+            tap_plane<PH, 0>(B, s_w);
+            tap_plane<PH, 1>(B, s_w);
+            tap_plane<PH, 2>(B, s_w);
+        }
     }
 
     // Output plane z from accumulator slot SL, then the slot is cleared.
@@ -326,19 +242,22 @@ struct ZConv {
     }
 };
 
-template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_conv_zm(
-    const uint16_t* __restrict__ in, const uint16_t* __restrict__ w, const float* __restrict__ bias,
-    const uint16_t* __restrict__ mask, void* __restrict__ out, ConvShape s, ZMarch zm, int nseg) {
-    __shared__ __attribute__((aligned(16))) uint16_t s_w[27 * 32 * ZCS];
-    __shared__ __attribute__((aligned(16))) uint16_t s_in[2 * ZPLANE];
+// (32 input channels: one wavefront per SIMD, its registers hold the
+// activation fragments and three accumulator pairs; 8: two per SIMD)
+template <int CIN, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CIN == 32 ? 1 : 2, CIN == 32 ? 1 : 2))) void
+k_conv_zm(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w, const float* __restrict__ bias,
+          const uint16_t* __restrict__ mask, void* __restrict__ out, ConvShape s, ZMarch zm, int nseg) {
+    using L = ZLayout<CIN>;
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[27 * 32 * L::CS];
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[2 * L::PLANE];
     const int tid = threadIdx.x;
-    for (int c = tid; c < 27 * 32 * 4; c += 256) {
-        const int ch = c & 3, row = c >> 2;
-        *reinterpret_cast<uint4*>(&s_w[row * ZCS + ch * 8]) =
-            *reinterpret_cast<const uint4*>(w + int64_t(row) * 32 + ch * 8);
+    for (int c = tid; c < 27 * 32 * L::CH; c += 256) {
+        const int ch = c % L::CH, row = c / L::CH;
+        *reinterpret_cast<uint4*>(&s_w[row * L::CS + ch * 8]) =
+            *reinterpret_cast<const uint4*>(w + int64_t(row) * CIN + ch * 8);
     }
-    ZConv<MODE> zc;
+    ZConv<CIN, MODE> zc;
     zc.in = in;
     zc.s = s;
     zc.lane = tid & 63;
@@ -388,6 +307,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 // ---------------------------------------------------------- weight gradient
+
+// Brick counts of a volume batch along x, y and z.
+struct Bricks {
+    int bx, by, bz;
+};
 
 constexpr int WX = 32, WY = 2, WZ = 2;
 constexpr int WROWS_H = (WZ + 2) * (WY + 2);  // halo rows of H per brick
@@ -705,15 +629,16 @@ static int conv_groups() {
 }
 
 // Columns of 32 x 8 voxels, each split along z into as few segments as give
-// every compute unit one (the kernel's LDS allows one workgroup per unit).
-static void launch_conv_zm(ConvMode mode, const uint16_t* in, const uint16_t* w, const float* bias, const uint16_t* mask,
+// every workgroup slot one (one workgroup per compute unit with 32 input
+// channels, two with 8).
+static void launch_conv_zm(int cin, ConvMode mode, const uint16_t* in, const uint16_t* w, const float* bias, const uint16_t* mask,
                            void* out, const ConvShape& s, hipStream_t st) {
     ZMarch zm;
     zm.tx = (s.nx + ZX - 1) / ZX;
     zm.ty = (s.ny + ZY - 1) / ZY;
     const int64_t cols = int64_t(zm.tx) * zm.ty * s.nb;
     if (cols <= 0 || s.nz <= 0) return;
-    const int units = conv_groups() / 2;
+    const int units = cin == 32 ? conv_groups() / 2 : conv_groups();
     int64_t zsegs = (units + cols - 1) / cols;
     const int64_t zmax = (s.nz + 3) / 4;  // at least four planes per segment
     if (zsegs > zmax) zsegs = zmax;
@@ -724,34 +649,23 @@ static void launch_conv_zm(ConvMode mode, const uint16_t* in, const uint16_t* w,
     if (nseg > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "convolution grid too large");
     const dim3 grid(unsigned(nseg < units ? nseg : units)), block(256);
     const int ns = int(nseg);
-    if (mode == CONV_BIAS_RELU)
-        hipLaunchKernelGGL((k_conv_zm<CONV_BIAS_RELU>), grid, block, 0, st, in, w, bias, mask, out, s, zm, ns);
-    else if (mode == CONV_BIAS_F32)
-        hipLaunchKernelGGL((k_conv_zm<CONV_BIAS_F32>), grid, block, 0, st, in, w, bias, mask, out, s, zm, ns);
-    else
-        hipLaunchKernelGGL((k_conv_zm<CONV_MASK>), grid, block, 0, st, in, w, bias, mask, out, s, zm, ns);
+#define MXP_ZM(C, M) hipLaunchKernelGGL((k_conv_zm<C, M>), grid, block, 0, st, in, w, bias, mask, out, s, zm, ns)
+    if (cin == 32) {
+        if (mode == CONV_BIAS_RELU) MXP_ZM(32, CONV_BIAS_RELU);
+        else if (mode == CONV_BIAS_F32) MXP_ZM(32, CONV_BIAS_F32);
+        else MXP_ZM(32, CONV_MASK);
+    } else {
+        if (mode == CONV_BIAS_RELU) MXP_ZM(8, CONV_BIAS_RELU);
+        else if (mode == CONV_BIAS_F32) MXP_ZM(8, CONV_BIAS_F32);
+        else MXP_ZM(8, CONV_MASK);
+    }
+#undef MXP_ZM
 }
 
 void launch_conv(int cin, ConvMode mode, const uint16_t* in, const uint16_t* w, const float* bias,
                  const uint16_t* mask, void* out, const ConvShape& s, hipStream_t st) {
-    Bricks nbk{(s.nx + BX - 1) / BX, (s.ny + BY - 1) / BY, (s.nz + BZ - 1) / BZ};
-    const int64_t nb = int64_t(nbk.bx) * nbk.by * nbk.bz * s.nb;
-    if (nb <= 0) return;
-    if (nb > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "convolution grid too large");
-    const int groups = int(nb < conv_groups() ? nb : conv_groups());
-    const dim3 grid = dim3(unsigned(groups)), block = dim3(256);
-    const int nbr = int(nb);
-#define MXP_CONV(C, M) hipLaunchKernelGGL((k_conv<C, M>), grid, block, 0, st, in, w, bias, mask, out, s, nbk, nbr)
-    if (cin == 32) {
-        launch_conv_zm(mode, in, w, bias, mask, out, s, st);
-    } else if (cin == 8) {
-        if (mode == CONV_BIAS_RELU) MXP_CONV(8, CONV_BIAS_RELU);
-        else if (mode == CONV_BIAS_F32) MXP_CONV(8, CONV_BIAS_F32);
-        else MXP_CONV(8, CONV_MASK);
-    } else {
-        fail(MXP_ERR_INVALID_ARG, "convolution input channels must be 8 or 32");
-    }
-#undef MXP_CONV
+    if (cin != 32 && cin != 8) fail(MXP_ERR_INVALID_ARG, "convolution input channels must be 8 or 32");
+    launch_conv_zm(cin, mode, in, w, bias, mask, out, s, st);
     check_launch("conv");
 }
 
