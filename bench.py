@@ -400,7 +400,7 @@ def bench_learned(args, torch, mxp, wl):
                      "loss_first": losses[0], "loss_last": float(np.mean(losses[-20:])), "kappa": kappa},
         "roofline": {"bound": "mfma", "achieved": round(flops / t_fwd / 1e12, 1), "peak": PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(flops / t_fwd / 1e12 / PEAK_BF16_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_conv<32,*> (network forward, 6 layers, 256^3)",
+                     "kernel": "k_conv_zm<CIN,*> (network forward, 6 layers, 256^3)",
                      "forward_ms": round(t_fwd * 1e3, 3)},
     }
     print(json.dumps(line), flush=True)
