@@ -57,6 +57,17 @@ inline void check_launch(const char* what) {
 // ninth paired with zero weights, so a plane costs 30 products from 10
 // activation and 15 weight reads per wavefront.  The weights (27 x 32 x cin)
 // stay in LDS for all the segments a (persistent) workgroup visits.
+//
+// The last layer has two output channels, so a 32-channel tile would waste
+// 30 of its rows.  There the (dz, dy) taps go into the rows instead: row
+// i = 8 g + 4 h + q stands for output channel h and tap pair t = 4 g + q
+// (dz = t / 3, dy = t % 3; rows with t >= 9 have zero weights), and K runs
+// over (dx, input channel).  One input row then needs six products (three dx
+// times two channel halves) whose result register t of half-wavefront h is
+// the partial sum of channel h for output plane p + 1 - dz and row hy - dy;
+// each lane adds it to one of six running sums (three planes, two rows).  That
+// is 24 products per plane instead of 108, with the weights (six fragments)
+// held in registers.
 constexpr int ZX = 32, ZY = 8;                  // output voxels per column
 constexpr int ZHX = ZX + 2, ZHY = ZY + 2;       // staged plane with halo
 
@@ -77,12 +88,16 @@ template <int CIN, int MODE>
 struct ZConv {
     using L = ZLayout<CIN>;
     static constexpr int ZCS = L::CS, ZPLANE = L::PLANE, ZCHUNKS = L::CHUNKS, ZLOADS = L::LOADS;
+    static constexpr bool LAST = MODE == CONV_BIAS_F32;  // two output channels
+    static_assert(!LAST || CIN == 32, "the two-channel layer reads 32 channels");
     const uint16_t* in;
     ConvShape s;
     int x0, y0, vol, za, zb;
     int64_t vbase;
     int lane, wv, j, kh;
     f32x16 acc[2][3];
+    float oacc[3][2];    // last layer: running sums, [plane slot][row], channel kh
+    bf16x8 wl[3][2];     // last layer: weight fragments per (dx, channel half)
     uint4 stg[ZLOADS];
 
     // Loads of input plane p (zero outside the volume); every address is
@@ -148,10 +163,31 @@ struct ZConv {
         }
     }
 
+    // Last layer: the products of input row hr of the staged plane.
+    template <int PH, int HR>
+    __device__ __forceinline__ void last_row(const uint16_t* slot) {
+        f32x16 d = {};
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                d = mfma(wl[dx][kb], ld8(slot + ((2 * wv + HR) * ZHX + j + dx) * ZCS + 16 * kb + 8 * kh), d);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dz = t / 3, dy = t % 3, rr = HR - dy;
+            if (rr >= 0 && rr <= 1) oacc[(PH - dz + 3) % 3][rr] += d[t];
+        }
+    }
+
     // Products of the staged plane in `slot` (phase PH of the rotation).
     template <int PH>
     __device__ __forceinline__ void products(const uint16_t* slot, const uint16_t* s_w) {
-        if constexpr (CIN == 8) {
+        if constexpr (LAST) {
+            last_row<PH, 0>(slot);
+            last_row<PH, 1>(slot);
+            last_row<PH, 2>(slot);
+            last_row<PH, 3>(slot);
+        } else if constexpr (CIN == 8) {
             bf16x8 B[5][2];
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
@@ -181,21 +217,27 @@ struct ZConv {
     // Output plane z from accumulator slot SL, then the slot is cleared.
     template <int SL>
     __device__ __forceinline__ void emit(int z, const float (&bco)[16], const uint16_t* mask, void* out) {
-        if (z >= za && z < zb) {
+        if constexpr (LAST) {
+            if (z >= za && z < zb) {
 #pragma unroll
-            for (int rr = 0; rr < 2; ++rr) {
-                const int y = y0 + 2 * wv + rr, x = x0 + j;
-                if (y < s.ny && x < s.nx) {
-                    const int64_t vox = vbase + (int64_t(z) * s.ny + y) * s.nx + x;
-                    const f32x16& a = acc[rr][SL];
-                    if constexpr (MODE == CONV_BIAS_F32) {
-                        if (kh == 0) {
-                            float2 o;
-                            o.x = a[0] + bco[0];
-                            o.y = a[1] + bco[1];
-                            *reinterpret_cast<float2*>(static_cast<float*>(out) + vox * 2) = o;
-                        }
-                    } else {
+                for (int rr = 0; rr < 2; ++rr) {
+                    const int y = y0 + 2 * wv + rr, x = x0 + j;
+                    if (y < s.ny && x < s.nx) {
+                        const int64_t vox = vbase + (int64_t(z) * s.ny + y) * s.nx + x;
+                        static_cast<float*>(out)[vox * 2 + kh] = oacc[SL][rr] + bco[0];
+                    }
+                }
+            }
+            oacc[SL][0] = 0.0f;
+            oacc[SL][1] = 0.0f;
+        } else {
+            if (z >= za && z < zb) {
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr) {
+                    const int y = y0 + 2 * wv + rr, x = x0 + j;
+                    if (y < s.ny && x < s.nx) {
+                        const int64_t vox = vbase + (int64_t(z) * s.ny + y) * s.nx + x;
+                        const f32x16& a = acc[rr][SL];
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const int64_t off = vox * 32 + 8 * g + 4 * kh;
@@ -222,9 +264,9 @@ struct ZConv {
                     }
                 }
             }
+            acc[0][SL] = f32x16{};
+            acc[1][SL] = f32x16{};
         }
-        acc[0][SL] = f32x16{};
-        acc[1][SL] = f32x16{};
     }
 
     // Input plane p = za - 1 + t (phase PH = t mod 3): issue the next plane's
@@ -243,20 +285,18 @@ struct ZConv {
 };
 
 // (32 input channels: one wavefront per SIMD, its registers hold the
-// activation fragments and three accumulator pairs; 8: two per SIMD)
+// activation fragments and three accumulator pairs; 8 input channels and the
+// two-channel layer: two per SIMD)
 template <int CIN, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CIN == 32 ? 1 : 2, CIN == 32 ? 1 : 2))) void
+__global__ __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu(CIN == 32 && MODE != CONV_BIAS_F32 ? 1 : 2, CIN == 32 && MODE != CONV_BIAS_F32 ? 1 : 2))) void
 k_conv_zm(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w, const float* __restrict__ bias,
           const uint16_t* __restrict__ mask, void* __restrict__ out, ConvShape s, ZMarch zm, int nseg) {
     using L = ZLayout<CIN>;
-    __shared__ __attribute__((aligned(16))) uint16_t s_w[27 * 32 * L::CS];
+    constexpr bool LAST = ZConv<CIN, MODE>::LAST;
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[LAST ? 8 : 27 * 32 * L::CS];
     __shared__ __attribute__((aligned(16))) uint16_t s_in[2 * L::PLANE];
     const int tid = threadIdx.x;
-    for (int c = tid; c < 27 * 32 * L::CH; c += 256) {
-        const int ch = c % L::CH, row = c / L::CH;
-        *reinterpret_cast<uint4*>(&s_w[row * L::CS + ch * 8]) =
-            *reinterpret_cast<const uint4*>(w + int64_t(row) * CIN + ch * 8);
-    }
     ZConv<CIN, MODE> zc;
     zc.in = in;
     zc.s = s;
@@ -264,15 +304,36 @@ k_conv_zm(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w, const
     zc.wv = tid >> 6;
     zc.j = zc.lane & 31;
     zc.kh = zc.lane >> 5;
-    // bias of the output channels this lane holds, 8 (r / 4) + 4 kh + r % 4
-    // (the last layer has two)
     float bco[16];
+    if constexpr (LAST) {
+        // A row i = lane % 32: output channel (i / 4) % 2, tap pair t = 4 (i / 8) + i % 4
+        const int i = zc.lane & 31;
+        const int co = (i >> 2) & 1, t = 4 * (i >> 3) + (i & 3);
+        const int dz = t / 3, dy = t % 3;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int co = 8 * (r >> 2) + 4 * zc.kh + (r & 3);
-        bco[r] = 0.0f;
-        if constexpr (MODE == CONV_BIAS_RELU) bco[r] = bias[co];
-        if constexpr (MODE == CONV_BIAS_F32) bco[r] = co < 2 ? bias[co < 2 ? co : 0] : 0.0f;
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const int tap = t < 9 ? dz * 9 + dy * 3 + dx : 0;
+                const bf16x8 v = ld8(w + (int64_t(tap) * 32 + co) * 32 + 16 * kb + 8 * zc.kh);
+                zc.wl[dx][kb] = t < 9 ? v : bf16x8{};
+            }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) bco[r] = 0.0f;
+        bco[0] = bias[zc.kh];  // this half-wavefront's output channel
+    } else {
+        for (int c = tid; c < 27 * 32 * L::CH; c += 256) {
+            const int ch = c % L::CH, row = c / L::CH;
+            *reinterpret_cast<uint4*>(&s_w[row * L::CS + ch * 8]) =
+                *reinterpret_cast<const uint4*>(w + int64_t(row) * CIN + ch * 8);
+        }
+        // bias of the output channels this lane holds, 8 (r / 4) + 4 kh + r % 4
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int co = 8 * (r >> 2) + 4 * zc.kh + (r & 3);
+            bco[r] = 0.0f;
+            if constexpr (MODE == CONV_BIAS_RELU) bco[r] = bias[co];
+        }
     }
     for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
         int b = seg;
@@ -290,7 +351,10 @@ k_conv_zm(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w, const
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-            for (int q = 0; q < 3; ++q) zc.acc[rr][q] = f32x16{};
+            for (int q = 0; q < 3; ++q) {
+                if constexpr (LAST) zc.oacc[q][rr] = 0.0f;
+                else zc.acc[rr][q] = f32x16{};
+            }
         // input planes za - 1 .. zb
         const int T = zc.zb - zc.za + 2;
         zc.issue(zc.za - 1, tid);
@@ -638,7 +702,7 @@ static void launch_conv_zm(int cin, ConvMode mode, const uint16_t* in, const uin
     zm.ty = (s.ny + ZY - 1) / ZY;
     const int64_t cols = int64_t(zm.tx) * zm.ty * s.nb;
     if (cols <= 0 || s.nz <= 0) return;
-    const int units = cin == 32 ? conv_groups() / 2 : conv_groups();
+    const int units = cin == 32 && mode != CONV_BIAS_F32 ? conv_groups() / 2 : conv_groups();
     int64_t zsegs = (units + cols - 1) / cols;
     const int64_t zmax = (s.nz + 3) / 4;  // at least four planes per segment
     if (zsegs > zmax) zsegs = zmax;
@@ -656,8 +720,8 @@ static void launch_conv_zm(int cin, ConvMode mode, const uint16_t* in, const uin
         else MXP_ZM(32, CONV_MASK);
     } else {
         if (mode == CONV_BIAS_RELU) MXP_ZM(8, CONV_BIAS_RELU);
-        else if (mode == CONV_BIAS_F32) MXP_ZM(8, CONV_BIAS_F32);
-        else MXP_ZM(8, CONV_MASK);
+        else if (mode == CONV_MASK) MXP_ZM(8, CONV_MASK);
+        else fail(MXP_ERR_INVALID_ARG, "the two-channel output layer reads 32 channels");
     }
 #undef MXP_ZM
 }
