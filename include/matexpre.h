@@ -338,10 +338,12 @@ mxp_status mxp_collect_pairs(mxp_problem* prob, const mxp_solve_opts* opts, cons
  * value and its output, scaled back, is multiplied by out_scale (the typical
  * ||M(v)|| / ||v|| of the training pairs).  At an outer iteration z_j =
  * network(v_j) is kept if the Arnoldi residual estimate falls below a
- * threshold times the previous one: stall_ratio if > 0, else exp(rate * T),
- * rate = the mean log reduction per second of the MatExPre iterations so far
- * and T = the time of the network try (a try is kept when it is at least as
- * cost-effective as MatExPre).  Otherwise z_j = M(v_j) from MatExPre (a
+ * threshold times the previous one: stall_ratio if > 0, else
+ * min(exp(g), exp(rate * T)) with g the mean log reduction per MatExPre
+ * iteration so far, rate the same per second and T the time of the network
+ * try (a kept direction takes a slot of the restart cycle, so it must reduce
+ * the residual as much as the MatExPre iteration it displaces, and at least
+ * as cost-effectively).  Otherwise z_j = M(v_j) from MatExPre (a
  * fallback); after two fallbacks in a row MatExPre alone is used until the
  * next restart cycle.  The first outer iteration always uses MatExPre.
  * Convergence is judged by the complex-double true residual as always.

@@ -1413,13 +1413,15 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
             cpx<double>* vn = V + size_t(j + 1) * n;
             // Learned stage: try the network's z_j first and keep it when the
             // Arnoldi residual estimate falls below a threshold times the
-            // previous one: stall_ratio when it is > 0, else the reduction
-            // that MatExPre's own iterations achieve on average in the time
-            // one network try takes (so a try is kept when it is at least as
-            // cost-effective).  Otherwise the MatExPre preconditioner
-            // supplies z_j; after two misses in a row it does so until the
-            // next restart cycle.  The first iteration of a solve always
-            // uses MatExPre (it calibrates the adaptive threshold).
+            // previous one: stall_ratio when it is > 0, else the smaller of
+            // the mean reduction of MatExPre's own iterations (a kept
+            // direction takes a slot of the restart cycle, so it must do as
+            // well as the iteration it displaces) and the reduction they
+            // achieve on average in the time one network try takes (so it is
+            // also at least as cost-effective).  Otherwise the MatExPre
+            // preconditioner supplies z_j; after two misses in a row it does
+            // so until the next restart cycle.  The first iteration of a
+            // solve always uses MatExPre (it calibrates the threshold).
             double hn = 0.0, res = 0.0;
             bool accepted = false;
             const bool calibrated = o.stall_ratio > 0 || m_count > 0;
@@ -1433,8 +1435,9 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
                 res = trial.add_column(j, h, hn);
                 double thr = o.stall_ratio;
                 if (thr <= 0) {
-                    const double rate = m_log / m_count / std::max(m_sec / m_count, 1e-9);  // log reduction per second
-                    thr = std::min(1.0, std::exp(rate * n_sec));
+                    const double per_it = m_log / m_count;                          // log reduction per iteration
+                    const double rate = per_it / std::max(m_sec / m_count, 1e-9);  // ... per second
+                    thr = std::min(1.0, std::min(std::exp(per_it), std::exp(rate * n_sec)));
                 }
                 if (std::isfinite(res) && res <= thr * prev_res) {
                     gv = trial;
