@@ -21,7 +21,11 @@
 //    ring (each lane reads only what it wrote: no barriers);
 //  * x-neighbours come from the adjacent lane through DPP wavefront shifts;
 //  * row j+1 is fetched while the levels of row j are computed;
-//  * a level is skipped on rows no output depends on.
+//  * a level is skipped on rows no output depends on;
+//  * the per-row diagonal term goes through the scalar cache: in complex
+//    double the three rows of a group are loaded together at the start of
+//    the group (one wait per group instead of one per row: 8% faster
+//    there, 6% slower in complex float, which loads it per row).
 // Waves are independent.
 #include <hip/hip_runtime.h>
 
@@ -272,14 +276,19 @@ struct Pass2D {
     // One row step at iteration j (PH = (j - jstart) mod 3).
     template <int PH, bool FAST>
     __device__ __forceinline__ void step_impl(const Params& a, cpx<R>* __restrict__ xs, cpx<R>* __restrict__ dg,
-                                              int j) {
+                                              const cpx<R> (&gyg)[3], int j) {
         const cpx<R> zero{R(0), R(0)};
         const bool rin = (j >= 0 && j < a.n1);
         const int slot_j = j & (M - 1);
         constexpr int sj = PH;
         // row j (fetched during the previous step) into the windows and the ring
-        const int rj = __builtin_amdgcn_readfirstlane(rin ? j : 0);
-        const cpx<R> gyj = sload(a.gy, rj);
+        cpx<R> gyj;
+        if constexpr (sizeof(R) == 8) {
+            gyj = gyg[PH];
+        } else {
+            const int rj = __builtin_amdgcn_readfirstlane(rin ? j : 0);
+            gyj = sload(a.gy, rj);
+        }
 #pragma unroll
         for (int e = 0; e < NX; ++e) {
             const bool ok = rin && cin[e];
@@ -338,17 +347,29 @@ struct Pass2D {
     // Three row steps j0, j0+1, j0+2.  In the steady state (every level row of
     // the group needed and interior) one uniform test selects a body free of
     // branches, so the scheduler can overlap the level chains of the rows.
+    // Scalar loads of the y diagonal term of rows j .. j+2 (clamped rows are
+    // never used unmasked).
+    __device__ __forceinline__ void load_gy(const Params& a, int j, cpx<R> (&g)[3]) const {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int r = j + q;
+            g[q] = sload(a.gy, __builtin_amdgcn_readfirstlane(r >= 0 && r < a.n1 ? r : 0));
+        }
+    }
+
     __device__ __forceinline__ void group(const Params& a, cpx<R>* __restrict__ xs, cpx<R>* __restrict__ dg,
                                           int j0) {
+        cpx<R> gyg[3] = {};
+        if constexpr (sizeof(R) == 8) load_gy(a, j0, gyg);
         const bool fast = x_interior && (j0 >= Y0 + K) && (j0 - K >= a.iy0) && (j0 + 1 < a.iy1);
         if (fast) {
-            step_impl<0, true>(a, xs, dg, j0);
-            step_impl<1, true>(a, xs, dg, j0 + 1);
-            step_impl<2, true>(a, xs, dg, j0 + 2);
+            step_impl<0, true>(a, xs, dg, gyg, j0);
+            step_impl<1, true>(a, xs, dg, gyg, j0 + 1);
+            step_impl<2, true>(a, xs, dg, gyg, j0 + 2);
         } else {
-            step_impl<0, false>(a, xs, dg, j0);
-            step_impl<1, false>(a, xs, dg, j0 + 1);
-            step_impl<2, false>(a, xs, dg, j0 + 2);
+            step_impl<0, false>(a, xs, dg, gyg, j0);
+            step_impl<1, false>(a, xs, dg, gyg, j0 + 1);
+            step_impl<2, false>(a, xs, dg, gyg, j0 + 2);
         }
         store_row<0>(a, j0);
         store_row<1>(a, j0 + 1);
