@@ -95,6 +95,8 @@ def emulated_backward(layers, acts, gout):
 
 
 SHAPE = (2, 5, 7, 45)  # two volumes; x spans two 32-wide tiles, y and z ragged
+# one volume over 3 x 3 columns of 32 x 8 voxels (both ragged) and three z segments
+SHAPES = [SHAPE, (1, 9, 19, 70)]
 
 
 def random_params(seed):
@@ -105,19 +107,20 @@ def random_params(seed):
     return flat_of(layers)
 
 
-def test_forward_matches_oracle(ctx):
-    announce("cnn forward")
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_matches_oracle(ctx, shape):
+    announce("cnn forward", shape)
     net = mxp.Network(ctx, 1)
     flat = random_params(3)
     net.set_params(flat)
     assert np.array_equal(net.get_params(), flat)
-    x, bits = make_input(SHAPE, 4)
+    x, bits = make_input(shape, 4)
     xd = torch.from_numpy(bits.view(np.int16)).to("cuda:0")
-    out = torch.empty(int(np.prod(SHAPE[:4])) * 2, dtype=torch.float32, device="cuda:0")
-    net.forward(SHAPE, xd, out)
-    y = out.cpu().numpy().astype(np.float64).reshape(SHAPE + (2,))
+    out = torch.empty(int(np.prod(shape[:4])) * 2, dtype=torch.float32, device="cuda:0")
+    net.forward(shape, xd, out)
+    y = out.cpu().numpy().astype(np.float64).reshape(shape + (2,))
     layers = layers_of(flat)
-    for b in range(SHAPE[0]):
+    for b in range(shape[0]):
         ref, _ = emulated_forward(layers, x[b])
         assert rel(y[b], ref) <= 2e-3
         plain, _ = conv.forward(layers, x[b][..., :3])
@@ -125,20 +128,21 @@ def test_forward_matches_oracle(ctx):
     net.close()
 
 
-def test_backward_matches_oracle(ctx):
-    announce("cnn backward")
+@pytest.mark.parametrize("shape", SHAPES)
+def test_backward_matches_oracle(ctx, shape):
+    announce("cnn backward", shape)
     net = mxp.Network(ctx, 1)
     flat = random_params(5)
     net.set_params(flat)
-    x, bits = make_input(SHAPE, 6)
+    x, bits = make_input(shape, 6)
     rng = np.random.default_rng(7)
-    gout = rng.standard_normal(SHAPE + (2,)).astype(np.float32)
-    net.backward(SHAPE, torch.from_numpy(bits.view(np.int16)).to("cuda:0"),
+    gout = rng.standard_normal(shape + (2,)).astype(np.float32)
+    net.backward(shape, torch.from_numpy(bits.view(np.int16)).to("cuda:0"),
                  torch.from_numpy(gout.ravel()).to("cuda:0"))
     g = layers_of(net.get_grads())
     layers = layers_of(flat)
     ref = None
-    for b in range(SHAPE[0]):
+    for b in range(shape[0]):
         _, acts = emulated_forward(layers, x[b])
         gb = emulated_backward(layers, acts, gout[b].astype(np.float64))
         ref = gb if ref is None else [{k: r[k] + q[k] for k in r} for r, q in zip(ref, gb)]
