@@ -435,8 +435,8 @@ def main():
                          "1 GiB device copy (counter calibration); for profiler runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part "
-              "of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): the solver has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

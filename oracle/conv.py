@@ -1,7 +1,7 @@
 """Reference 3x3x3 convolutional network for the learned preconditioner stage
 (oracle side, float64 NumPy).
 
-The paper has no learned component.  The network is this build's: six 3x3x3
+The paper has no learned component; the network is the library's own: six 3x3x3
 convolutions with zero padding, channels 3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 2,
 bias on every layer, ReLU after the first five.  Volumes are channels-last,
 shape (nz, ny, nx, C) with x fastest, matching the grid ordering of the solver.
