@@ -23,7 +23,8 @@ import numpy as np
 __all__ = [
     "Problem", "config1", "config2", "config3", "config4_main", "config4_extras",
     "small_problem", "delta_source", "gaussian_source", "grf_speed",
-    "layered_speed", "random_vector", "config4_sources",
+    "layered_speed", "random_vector", "config4_sources", "lens_problem", "lens_source",
+    "homog_problem", "dipole_source",
 ]
 
 
@@ -209,3 +210,67 @@ def small_problem(n: Tuple[int, ...], layer: int, ppw: float = 10.0,
         shape = tuple(reversed(n))
         c = grf_speed(shape, max(2.0, min(n) / 6.0), 1.0, 3.0, seed)
     return Problem(name, tuple(n), h, omega_for(ppw, h), layer, c, 1.0)
+
+
+def lens_problem(dim: int, freq: float, layer: int = 20) -> Problem:
+    """Converging-lens model (paper, Section 5.3.1, converging lens models):
+    c = 1 - exp(-|x - x0|^2 / (2 sigma^2)) / 2 on the unit square or cube,
+    sigma = 1/32, x0 = (0.5, 0.1) in 2D and (0.5, 0.25, 0.5) in 3D, so
+    c_min = 1/2; h = 1/(20 freq) gives 10 points per wavelength at c_min.
+    The absorbing layer (20 points in the paper) lies outside the unit domain:
+    node i sits at x = (i - layer) h, so each axis has 20 freq + 1 + 2 layer
+    nodes.  omega = 2 pi freq; the paper's t = 0.1/freq^2 and s = 1/freq equal
+    this module's defaults 40 h^2 and 1/freq."""
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    m = int(round(20 * freq))
+    h = 1.0 / m
+    n = m + 1 + 2 * layer
+    x0 = (0.5, 0.1) if dim == 2 else (0.5, 0.25, 0.5)
+    sigma = 1.0 / 32.0
+    coords = (np.arange(n) - layer) * h
+    shape = (n,) * dim
+    grids = np.meshgrid(*([coords] * dim), indexing="ij")  # (z,) y, x order
+    r2 = np.zeros(shape)
+    for g, c0 in zip(grids, reversed(x0)):
+        r2 = r2 + (g - c0) ** 2
+    c = 1.0 - 0.5 * np.exp(-r2 / (2.0 * sigma * sigma))
+    name = f"lens-{dim}d-{n}"
+    return Problem(name, (n,) * dim, h, 2.0 * math.pi * freq, layer, c)
+
+
+def lens_source(prob: Problem) -> np.ndarray:
+    """Discrete delta at the centre of the unit domain (the lens models' source)."""
+    m = prob.n[0] - 1 - 2 * prob.layer
+    centre = tuple(prob.layer + m // 2 for _ in prob.n)
+    return delta_source(prob, centre)
+
+
+def homog_problem(dim: int, freq: float) -> Problem:
+    """Homogeneous model of the paper's 2D and 3D homogeneous experiments
+    (Sections 5.1 and 5.2): c = 1 on the unit square or cube, 10 points per
+    wavelength (h = 1/(10 freq)), and one wavelength (10 points) of absorbing
+    layer outside the unit domain, so each axis has 10 freq + 21 nodes."""
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    m = int(round(10 * freq))
+    layer = 10
+    n = m + 1 + 2 * layer
+    return Problem(f"homog-{dim}d-{n}", (n,) * dim, 1.0 / m, 2.0 * math.pi * freq, layer, None, 1.0)
+
+
+def dipole_source(prob: Problem) -> np.ndarray:
+    """The homogeneous experiments' source: pairs of normalised Gaussians
+    (standard deviation 3h) at the unit domain's centre -+ 6h, the lower one
+    negative; along x in 2D (Section 5.1), along each axis in 3D (Section
+    5.2).  Coordinates of the unit domain start at the inner edge of the
+    absorbing layer."""
+    h, L = prob.h, prob.layer
+    centre = 0.5 + L * h  # the unit domain's centre in grid coordinates
+    f = np.zeros(prob.shape, dtype=np.complex128)
+    for axis in range(1 if prob.dim == 2 else 3):
+        for sign in (-1.0, 1.0):
+            c = [centre] * prob.dim
+            c[axis] = centre + sign * 6.0 * h
+            f += sign * gaussian_source(prob, tuple(c), 3.0 * h)
+    return f
