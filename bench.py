@@ -461,6 +461,28 @@ def bench_paper_tables(args, torch, mxp, wl):
         prec = 0 if prob.npts <= 241 ** 3 else 1
         st, sec = solve(prob, wl.dipole_source(prob), 1.0 / row["freq"], row["fprtol"], prec)
         record("fprtol_3d", {"freq": row["freq"], "fprtol": row["fprtol"]}, prob, row, st, sec, prec)
+    noshift = []
+    for row in tables["noshift_2d"]["rows"]:
+        prob = wl.homog_problem(2, row["freq"])
+        P = mxp.Problem(ctx, prob)
+        o = P.default_opts()
+        o.precision = mxp.MXP_PREC_FP64  # unshifted: the mixed form stalls below ~1e-4 (FP32 actions)
+        o.rtol = 1e-5
+        o.shift = 0.0
+        o.fprtol = 0.01
+        fd = torch.from_numpy(wl.dipole_source(prob).ravel()).to("cuda:0")
+        u = torch.zeros_like(fd)
+        t0 = time.perf_counter()
+        mxp.mxp_solve(P, o, fd, u)
+        sec = time.perf_counter() - t0
+        total += sec
+        inner, res = mxp.mxp_solve_history(P)
+        P.close()
+        del fd, u
+        noshift.append({"freq": row["freq"], "grid": list(prob.n), "inner": inner, "res": [float(f"{r:.4g}") for r in res],
+                        "paper": {"inner": row["inner"], "res": row["res"]}, "seconds": round(sec, 3)})
+        print(f"[bench] noshift_2d freq {row['freq']}: inner {inner} (paper {row['inner']}), "
+              f"res {['%.3e' % r for r in res]} (paper {row['res']}), {sec:.2f} s", file=sys.stderr, flush=True)
     skipped = []
     for row in tables["lens"]["rows"]:
         prob_n = 20 * row["freq"] + 41
@@ -508,7 +530,7 @@ def bench_paper_tables(args, torch, mxp, wl):
         "data": "synthetic: the paper's homogeneous and converging-lens models, recomputed from their definitions",
         "config": {"workload": "paper-tables", "entries": n, "skipped": skipped},
         "matches": {"outer_exact": exact, "outer_and_inner_within_1": near, "entries": n},
-        "entries": out, "weak_scaling_op": weak,
+        "entries": out, "noshift_2d": noshift, "weak_scaling_op": weak,
     }
     print(json.dumps(rec), flush=True)
 

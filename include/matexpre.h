@@ -254,6 +254,17 @@ mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32
 mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
                      mxp_solve_stats* stats);
 
+/* Per-outer-iteration record of the last single solve on the problem
+ * (mxp_solve or mxp_collect_pairs; batched solves leave it unchanged), as
+ * the paper tabulates it (Section 5.1.2): inner_its[k] = inner GMRES
+ * iterations of outer iteration k (-1 where a network direction was kept)
+ * and relres[k] = the Arnoldi estimate of the relative residual after it.
+ * *count receives the number of iterations recorded; min(cap, count) entries
+ * are copied to the host arrays.  Errors: INVALID_ARG (count NULL, cap < 0,
+ * or cap > 0 with a NULL array). */
+mxp_status mxp_solve_history(const mxp_problem* prob, int32_t cap, int32_t* inner_its, double* relres,
+                             int32_t* count);
+
 /* Solves many right-hand sides of one or more problems together (Section 3.4
  * method, as mxp_solve, for each).  Problem q has nrhs[q] right-hand sides
  * stored back to back at f[q] (nrhs[q] * size(q) complex doubles, device) and

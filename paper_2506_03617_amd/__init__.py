@@ -125,7 +125,7 @@ ABI_SYMBOLS = (
     "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
     "mxp_cnn_num_params", "mxp_cnn_create", "mxp_cnn_destroy", "mxp_cnn_get_params", "mxp_cnn_set_params",
     "mxp_cnn_get_grads", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
-    "mxp_collect_pairs", "mxp_problem_set_learned", "mxp_cnn_save", "mxp_cnn_load",
+    "mxp_collect_pairs", "mxp_problem_set_learned", "mxp_cnn_save", "mxp_cnn_load", "mxp_solve_history",
 )
 
 
@@ -179,6 +179,7 @@ def _load():
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mxp_solve_stats)]),
         "mxp_problem_set_learned": (st, [P, P, ctypes.c_double]),
+        "mxp_solve_history": (st, [P, ctypes.c_int32, P, P, ctypes.POINTER(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -445,6 +446,18 @@ class Network:
             self.close()
         except Exception:
             pass
+
+
+def mxp_solve_history(prob: Problem):
+    """Inner iterations and relative residual estimate of every outer
+    iteration of the last single solve on `prob`."""
+    n = ctypes.c_int32()
+    _check(lib.mxp_solve_history(prob.handle, 0, None, None, ctypes.byref(n)))
+    inner = np.zeros(n.value, dtype=np.int32)
+    res = np.zeros(n.value, dtype=np.float64)
+    if n.value:
+        _check(lib.mxp_solve_history(prob.handle, n.value, inner.ctypes.data, res.ctypes.data, ctypes.byref(n)))
+    return inner.tolist(), res.tolist()
 
 
 def mxp_cnn_make_sample(prob: Problem, r, z, offset, crop, rscale: float, zscale: float, x, target) -> None:

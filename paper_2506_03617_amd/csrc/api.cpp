@@ -163,6 +163,10 @@ struct mxp_problem {
     mxp::Workspace ws;      // workspace of the single-solve calls
     mxp_cnn* net = nullptr; // learned stage (not owned), with its output scale
     double net_scale = 1.0;
+    // per outer iteration of the last single solve: inner iterations (-1 for
+    // a kept network direction) and the Arnoldi relative residual estimate
+    std::vector<int32_t> hist_inner;
+    std::vector<double> hist_res;
 };
 
 namespace mxp {
@@ -1374,6 +1378,8 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
     cpx<double>* r = WS.outerR.as<cpx<double>>();
     Counters cnt;
     std::vector<int> inner;
+    std::vector<int32_t> hist_inner;
+    std::vector<double> hist_res;
     const double bnorm = norm2(run, f);
     // r = -f - A u
     apply_A64(P, s, 0.0, u, r, -1.0, f, -1.0);
@@ -1473,6 +1479,8 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
             }
             ++its;
             prev_res = res;
+            hist_inner.push_back(accepted ? -1 : inner.back());
+            hist_res.push_back(bnorm > 0 ? res / bnorm : 0.0);
             if (P->ctx->verbose) {
                 const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
                 std::fprintf(stderr, "[mxp] outer %d: est relres %.3e, %s, steps %lld, %.2f s\n", its,
@@ -1500,6 +1508,10 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
         if (relres <= o.rtol) break;
     }
     HIP_CHECK(hipStreamSynchronize(s));
+    if (!run.batch) {  // batched right-hand sides run on concurrent host threads
+        P->hist_inner = std::move(hist_inner);
+        P->hist_res = std::move(hist_res);
+    }
     if (st) {
         std::memset(st, 0, sizeof(*st));
         st->outer_its = its;
@@ -1635,6 +1647,21 @@ void mxp_problem_destroy(mxp_problem* prob) {
     (void)hipSetDevice(prob->ctx->device);
     (void)hipStreamSynchronize(prob->ctx->stream);
     delete prob;
+}
+
+mxp_status mxp_solve_history(const mxp_problem* prob, int32_t cap, int32_t* inner_its, double* relres,
+                             int32_t* count) {
+    return guard([&]() {
+        if (!prob || !count) fail(MXP_ERR_INVALID_ARG, "problem or count is NULL");
+        if (cap < 0 || (cap > 0 && (!inner_its || !relres))) fail(MXP_ERR_INVALID_ARG, "history buffers");
+        const int32_t n = int32_t(prob->hist_inner.size());
+        *count = n;
+        for (int32_t k = 0; k < n && k < cap; ++k) {
+            inner_its[k] = prob->hist_inner[size_t(k)];
+            relres[k] = prob->hist_res[size_t(k)];
+        }
+        return MXP_OK;
+    });
 }
 
 int64_t mxp_problem_size(const mxp_problem* prob) { return prob ? prob->g.npts() : 0; }

@@ -78,3 +78,30 @@ def test_lens_table(ctx, dim, freq, prec):
     announce("paper lens table", dim, freq, prec)
     prob = wl.lens_problem(dim, freq)
     check(solve(ctx, prob, wl.lens_source(prob), 1.0 / freq, 0.08, prec), row)
+
+
+@pytest.mark.parametrize("freq", [40, 80])
+def test_unshifted_table_2d_first_iteration(ctx, freq):
+    # s = 0: the paper tabulates each outer iteration.  The number of outer
+    # iterations and the first one (its inner count and the residual after it)
+    # are compared; later inner counts depend on where each inner solve of an
+    # undamped fixed-point system crosses fprtol and are not pinned.
+    row = next(r for r in TABLES["noshift_2d"]["rows"] if r["freq"] == freq)
+    announce("paper unshifted table 2d", freq)
+    prob = wl.homog_problem(2, freq)
+    P = mxp.Problem(ctx, prob)
+    o = P.default_opts()
+    o.precision = mxp.MXP_PREC_FP64
+    o.rtol = 1e-5
+    o.shift = 0.0
+    o.fprtol = 0.01
+    fd = torch.from_numpy(wl.dipole_source(prob).ravel()).to("cuda:0")
+    u = torch.zeros_like(fd)
+    st = mxp.mxp_solve(P, o, fd, u)
+    inner, res = mxp.mxp_solve_history(P)
+    P.close()
+    assert st["status"] == mxp.MXP_OK
+    assert len(inner) == st["outer_its"] == len(res)
+    assert abs(len(inner) - len(row["inner"])) <= 1
+    assert abs(inner[0] - row["inner"][0]) <= 1
+    assert abs(res[0] - row["res"][0]) <= 0.05 * row["res"][0]

@@ -57,6 +57,7 @@ def test_homogeneous_model_and_dipole_source():
 def test_stored_paper_tables_are_well_formed():
     d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
     assert len(d["shift_2d"]["rows"]) == 16 and len(d["fprtol_3d"]["rows"]) == 12 and len(d["lens"]["rows"]) == 6
+    assert [len(r["inner"]) for r in d["noshift_2d"]["rows"]] == [3, 4, 4, 4]
     for key in ("shift_2d", "fprtol_3d", "lens"):
         assert d[key]["citation"].startswith("Section 5.")
         for r in d[key]["rows"]:
