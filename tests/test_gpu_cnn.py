@@ -12,7 +12,18 @@ bfloat16 boundary (2^-8 relative each, a small fraction of the elements).
 2e-3 relative in the 2-norm covers both with margin; a wrong tap, channel,
 transpose or mask is an O(1) error.  Without the rounding emulation the
 difference is the bfloat16 error itself (about 1e-2), checked separately
-against a looser bound."""
+against a looser bound.
+
+Gradients over larger volumes meet a second effect.  A one-ulp bf16 flip in
+an upstream activation moves a hidden pre-activation by a few 1e-4; where
+one lies that close to zero (in the 9 x 19 x 70 volume, -1.1e-4 against a
+typical 0.64) its ReLU mask flips, and one element of that layer's gradient
+changes by O(1).  A parameter gradient sums about V x 32 such elements with
+random signs, so one flip moves it by about 1/sqrt(V x 32) relative, times a
+few: 1e-2 measured there, from a single flipped mask element (located by
+point gradients, each of which agrees exactly elsewhere).  The larger volume
+therefore checks gradients to 3e-2, still far below the O(1) error of a
+wrong tap, channel or transpose; its forward pass keeps the 2e-3 bar."""
 import numpy as np
 import pytest
 
@@ -146,9 +157,10 @@ def test_backward_matches_oracle(ctx, shape):
         _, acts = emulated_forward(layers, x[b])
         gb = emulated_backward(layers, acts, gout[b].astype(np.float64))
         ref = gb if ref is None else [{k: r[k] + q[k] for k in r} for r, q in zip(ref, gb)]
+    tol = 2e-3 if shape == SHAPE else 3e-2  # mask flips near zero: module docstring
     for l in range(len(layers)):
-        assert rel(g[l]["w"], ref[l]["w"]) <= 2e-3, l
-        assert rel(g[l]["b"], ref[l]["b"]) <= 2e-3, l
+        assert rel(g[l]["w"], ref[l]["w"]) <= tol, l
+        assert rel(g[l]["b"], ref[l]["b"]) <= tol, l
     net.close()
 
 
