@@ -144,10 +144,15 @@ typedef struct {
     int32_t use_learned;    /* 1: learned network tried first at outer iterations (see below) */
     double stall_ratio;     /* in [0, 1]: > 0 keeps a learned z_j if the residual estimate drops
                                below this factor times the previous one; 0 (default) sets the
-                               factor from MatExPre's own reduction per second (see below) */
+                               factor from MatExPre's own iterations (see below) */
     int32_t use_graphs;     /* 1: each exp / psi_1 action is captured into a HIP graph on its
                                second use and replayed afterwards (single solves; the
                                results are identical); 0 (default): launched directly */
+    int32_t inner_solver;   /* solver of (I - exp(i t A_s)) w = psi_1(i t A_s) r inside
+                               Algorithm 1: 0 (default) GMRES(inner_restart); 1 the plain
+                               fixed-point iteration w <- exp(i t A_s) w + psi_1 r from w = 0
+                               (Section 2.2, Theorem 2.1), stopped by the same residual test;
+                               single solves only */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per

@@ -8,6 +8,8 @@ Paper passages followed:
     GMRES on (I - exp(i t A_s)) w = r to relative tolerance fprtol;
     return w                                                         (Section 3.4, Algorithm 1)
   * restart 30, outer relative tolerance                             (Section 4 intro)
+  * variant: the plain fixed-point iteration v <- exp(i t A) v + b from
+    zero instead of GMRES on the same system                         (Section 2.2, Theorem 2.1)
 
 Readings: inner GMRES starts from w = 0 and stops on the Arnoldi residual
 estimate relative to ||psi_1(i t A_s) r||; outer FGMRES starts from the given
@@ -107,11 +109,40 @@ class PrecondResult:
     rhat_norm: float
 
 
+def fixed_point_iteration(apply_E: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float,
+                          maxit: int, ref: float):
+    """The plain fixed-point iteration v_{k+1} = E v_k + b from v_0 = 0
+    (Section 2.2, Theorem 2.1).  Its residual b - (I - E) v_k is the step
+    v_{k+1} - v_k.  Returns the first iterate whose residual norm is at most
+    tol * ref (v_0 = 0 when ||b|| already is) and the number of E applications
+    made; v_1 = b takes none."""
+    v = np.zeros_like(b)
+    if np.linalg.norm(b) <= tol * ref:
+        return v, 0
+    v = b.copy()
+    its = 0
+    while its < maxit:
+        step = apply_E(v) + b - v
+        its += 1
+        if np.linalg.norm(step) <= tol * ref:
+            break
+        v = v + step
+    return v, its
+
+
 def precond_apply(As, t: float, r: np.ndarray, fprtol: float, restart: int = 30,
-                  maxit: int = 300) -> PrecondResult:
-    """Algorithm 1: M(r) with the constant -i t dropped."""
+                  maxit: int = 300, inner: str = "gmres") -> PrecondResult:
+    """Algorithm 1: M(r) with the constant -i t dropped.  inner = "gmres"
+    (the paper's) or "fixed_point" (Theorem 2.1's plain iteration)."""
     rhat = matfun.phi1_action(As, t, r)
     z = np.linalg.norm(rhat)
+    if inner == "fixed_point":
+        if z == 0.0:
+            return PrecondResult(np.zeros_like(rhat), 0, z)
+        w, its = fixed_point_iteration(lambda v: matfun.exp_action(As, t, v), rhat, fprtol, maxit, z)
+        return PrecondResult(w, its, z)
+    if inner != "gmres":
+        raise ValueError("inner must be 'gmres' or 'fixed_point'")
 
     def fixed_point_op(v):
         return v - matfun.exp_action(As, t, v)
@@ -193,7 +224,7 @@ def fgmres(A, b: np.ndarray, precond: Callable[[np.ndarray], np.ndarray], rtol: 
 
 def matexpre_solve(prob, f: np.ndarray, t: float, shift: float, fprtol: float = 0.08,
                    rtol: float = 1e-6, outer_restart: int = 30, inner_restart: int = 30,
-                   max_outer: int = 500, max_inner: int = 300) -> SolveResult:
+                   max_outer: int = 500, max_inner: int = 300, inner_solver: str = "gmres") -> SolveResult:
     """FGMRES on A u = -f preconditioned by Algorithm 1 with A_s."""
     from . import operator as op
     A = op.helmholtz(prob, 0.0)
@@ -202,7 +233,7 @@ def matexpre_solve(prob, f: np.ndarray, t: float, shift: float, fprtol: float = 
     inner: List[int] = []
 
     def M(v):
-        pr = precond_apply(As, t, v, fprtol, restart=inner_restart, maxit=max_inner)
+        pr = precond_apply(As, t, v, fprtol, restart=inner_restart, maxit=max_inner, inner=inner_solver)
         inner.append(pr.inner_iterations)
         return pr.w
 

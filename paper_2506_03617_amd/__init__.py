@@ -30,6 +30,7 @@ MXP_ERR_UNSUPPORTED = -6
 
 MXP_C64, MXP_C128, MXP_F32, MXP_F64 = 0, 1, 2, 3
 MXP_PREC_FP64, MXP_PREC_MIXED = 0, 1
+MXP_INNER_GMRES, MXP_INNER_FIXED_POINT = 0, 1
 
 
 class MxpError(RuntimeError):
@@ -69,6 +70,7 @@ class mxp_solve_opts(ctypes.Structure):
         ("use_learned", ctypes.c_int32),
         ("stall_ratio", ctypes.c_double),
         ("use_graphs", ctypes.c_int32),
+        ("inner_solver", ctypes.c_int32),
     ]
 
 

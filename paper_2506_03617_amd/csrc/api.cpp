@@ -1287,6 +1287,28 @@ static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<
     const double tol = o.fprtol * z;
     // Algorithm 1 tests the tolerance before the first inner iteration.
     if (z == 0.0 || z <= tol) return 0;
+    if (o.inner_solver == 1) {
+        // plain fixed-point iteration w <- exp(i t A_s) w + r_hat from w = 0
+        // (Theorem 2.1).  The residual r_hat - (I - exp(i t A_s)) w of the
+        // current iterate is also the step to the next one; the first iterate
+        // whose residual meets the test is returned.  w_1 = r_hat needs no
+        // action (w_0 = 0 failed the test above).
+        cpx<double>* d = V;
+        launch_scale(one, rhat, w, n, s);
+        int its = 0;
+        while (its < o.max_inner) {
+            action64(run, sc, o.t, o.shift, false, o.precision, w, d, &cnt.steps);
+            cnt.actions++;
+            ++its;
+            launch_axpby(one, rhat, one, d, n, s);  // exp(i t A_s) w + r_hat
+            launch_axpby(mone, w, one, d, n, s);    // minus w: the residual of w
+            const double res = norm2(run, d);
+            if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite fixed-point residual");
+            if (res <= tol) break;
+            launch_axpby(one, d, one, w, n, s);     // the next iterate
+        }
+        return its;
+    }
     const cpx<double>* rcur = rhat;
     double beta = z;
     int its = 0;
@@ -1360,6 +1382,7 @@ static void check_opts(const mxp_solve_opts* o) {
     if (o->cheb_S < 0 || o->cheb_m < 0) fail(MXP_ERR_INVALID_ARG, "cheb_S, cheb_m must be >= 0");
     if (o->use_learned && !(o->stall_ratio >= 0 && o->stall_ratio <= 1))
         fail(MXP_ERR_INVALID_ARG, "stall_ratio must be in [0, 1]");
+    if (o->inner_solver != 0 && o->inner_solver != 1) fail(MXP_ERR_INVALID_ARG, "inner_solver must be 0 or 1");
 }
 
 static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
@@ -1394,6 +1417,7 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
     }
     if (o.use_learned && !P->net) fail(MXP_ERR_INVALID_ARG, "use_learned needs a network (mxp_problem_set_learned)");
     if (o.use_learned && run.batch) fail(MXP_ERR_UNSUPPORTED, "the learned stage runs in single solves only");
+    if (o.inner_solver != 0 && run.batch) fail(MXP_ERR_UNSUPPORTED, "the fixed-point inner solver runs in single solves only");
     int misses = 0;
     // cost-aware acceptance: mean log residual reduction and wall time of the
     // MatExPre iterations so far, wall time of the last network try
@@ -1684,6 +1708,7 @@ mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out
         out->use_learned = 0;
         out->stall_ratio = 0.0;
         out->use_graphs = 0;
+        out->inner_solver = 0;
         return MXP_OK;
     });
 }
@@ -1833,6 +1858,9 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             if (!P) fail(MXP_ERR_INVALID_ARG, "batch: problem is NULL");
             if (P->ctx->device != ctx->device) fail(MXP_ERR_INVALID_ARG, "batch: problem on another device");
             check_opts(&opts[q]);
+            if (opts[q].use_learned) fail(MXP_ERR_UNSUPPORTED, "batch: the learned stage runs in single solves only");
+            if (opts[q].inner_solver != 0)
+                fail(MXP_ERR_UNSUPPORTED, "batch: the fixed-point inner solver runs in single solves only");
             if (nrhs[q] < 0) fail(MXP_ERR_INVALID_ARG, "batch: nrhs must be >= 0");
             if (nrhs[q] == 0) continue;
             if (!f[q] || !u[q] || f[q] == u[q]) fail(MXP_ERR_INVALID_ARG, "batch: f and u must be distinct non-NULL");

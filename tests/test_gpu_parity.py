@@ -310,3 +310,41 @@ def test_graph_replayed_actions_match_direct_launches(ctx, name, prec):
     w = torch.empty_like(r)
     assert mxp.mxp_apply_precond(P, o, r, w) == its
     assert torch.equal(w, w_ref)
+
+
+@pytest.mark.parametrize("name", ["2d-inh", "3d-inh"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fixed_point_inner_solver(ctx, name, prec):
+    # Theorem 2.1's plain iteration in place of inner GMRES: one apply against
+    # the oracle's, then whole solves (counts, and the iterate at rtol 1e-12)
+    prob = make(name)
+    announce("fixed-point inner", name, prec)
+    P = mxp.Problem(ctx, prob)
+    o = P.default_opts()
+    o.precision = prec
+    o.inner_solver = mxp.MXP_INNER_FIXED_POINT
+    r = wl.random_vector(prob.npts, 4)
+    rd = to_dev(r)
+    wd = torch.empty_like(rd)
+    its = mxp.mxp_apply_precond(P, o, rd, wd)
+    ref = krylov.precond_apply(op.helmholtz(prob, o.shift), o.t, r, o.fprtol, inner="fixed_point")
+    assert abs(its - ref.inner_iterations) <= 1
+    if its == ref.inner_iterations:
+        assert rel(to_host(wd), ref.w) <= (1e-10 if prec == 0 else 1e-5)
+    centre = tuple(m // 2 for m in prob.n)
+    f = wl.delta_source(prob, centre).ravel()
+    fd = to_dev(f)
+    ud = torch.zeros_like(fd)
+    st = mxp.mxp_solve(P, o, fd, ud)
+    sref = krylov.matexpre_solve(prob, f, o.t, o.shift, o.fprtol, o.rtol, inner_solver="fixed_point")
+    assert st["status"] == mxp.MXP_OK and st["true_relres"] <= o.rtol
+    assert abs(st["outer_its"] - sref.outer_iterations) <= 1
+    assert abs(st["inner_mean"] - sref.inner_mean) <= 1.0
+    o.rtol = 1e-12
+    ud.zero_()
+    st = mxp.mxp_solve(P, o, fd, ud)
+    assert st["true_relres"] <= 1e-12
+    assert rel(to_host(ud), krylov.direct_solve(prob, f)) <= (1e-10 if prec == 0 else 1e-5)
+    # batched solves keep to GMRES
+    with pytest.raises(mxp.MxpError):
+        mxp.mxp_solve_batch(ctx, [P], [o], [fd[None, :]], [ud[None, :].clone()], 1)

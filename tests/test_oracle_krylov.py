@@ -81,3 +81,42 @@ def test_inner_stop_is_relative_to_phi1_residual():
     assert true_res <= 0.08 * np.linalg.norm(rhat) * (1 + 1e-8)
     assert pr.rhat_norm == pytest.approx(np.linalg.norm(rhat))
     assert pr.inner_iterations >= 1
+
+
+def test_fixed_point_iteration_is_the_neumann_series():
+    # Theorem 2.1's iteration from zero: v_k = sum_{n<k} E^n b, residual E^k b.
+    # For a diagonal E the stopping index is known in closed form.
+    rng = np.random.default_rng(3)
+    N = 40
+    lam = 0.95 * rng.uniform(0.2, 1.0, N) * np.exp(2j * np.pi * rng.uniform(size=N))
+    E = np.diag(lam)
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    tol = 1e-3
+    v, its = krylov.fixed_point_iteration(lambda x: E @ x, b, tol, 10000, np.linalg.norm(b))
+    k = next(k for k in range(1, 10000) if np.linalg.norm(lam ** k * b) <= tol * np.linalg.norm(b))
+    assert its == k
+    partial = sum(lam ** n * b for n in range(k))
+    assert np.allclose(v, partial, rtol=1e-12, atol=1e-12)
+    # iteration limit: the iterate after the last step is returned, untested
+    v2, its2 = krylov.fixed_point_iteration(lambda x: E @ x, b, tol, 3, np.linalg.norm(b))
+    assert its2 == 3 and np.allclose(v2, sum(lam ** n * b for n in range(4)))
+    # tolerance met at v_0 = 0 only when tol >= 1
+    v3, its3 = krylov.fixed_point_iteration(lambda x: E @ x, b, 1.0, 10, np.linalg.norm(b))
+    assert its3 == 0 and not v3.any()
+
+
+def test_fixed_point_precond_meets_its_tolerance_and_solve_converges():
+    prob = _prob(n=(24, 22), layer=5)
+    t, s = prob.default_t(), prob.default_shift()
+    As = op.helmholtz(prob, s)
+    r = wl.random_vector(prob.npts, 5)
+    pr = krylov.precond_apply(As, t, r, 0.08, inner="fixed_point")
+    rhat = matfun.phi1_action(As, t, r)
+    resid = rhat - (pr.w - matfun.exp_action(As, t, pr.w))
+    assert np.linalg.norm(resid) <= 0.08 * np.linalg.norm(rhat)
+    assert pr.inner_iterations >= 1
+    # with the shift the plain iteration converges and the solve reaches the direct solution
+    f = wl.delta_source(prob, (12, 11))
+    res = krylov.matexpre_solve(prob, f, t, s, fprtol=0.08, rtol=1e-12, inner_solver="fixed_point")
+    ref = krylov.direct_solve(prob, f)
+    assert res.converged and np.linalg.norm(res.u - ref) <= 1e-10 * np.linalg.norm(ref)
