@@ -133,9 +133,10 @@ __device__ __forceinline__ T sload_words(const T* p) {
 // loop-invariant: a ghost neighbour gets weight zero and a clamped offset (no
 // branch around a load); the z boundary and the z tables are uniform.  OPS
 // marks the operands present (1: x, 2: b2, 4: b3, 8: D), so absent ones cost
-// no load.  Measured on 256^3: chunks of 8 planes in plain workgroup order
-// beat longer chunks and an XCD-contiguous renumbering (the halo rows are
-// served by L1 and the last-level cache, not a shared L2).
+// no load.  Measured on 256^3: 64 x 4 tiles with chunks of 16 planes in plain
+// workgroup order (taller tiles, 8-plane chunks and an XCD-contiguous
+// renumbering were as fast or slower: the halo rows are served by L1 and the
+// last-level cache, not a shared L2).
 // (at most four wavefronts per SIMD: with the default target of eight the
 // compiler serialises the complex-double loads to save registers)
 template <typename R, int OPS>
@@ -412,7 +413,7 @@ Sweep3DGeom sweep3d_geometry(const StencilArgs<R>& a) {
     Sweep3DGeom m;
     m.tiles_x = int((a.n0 + kBX - 1) / kBX);
     m.tiles_y = int((a.n1 + kBY - 1) / kBY);
-    m.zc = 8;
+    m.zc = 16;
     m.zchunks = int((a.n2 + m.zc - 1) / m.zc);
     return m;
 }

@@ -32,7 +32,7 @@ CASES = {
     "2d-inh": dict(n=(67, 45), layer=8, inh=True),
     "3d-homog": dict(n=(33, 29, 21), layer=4, inh=False),
     "3d-inh": dict(n=(33, 29, 21), layer=4, inh=True),
-    # z chunks of 8 planes with a ragged last chunk, ragged x and y tiles
+    # z chunks of 16 planes with a ragged last chunk, ragged x and y tiles
     "3d-ragged": dict(n=(70, 9, 37), layer=3, inh=True),
 }
 
