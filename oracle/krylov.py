@@ -9,7 +9,10 @@ Paper passages followed:
     return w                                                         (Section 3.4, Algorithm 1)
   * restart 30, outer relative tolerance                             (Section 4 intro)
   * variant: the plain fixed-point iteration v <- exp(i t A) v + b from
-    zero instead of GMRES on the same system                         (Section 2.2, Theorem 2.1)
+    zero instead of GMRES on the same system                         (Section 2.1, Theorem 2.1)
+  * variant: the second inverse formula, (I - psi_1(i t A_s)) w =
+    psi_2(i t A_s) r, by GMRES or by its fixed-point iteration, the
+    matrix form of the time-averaged map            (Section 3.1; Section 2.2, Theorem 2.2)
 
 Readings: inner GMRES starts from w = 0 and stops on the Arnoldi residual
 estimate relative to ||psi_1(i t A_s) r||; outer FGMRES starts from the given
@@ -112,7 +115,7 @@ class PrecondResult:
 def fixed_point_iteration(apply_E: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float,
                           maxit: int, ref: float):
     """The plain fixed-point iteration v_{k+1} = E v_k + b from v_0 = 0
-    (Section 2.2, Theorem 2.1).  Its residual b - (I - E) v_k is the step
+    (Section 2.1, Theorem 2.1).  Its residual b - (I - E) v_k is the step
     v_{k+1} - v_k.  Returns the first iterate whose residual norm is at most
     tol * ref (v_0 = 0 when ||b|| already is) and the number of E applications
     made; v_1 = b takes none."""
@@ -131,21 +134,37 @@ def fixed_point_iteration(apply_E: Callable[[np.ndarray], np.ndarray], b: np.nda
 
 
 def precond_apply(As, t: float, r: np.ndarray, fprtol: float, restart: int = 30,
-                  maxit: int = 300, inner: str = "gmres") -> PrecondResult:
+                  maxit: int = 300, inner: str = "gmres", form: str = "exp") -> PrecondResult:
     """Algorithm 1: M(r) with the constant -i t dropped.  inner = "gmres"
-    (the paper's) or "fixed_point" (Theorem 2.1's plain iteration)."""
-    rhat = matfun.phi1_action(As, t, r)
+    (the paper's) or "fixed_point" (Theorem 2.1's plain iteration).
+
+    form = "exp" solves (I - exp(i t A_s)) w = psi_1(i t A_s) r (eq. inverse-1);
+    form = "psi2" solves (I - psi_1(i t A_s)) w = psi_2(i t A_s) r, the second
+    inverse formula of Section 3.1, whose fixed-point iteration is the matrix
+    form of the time-averaged map of Theorem 2.2."""
+    if form == "exp":
+        rhat = matfun.phi1_action(As, t, r)
+
+        def E(v):
+            return matfun.exp_action(As, t, v)
+    elif form == "psi2":
+        rhat = matfun.phi2_action(As, t, r)
+
+        def E(v):
+            return matfun.phi1_action(As, t, v)
+    else:
+        raise ValueError("form must be 'exp' or 'psi2'")
     z = np.linalg.norm(rhat)
     if inner == "fixed_point":
         if z == 0.0:
             return PrecondResult(np.zeros_like(rhat), 0, z)
-        w, its = fixed_point_iteration(lambda v: matfun.exp_action(As, t, v), rhat, fprtol, maxit, z)
+        w, its = fixed_point_iteration(E, rhat, fprtol, maxit, z)
         return PrecondResult(w, its, z)
     if inner != "gmres":
         raise ValueError("inner must be 'gmres' or 'fixed_point'")
 
     def fixed_point_op(v):
-        return v - matfun.exp_action(As, t, v)
+        return v - E(v)
 
     res = gmres(fixed_point_op, rhat, fprtol, restart=restart, maxit=maxit, ref=z)
     return PrecondResult(res.x, res.iterations, z)
@@ -224,7 +243,8 @@ def fgmres(A, b: np.ndarray, precond: Callable[[np.ndarray], np.ndarray], rtol: 
 
 def matexpre_solve(prob, f: np.ndarray, t: float, shift: float, fprtol: float = 0.08,
                    rtol: float = 1e-6, outer_restart: int = 30, inner_restart: int = 30,
-                   max_outer: int = 500, max_inner: int = 300, inner_solver: str = "gmres") -> SolveResult:
+                   max_outer: int = 500, max_inner: int = 300, inner_solver: str = "gmres",
+                   form: str = "exp") -> SolveResult:
     """FGMRES on A u = -f preconditioned by Algorithm 1 with A_s."""
     from . import operator as op
     A = op.helmholtz(prob, 0.0)
@@ -233,7 +253,8 @@ def matexpre_solve(prob, f: np.ndarray, t: float, shift: float, fprtol: float = 
     inner: List[int] = []
 
     def M(v):
-        pr = precond_apply(As, t, v, fprtol, restart=inner_restart, maxit=max_inner, inner=inner_solver)
+        pr = precond_apply(As, t, v, fprtol, restart=inner_restart, maxit=max_inner, inner=inner_solver,
+                           form=form)
         inner.append(pr.inner_iterations)
         return pr.w
 

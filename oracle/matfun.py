@@ -7,11 +7,16 @@ Paper passages followed:
     method (the paper cites Al-Mohy--Higham and uses a restarted
     Krylov method, Section 4 intro)
 
+  * double time integral: (1/t) int_0^t int_0^s exp(i sigma A) d sigma ds
+    = t psi_2(i t A), and the second inverse formula
+    A^{-1} = -i t (I - psi_1(i t A))^{-1} psi_2(i t A)     (Section 3.1, after eq. inverse-1)
+
 Routes:
   (i)  dense: scipy.linalg.expm on the full matrix (tiny grids);
   (ii) scipy.sparse.linalg.expm_multiply (Al-Mohy--Higham 2011), with psi_1
        from the augmented matrix [[M, v], [0, 0]] whose exponential carries
-       psi_1(M) v in its last column;
+       psi_1(M) v in its last column, and psi_2 from
+       [[M, v, 0], [0, 0, 1], [0, 0, 0]] (last column: psi_2(M) v);
   (iii) closed form for the homogeneous operator without a layer: A_s is
        diagonalised by the type-I discrete sine transform.
 
@@ -70,6 +75,23 @@ def phi1_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
     return spla.expm_multiply(aug, e)[:N]
 
 
+def phi2_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
+    """psi_2(i t A_s) v via the exponential of the augmented matrix
+    [[i t A_s, v, 0], [0, 0, 1], [0, 0, 0]] applied to the last unit vector:
+    its top block is int_0^1 (1 - u) exp(u i t A_s) v du = psi_2(i t A_s) v."""
+    N = As.shape[0]
+    v = np.asarray(v, dtype=np.complex128)
+    M = (1j * t) * As.tocsc()
+    cols = sp.csc_matrix(np.stack([v, np.zeros_like(v)], axis=1))
+    top = sp.hstack([M, cols])
+    J = sp.csc_matrix(np.array([[0.0, 1.0], [0.0, 0.0]], dtype=np.complex128))
+    bottom = sp.hstack([sp.csc_matrix((2, N), dtype=np.complex128), J])
+    aug = sp.vstack([top, bottom]).tocsr()
+    e = np.zeros(N + 2, dtype=np.complex128)
+    e[-1] = 1.0
+    return spla.expm_multiply(aug, e)[:N]
+
+
 def exp_dense(As, t: float) -> np.ndarray:
     """exp(i t A_s) as a dense matrix (tiny grids)."""
     Ad = As.toarray() if sp.issparse(As) else np.asarray(As)
@@ -84,6 +106,18 @@ def phi1_dense(As, t: float) -> np.ndarray:
     aug[:N, :N] = (1j * t) * Ad
     aug[:N, N:] = np.eye(N)
     return sla.expm(aug)[:N, N:]
+
+
+def phi2_dense(As, t: float) -> np.ndarray:
+    """psi_2(i t A_s) as a dense matrix: the top-right block of
+    exp([[M, I, 0], [0, 0, I], [0, 0, 0]]), M = i t A_s."""
+    Ad = As.toarray() if sp.issparse(As) else np.asarray(As)
+    N = Ad.shape[0]
+    aug = np.zeros((3 * N, 3 * N), dtype=np.complex128)
+    aug[:N, :N] = (1j * t) * Ad
+    aug[:N, N:2 * N] = np.eye(N)
+    aug[N:2 * N, 2 * N:] = np.eye(N)
+    return sla.expm(aug)[:N, 2 * N:]
 
 
 def dirichlet_eigs(n: int, h: float) -> np.ndarray:

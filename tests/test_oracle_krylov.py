@@ -120,3 +120,35 @@ def test_fixed_point_precond_meets_its_tolerance_and_solve_converges():
     res = krylov.matexpre_solve(prob, f, t, s, fprtol=0.08, rtol=1e-12, inner_solver="fixed_point")
     ref = krylov.direct_solve(prob, f)
     assert res.converged and np.linalg.norm(res.u - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_psi2_form_precond_is_scaled_inverse_when_inner_solve_is_exact():
+    # (I - psi_1(i t A_s))^{-1} psi_2(i t A_s) r = (i / t) A_s^{-1} r (Section 3.1)
+    prob = wl.small_problem((14, 12), layer=3, ppw=10, inhomogeneous=True, seed=2)
+    s = 1.0 / prob.freq
+    As = op.helmholtz(prob, s)
+    t = prob.default_t()
+    r = wl.random_vector(prob.npts, 9)
+    pr = krylov.precond_apply(As, t, r, 1e-12, restart=200, maxit=400, form="psi2")
+    ref = (1j / t) * spla.spsolve(As.tocsc(), r)
+    assert np.linalg.norm(pr.w - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_psi2_form_fixed_point_meets_tolerance_and_solve_converges():
+    prob = wl.small_problem((16, 14), layer=3, ppw=10, inhomogeneous=False, seed=3)
+    s = 1.0 / prob.freq
+    As = op.helmholtz(prob, s)
+    t = prob.default_t()
+    r = wl.random_vector(prob.npts, 10)
+    pr = krylov.precond_apply(As, t, r, 0.08, inner="fixed_point", form="psi2")
+    rhat = matfun.phi2_action(As, t, r)
+    res = rhat - (pr.w - matfun.phi1_action(As, t, pr.w))
+    assert np.linalg.norm(res) <= 0.08 * np.linalg.norm(rhat) * (1 + 1e-12)
+    assert pr.inner_iterations >= 1
+    f = wl.delta_source(prob, tuple(k // 2 for k in prob.n))
+    for inner in ("gmres", "fixed_point"):
+        sol = krylov.matexpre_solve(prob, f, t, s, inner_solver=inner, form="psi2")
+        assert sol.converged
+        A = op.helmholtz(prob, 0.0)
+        b = op.rhs(f)
+        assert np.linalg.norm(b - A @ sol.u) <= 1e-6 * np.linalg.norm(b) * (1 + 1e-9)

@@ -133,3 +133,81 @@ def test_truncated_preconditioner_spectrum(N):
     radius = math.exp(-(N + 1) * t * lam_star)
     assert np.abs(mu - 1).max() <= radius * (1 + 1e-9) + 1e-12
     assert np.abs(mu - 1).max() >= radius * (1 - 1e-6)
+
+
+def test_phi2_routes_agree_and_match_double_integral():
+    # t^2 psi_2(i t A) v = int_0^t (t - tau) exp(i tau A) v d tau, the double time
+    # integral of Section 3.1 with the inner integral done; Gauss-Legendre in tau over
+    # the eigendecomposition (independent of the augmented-exponential routes)
+    prob, As, t = _tiny(shift=0.05, dim=2, inh=True)
+    v = wl.random_vector(prob.npts, 7)
+    P2 = matfun.phi2_dense(As, t)
+    got = matfun.phi2_action(As, t, v)
+    assert np.linalg.norm(got - P2 @ v) <= 1e-12 * np.linalg.norm(P2 @ v)
+    xg, wg = np.polynomial.legendre.leggauss(60)
+    lam, X = np.linalg.eig(As.toarray())
+    c = np.linalg.solve(X, v)
+    integ = np.zeros(prob.npts, dtype=complex)
+    panels = 64
+    for p in range(panels):
+        a, b = p * t / panels, (p + 1) * t / panels
+        for x, w in zip(xg, wg):
+            tau = 0.5 * (b - a) * x + 0.5 * (a + b)
+            integ += 0.5 * (b - a) * w * (t - tau) * (X @ (np.exp(1j * tau * lam) * c))
+    assert np.linalg.norm(t * t * (P2 @ v) - integ) <= 1e-8 * np.linalg.norm(integ)
+
+
+def test_phi2_dense_closed_form_when_invertible():
+    # psi_2(M) = M^{-2}(e^M - I - M) for invertible M (Definition psi)
+    prob, As, t = _tiny(shift=0.02)
+    M = 1j * t * As.toarray()
+    I = np.eye(M.shape[0])
+    ref = np.linalg.solve(M, np.linalg.solve(M, sla.expm(M) - I - M))
+    P2 = matfun.phi2_dense(As, t)
+    assert np.abs(P2 - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_phi2_action_matches_dst_closed_form_without_layer():
+    # no layer: psi_2(i t A_s) is diagonal in the DST-I basis with entries psi_2(i t lambda_k)
+    import scipy.fft
+    prob = wl.small_problem((24, 20), layer=0)
+    s = 0.04
+    As = op.helmholtz(prob, s)
+    t = prob.default_t()
+    v = wl.random_vector(prob.npts, 8)
+    shape = tuple(reversed(prob.n))
+    lam = np.full(shape, prob.omega**2 * (1 + 1j * s))
+    lam = lam + matfun.dirichlet_eigs(prob.n[0], prob.h)[None, :] + matfun.dirichlet_eigs(prob.n[1], prob.h)[:, None]
+    W = scipy.fft.dstn(v.reshape(shape), type=1, norm="ortho")
+    W = W * np.vectorize(lambda z: matfun.psi_scalar(2, 1j * t * z))(lam)
+    ref = scipy.fft.idstn(W, type=1, norm="ortho").ravel()
+    got = matfun.phi2_action(As, t, v)
+    assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.1])
+def test_second_inverse_identity(shift):
+    # Section 3.1: A^{-1} = -i t (I - psi_1(i t A))^{-1} psi_2(i t A)
+    prob, A, t = _tiny(shift=shift, inh=True)
+    Ad = A.toarray()
+    P1 = matfun.phi1_dense(A, t)
+    P2 = matfun.phi2_dense(A, t)
+    lhs = -1j * t * np.linalg.solve(np.eye(Ad.shape[0]) - P1, P2)
+    Ainv = np.linalg.inv(Ad)
+    assert np.abs(lhs - Ainv).max() <= 1e-9 * np.abs(Ainv).max()
+
+
+def test_time_averaged_map_contraction_per_mode():
+    # Theorem 2.2's per-mode factor: for Im(lambda) >= 0 the eigenvalue psi_1(i t lambda)
+    # of the time-averaged map has modulus at most min(1, 2 / (|lambda| t))
+    prob, A, t = _tiny(shift=0.0)
+    lam = np.linalg.eigvals(A.toarray())
+    assert lam.imag.min() > 0
+    mu = np.linalg.eigvals(matfun.phi1_dense(A, t))
+    bound = np.minimum(1.0, 2.0 / (np.abs(lam) * t))
+    # match each computed eigenvalue of psi_1(i t A) to psi_1(i t lambda_k)
+    pred = np.array([matfun.psi_scalar(1, 1j * t * z) for z in lam])
+    d = np.abs(mu[:, None] - pred[None, :])
+    assert d.min(axis=1).max() <= 1e-9
+    assert np.all(np.abs(pred) <= bound * (1 + 1e-12))
+    assert np.abs(mu).max() < 1.0
