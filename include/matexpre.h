@@ -148,11 +148,17 @@ typedef struct {
     int32_t use_graphs;     /* 1: each exp / psi_1 action is captured into a HIP graph on its
                                second use and replayed afterwards (single solves; the
                                results are identical); 0 (default): launched directly */
-    int32_t inner_solver;   /* solver of (I - exp(i t A_s)) w = psi_1(i t A_s) r inside
-                               Algorithm 1: 0 (default) GMRES(inner_restart); 1 the plain
-                               fixed-point iteration w <- exp(i t A_s) w + psi_1 r from w = 0
-                               (Section 2.2, Theorem 2.1), stopped by the same residual test;
-                               single solves only */
+    int32_t inner_solver;   /* inner system and solver of Algorithm 1:
+                               0 (default) GMRES(inner_restart) on
+                                 (I - exp(i t A_s)) w = psi_1(i t A_s) r;
+                               1 the plain fixed-point iteration w <- exp(i t A_s) w + psi_1 r
+                                 from w = 0 (Section 2.1, Theorem 2.1), stopped by the same
+                                 residual test;
+                               2 GMRES(inner_restart) on (I - psi_1(i t A_s)) w = psi_2(i t A_s) r,
+                                 the second inverse formula of Section 3.1;
+                               3 its fixed-point iteration w <- psi_1(i t A_s) w + psi_2 r, the
+                                 time-averaged map of Section 2.2, Theorem 2.2.
+                               Nonzero values: single solves only */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per
@@ -221,10 +227,20 @@ mxp_status mxp_apply_exp(mxp_problem* prob, double t, double shift, mxp_dtype dt
 mxp_status mxp_apply_psi1(mxp_problem* prob, double t, double shift, mxp_dtype dtype,
                           const void* x, void* y);
 
+/* y = psi_2(i t A_s) x  (Section 3.1: t psi_2(i t A) is the time average over
+ * [0, t] of the integral of exp(i tau A) from 0).  Evaluated on the exp
+ * schedule's substeps: one psi_2 series and two psi_1 series at tau = t/S plus
+ * S - 2 exp series.  Same arguments, layout and errors as mxp_apply_exp;
+ * UNSUPPORTED if no psi_2 series within 512 terms meets the precision's bound. */
+mxp_status mxp_apply_psi2(mxp_problem* prob, double t, double shift, mxp_dtype dtype,
+                          const void* x, void* y);
+
 /* w = M(r), Algorithm 1 (Section 3.4): psi_1 action, then GMRES from w = 0 on
  * (I - exp(i t A_s)) w = psi_1(i t A_s) r until the residual estimate is
  * <= fprtol * ||psi_1(i t A_s) r||.  r and w are complex double; with
  * MXP_PREC_MIXED the matrix-function actions run in complex float.
+ * opts->inner_solver selects the inner system and solver (the psi_2 form
+ * returns w ~ (I - psi_1(i t A_s))^{-1} psi_2(i t A_s) r).
  * *inner_its (may be NULL) receives the inner iteration count. */
 mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r,
                              void* w, int32_t* inner_its);

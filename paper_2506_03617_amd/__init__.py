@@ -30,7 +30,7 @@ MXP_ERR_UNSUPPORTED = -6
 
 MXP_C64, MXP_C128, MXP_F32, MXP_F64 = 0, 1, 2, 3
 MXP_PREC_FP64, MXP_PREC_MIXED = 0, 1
-MXP_INNER_GMRES, MXP_INNER_FIXED_POINT = 0, 1
+MXP_INNER_GMRES, MXP_INNER_FIXED_POINT, MXP_INNER_PSI2_GMRES, MXP_INNER_PSI2_FIXED_POINT = 0, 1, 2, 3
 
 
 class MxpError(RuntimeError):
@@ -123,7 +123,7 @@ ABI_SYMBOLS = (
     "mxp_context_create", "mxp_context_destroy", "mxp_last_error", "mxp_version",
     "mxp_problem_create", "mxp_problem_destroy", "mxp_problem_size",
     "mxp_solve_opts_default", "mxp_design_schedule",
-    "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_precond", "mxp_solve",
+    "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_psi2", "mxp_apply_precond", "mxp_solve",
     "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
     "mxp_cnn_num_params", "mxp_cnn_create", "mxp_cnn_destroy", "mxp_cnn_get_params", "mxp_cnn_set_params",
     "mxp_cnn_get_grads", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
@@ -155,6 +155,7 @@ def _load():
         "mxp_apply_A": (st, [P, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_exp": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_psi1": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
+        "mxp_apply_psi2": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_precond": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(ctypes.c_int32)]),
         "mxp_solve": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(mxp_solve_stats)]),
         "mxp_set_tiles": (st, [P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -344,6 +345,10 @@ def mxp_apply_exp(prob: Problem, t: float, shift: float, x, y) -> None:
 
 def mxp_apply_psi1(prob: Problem, t: float, shift: float, x, y) -> None:
     _check(lib.mxp_apply_psi1(prob.handle, t, shift, _dtype_of(x), _ptr(x), _ptr(y)))
+
+
+def mxp_apply_psi2(prob: Problem, t: float, shift: float, x, y) -> None:
+    _check(lib.mxp_apply_psi2(prob.handle, t, shift, _dtype_of(x), _ptr(x), _ptr(y)))
 
 
 def mxp_apply_precond(prob: Problem, opts: mxp_solve_opts, r, w) -> int:

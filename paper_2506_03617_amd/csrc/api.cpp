@@ -69,7 +69,15 @@ struct DiagTables {
 struct Sched {
     mxp_schedule s;
     DiagTables diag;
+    double t = 0.0;
+    mxp_precision prec = MXP_PREC_FP64;
+    // psi_2 series on the same segment, designed at its first use
+    mutable std::vector<double> coef_psi2;
+    mutable int m_psi2 = -1;
 };
+
+// Which matrix function an action applies.
+enum ActFn { ACT_EXP = 0, ACT_PSI1 = 1, ACT_PSI2 = 2 };
 
 // Tile configuration of the temporally blocked 2D Clenshaw pass.
 struct TileCfg {
@@ -91,13 +99,13 @@ struct GraphEntry {
 
 struct Workspace {
     // [0..5] pass/substep buffers, [6] psi addend, (f64) [7..8] graph input /
-    // output, (f32) [7..8] casts
-    DevMem act64[9], act32[10];
+    // output, (f32) [7..8] casts, [9] the psi_2 action's first-substep term
+    DevMem act64[10], act32[10];
     DevMem innerV, innerRh, innerTmp, innerRr;
     DevMem outerV, outerZ, outerR;
     DevMem partial, small;
     std::vector<cpx<double>> host_small;
-    // captured actions, keyed by (schedule, psi, precision); the stream they
+    // captured actions, keyed by (schedule, function, precision); the stream they
     // replay on and the events that order it with the solve's stream
     std::map<std::tuple<const void*, int, int>, GraphEntry> graphs;
     hipStream_t gstream = nullptr;
@@ -310,6 +318,8 @@ static const Sched& get_sched(mxp_problem* P, double t, double shift, mxp_precis
     auto sc = std::make_unique<Sched>();
     design_schedule(P->g, t, shift, prec, &sc->s, forceS, forcem);
     build_diag(P, shift, cd(sc->s.centre_re, sc->s.centre_im), sc->diag);
+    sc->t = t;
+    sc->prec = prec;
     const Sched& ref = *sc;
     P->scheds.emplace(key, std::move(sc));
     return ref;
@@ -601,11 +611,13 @@ static void cheb_series_fused(mxp_problem* P, const Emit<R>& em, const StencilAr
 template <typename R>
 static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s);
 
-// y = exp(i t A_s) x (psi = false) or psi_1(i t A_s) x (psi = true), precision R.
+// y = exp(i t A_s) x, psi_1(i t A_s) x or psi_2(i t A_s) x (fn), precision R.
 // x and y distinct device vectors of precision R; buffers from workspace ws.
 template <typename R>
 static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched& sd, double t, double shift,
-                   bool psi, const cpx<R>* x, cpx<R>* y, int64_t* steps) {
+                   int fn, const cpx<R>* x, cpx<R>* y, int64_t* steps) {
+    if (fn < ACT_EXP || fn > ACT_PSI2) fail(MXP_ERR_INVALID_ARG, "unknown matrix function");
+    const bool psi = fn == ACT_PSI1;
     const mxp_schedule& sc = sd.s;
     const int64_t n = npts(P);
     DevMem* W = act_buffers<R>(ws);
@@ -654,6 +666,39 @@ static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched
         pick(xin, b, &spare);
         return spare;
     };
+    if (fn == ACT_PSI2) {
+        // With tau = t/S, E = exp(i tau A_s) and F = tau psi_1(i tau A_s):
+        //   t^2 psi_2(i t A_s) x = S y_1 + F (g_1 + ... + g_{S-1}),
+        // y_1 = tau^2 psi_2(i tau A_s) x, g_1 = F x, g_{k+1} = E g_k + g_1
+        // (split the double time integral at the substeps).  The running sum
+        // G_k = g_1 + ... + g_k obeys G_{k+1} = E G_k + (k+1) g_1, so its mean
+        // H_k = G_k / k obeys H_{k+1} = (k/(k+1)) E H_k + g_1: one exp series
+        // with scaled coefficients per substep, and no extra vector update.
+        if (sd.m_psi2 < 0) design_psi2_series(sc, sd.t, sd.prec, &sd.coef_psi2, &sd.m_psi2);
+        const double it2 = 1.0 / (t * t);
+        if (S == 1) {
+            series(sd.coef_psi2.data(), sd.m_psi2, x, y, cd(it2, 0.0), nullptr);
+            return;
+        }
+        W[9].ensure(size_t(n) * sizeof(cpx<R>));
+        cpx<R>* y1 = W[9].as<cpx<R>>();
+        series(sd.coef_psi2.data(), sd.m_psi2, x, y1, cd(1.0, 0.0), nullptr);
+        series(sc.coef_psi, sc.m_psi, x, pbuf, cd(1.0, 0.0), nullptr);  // g_1 = H_1
+        const cpx<R>* hk = pbuf;
+        std::vector<double> scaled(2 * size_t(std::max(sc.m, sc.m_psi) + 1));
+        for (int k = 1; k <= S - 2; ++k) {
+            const double f = double(k) / double(k + 1);
+            for (int i = 0; i < 2 * (sc.m + 1); ++i) scaled[i] = f * sc.coef[i];
+            cpx<R>* out = substep_out(hk);
+            series(scaled.data(), sc.m, hk, out, cd(1.0, 0.0), pbuf);
+            hk = out;
+        }
+        // t^2 psi_2 x = S (((S-1)/S) F H_{S-1} + y_1)
+        const double f = double(S - 1) / double(S);
+        for (int i = 0; i < 2 * (sc.m_psi + 1); ++i) scaled[i] = f * sc.coef_psi[i];
+        series(scaled.data(), sc.m_psi, hk, y, cd(double(S) * it2, 0.0), y1);
+        return;
+    }
     const cpx<R>* xcur = x;
     int first = 0;
     const cpx<R>* add = nullptr;
@@ -866,16 +911,16 @@ static void upload_coeffs(Run& run, const std::vector<cd>& y) {
     HIP_CHECK(hipStreamSynchronize(run.s));
 }
 
-// y = exp or psi_1 action on complex-double vectors, in the requested
+// y = exp, psi_1 or psi_2 action (fn) on complex-double vectors, in the requested
 // precision, enqueued on stream s with workspace ws, or recorded into
 // rec64 / rec32 when given (the caller then launches the records and, for
 // the mixed form, the cast back).  The mixed form casts at the boundary.
 static void action64_on(mxp_problem* P, Workspace& ws, hipStream_t s, const Sched& sc, double t, double shift,
-                        bool psi, mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps,
+                        int fn, mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps,
                         std::vector<StepRec<double>>* rec64 = nullptr,
                         std::vector<StepRec<float>>* rec32 = nullptr) {
     if (prec == MXP_PREC_FP64) {
-        action<double>(P, ws, Emit<double>{s, rec64}, sc, t, shift, psi, x, y, steps);
+        action<double>(P, ws, Emit<double>{s, rec64}, sc, t, shift, fn, x, y, steps);
         return;
     }
     const int64_t n = npts(P);
@@ -884,23 +929,23 @@ static void action64_on(mxp_problem* P, Workspace& ws, hipStream_t s, const Sche
     cpx<float>* xs = ws.act32[7].as<cpx<float>>();
     cpx<float>* ys = ws.act32[8].as<cpx<float>>();
     launch_to_c64(x, xs, n, s);
-    action<float>(P, ws, Emit<float>{s, rec32}, sc, t, shift, psi, xs, ys, steps);
+    action<float>(P, ws, Emit<float>{s, rec32}, sc, t, shift, fn, xs, ys, steps);
     if (!rec32) launch_to_c128(ys, y, n, s);
 }
 
-static void action64(Run& run, const Sched& sc, double t, double shift, bool psi, mxp_precision prec,
+static void action64(Run& run, const Sched& sc, double t, double shift, int fn, mxp_precision prec,
                      const cpx<double>* x, cpx<double>* y, int64_t* steps);
 
 // The same action from a captured HIP graph.  The graph reads a fixed input
 // buffer and writes a fixed output buffer of the workspace (the mixed form's
 // cast buffers, or two complex-double staging buffers), so one capture per
-// (schedule, psi, precision) serves every call: the input is staged, the
+// (schedule, function, precision) serves every call: the input is staged, the
 // graph replays on the workspace's stream (ordered after and before the
 // caller's stream by events) and the output is copied out.  The first use of
 // a key runs eagerly (it allocates the buffers and tunes the tiles), the
 // second captures.  Kernels only: nothing in an action is a memset or a copy.
 static void action64_graph(mxp_problem* P, Workspace& ws, hipStream_t s, const Sched& sc, double t, double shift,
-                           bool psi, mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps) {
+                           int fn, mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps) {
     const int64_t n = npts(P);
     const bool f32 = prec != MXP_PREC_FP64;
     DevMem* in = f32 ? &ws.act32[7] : &ws.act64[7];
@@ -912,13 +957,13 @@ static void action64_graph(mxp_problem* P, Workspace& ws, hipStream_t s, const S
     else launch_scale({1.0, 0.0}, x, in->as<cpx<double>>(), n, s);
     auto run_action = [&](hipStream_t st, int64_t* cnt) {
         if (f32)
-            action<float>(P, ws, Emit<float>{st, nullptr}, sc, t, shift, psi, in->as<cpx<float>>(),
+            action<float>(P, ws, Emit<float>{st, nullptr}, sc, t, shift, fn, in->as<cpx<float>>(),
                           out->as<cpx<float>>(), cnt);
         else
-            action<double>(P, ws, Emit<double>{st, nullptr}, sc, t, shift, psi, in->as<cpx<double>>(),
+            action<double>(P, ws, Emit<double>{st, nullptr}, sc, t, shift, fn, in->as<cpx<double>>(),
                            out->as<cpx<double>>(), cnt);
     };
-    GraphEntry& ge = ws.graphs[std::make_tuple(static_cast<const void*>(&sc), int(psi), int(prec))];
+    GraphEntry& ge = ws.graphs[std::make_tuple(static_cast<const void*>(&sc), fn, int(prec))];
     if (ge.uses++ == 0) {
         run_action(s, steps);
     } else {
@@ -1222,15 +1267,17 @@ class Batcher {
     int64_t launches_ = 0;
 };
 
-static void action64(Run& run, const Sched& sc, double t, double shift, bool psi, mxp_precision prec,
+static void action64(Run& run, const Sched& sc, double t, double shift, int fn, mxp_precision prec,
                      const cpx<double>* x, cpx<double>* y, int64_t* steps) {
     if (!run.batch) {
         if (run.graphs)
-            action64_graph(run.P, *run.W, run.s, sc, t, shift, psi, prec, x, y, steps);
+            action64_graph(run.P, *run.W, run.s, sc, t, shift, fn, prec, x, y, steps);
         else
-            action64_on(run.P, *run.W, run.s, sc, t, shift, psi, prec, x, y, steps);
+            action64_on(run.P, *run.W, run.s, sc, t, shift, fn, prec, x, y, steps);
         return;
     }
+    if (fn == ACT_PSI2) fail(MXP_ERR_UNSUPPORTED, "batched solves apply exp and psi_1 actions only");
+    const bool psi = fn == ACT_PSI1;
     ActionReq r;
     r.run = &run;
     r.sd = &sc;
@@ -1279,28 +1326,35 @@ static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<
     cpx<double>* rr = WS.innerRr.as<cpx<double>>();
     const cpx<double> one{1.0, 0.0}, mone{-1.0, 0.0};
 
-    // r_hat = psi_1(i t A_s) r; z = ||r_hat||
-    action64(run, sc, o.t, o.shift, true, o.precision, r, rhat, &cnt.steps);
+    // The exp form (inner_solver 0, 1) solves (I - exp(i t A_s)) w = psi_1(i t A_s) r;
+    // the psi_2 form (2, 3) solves (I - psi_1(i t A_s)) w = psi_2(i t A_s) r, the
+    // second inverse formula (Section 3.1), whose fixed-point map is the
+    // time-averaged one of Theorem 2.2.  Both return w without the factor -i t.
+    const bool form2 = o.inner_solver >= 2;
+    const int fn_rhs = form2 ? ACT_PSI2 : ACT_PSI1;
+    const int fn_op = form2 ? ACT_PSI1 : ACT_EXP;
+    // r_hat = psi_1(i t A_s) r (or psi_2); z = ||r_hat||
+    action64(run, sc, o.t, o.shift, fn_rhs, o.precision, r, rhat, &cnt.steps);
     cnt.actions++;
     const double z = norm2(run, rhat);
     launch_zero<double>(w, n, s);
     const double tol = o.fprtol * z;
     // Algorithm 1 tests the tolerance before the first inner iteration.
     if (z == 0.0 || z <= tol) return 0;
-    if (o.inner_solver == 1) {
-        // plain fixed-point iteration w <- exp(i t A_s) w + r_hat from w = 0
-        // (Theorem 2.1).  The residual r_hat - (I - exp(i t A_s)) w of the
-        // current iterate is also the step to the next one; the first iterate
-        // whose residual meets the test is returned.  w_1 = r_hat needs no
-        // action (w_0 = 0 failed the test above).
+    if (o.inner_solver == 1 || o.inner_solver == 3) {
+        // plain fixed-point iteration w <- E w + r_hat from w = 0, E the
+        // form's operator (Theorems 2.1 and 2.2).  The residual r_hat - (I - E) w
+        // of the current iterate is also the step to the next one; the first
+        // iterate whose residual meets the test is returned.  w_1 = r_hat needs
+        // no action (w_0 = 0 failed the test above).
         cpx<double>* d = V;
         launch_scale(one, rhat, w, n, s);
         int its = 0;
         while (its < o.max_inner) {
-            action64(run, sc, o.t, o.shift, false, o.precision, w, d, &cnt.steps);
+            action64(run, sc, o.t, o.shift, fn_op, o.precision, w, d, &cnt.steps);
             cnt.actions++;
             ++its;
-            launch_axpby(one, rhat, one, d, n, s);  // exp(i t A_s) w + r_hat
+            launch_axpby(one, rhat, one, d, n, s);  // E w + r_hat
             launch_axpby(mone, w, one, d, n, s);    // minus w: the residual of w
             const double res = norm2(run, d);
             if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite fixed-point residual");
@@ -1322,9 +1376,9 @@ static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<
         for (int j = 0; j < m; ++j) {
             cpx<double>* vj = V + size_t(j) * n;
             cpx<double>* vn = V + size_t(j + 1) * n;
-            action64(run, sc, o.t, o.shift, false, o.precision, vj, tmp, &cnt.steps);
+            action64(run, sc, o.t, o.shift, fn_op, o.precision, vj, tmp, &cnt.steps);
             cnt.actions++;
-            // v_{j+1} <- v_j - exp(i t A_s) v_j
+            // v_{j+1} <- v_j - E v_j
             launch_scale(one, vj, vn, n, s);
             launch_axpby(mone, tmp, one, vn, n, s);
             const double hn = cgs2(run, V, n, j + 1, vn, h);
@@ -1344,8 +1398,8 @@ static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<
         upload_coeffs(run, y);
         launch_mcombine(w, V, n, k, small_buffers(run).y, n, s);
         if (conv || its >= o.max_inner) break;
-        // restart: r = r_hat - (w - exp(i t A_s) w)
-        action64(run, sc, o.t, o.shift, false, o.precision, w, tmp, &cnt.steps);
+        // restart: r = r_hat - (w - E w)
+        action64(run, sc, o.t, o.shift, fn_op, o.precision, w, tmp, &cnt.steps);
         cnt.actions++;
         launch_scale(one, rhat, rr, n, s);
         launch_axpby(mone, w, one, rr, n, s);
@@ -1382,7 +1436,7 @@ static void check_opts(const mxp_solve_opts* o) {
     if (o->cheb_S < 0 || o->cheb_m < 0) fail(MXP_ERR_INVALID_ARG, "cheb_S, cheb_m must be >= 0");
     if (o->use_learned && !(o->stall_ratio >= 0 && o->stall_ratio <= 1))
         fail(MXP_ERR_INVALID_ARG, "stall_ratio must be in [0, 1]");
-    if (o->inner_solver != 0 && o->inner_solver != 1) fail(MXP_ERR_INVALID_ARG, "inner_solver must be 0 or 1");
+    if (o->inner_solver < 0 || o->inner_solver > 3) fail(MXP_ERR_INVALID_ARG, "inner_solver must be 0, 1, 2 or 3");
 }
 
 static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
@@ -1417,7 +1471,7 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
     }
     if (o.use_learned && !P->net) fail(MXP_ERR_INVALID_ARG, "use_learned needs a network (mxp_problem_set_learned)");
     if (o.use_learned && run.batch) fail(MXP_ERR_UNSUPPORTED, "the learned stage runs in single solves only");
-    if (o.inner_solver != 0 && run.batch) fail(MXP_ERR_UNSUPPORTED, "the fixed-point inner solver runs in single solves only");
+    if (o.inner_solver != 0 && run.batch) fail(MXP_ERR_UNSUPPORTED, "the inner-solver variants run in single solves only");
     int misses = 0;
     // cost-aware acceptance: mean log residual reduction and wall time of the
     // MatExPre iterations so far, wall time of the last network try
@@ -1749,18 +1803,18 @@ mxp_status mxp_apply_A(mxp_problem* prob, double shift, mxp_dtype dtype, const v
 }
 
 static mxp_status apply_fn(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
-                           void* y, bool psi) {
+                           void* y, int fn) {
     return guard([&]() {
         check_problem(prob);
         if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
         int64_t steps = 0;
         if (dtype == MXP_C128) {
             const Sched& sc = get_sched(prob, t, shift, MXP_PREC_FP64, 0, 0);
-            action<double>(prob, prob->ws, Emit<double>{prob->ctx->stream, nullptr}, sc, t, shift, psi,
+            action<double>(prob, prob->ws, Emit<double>{prob->ctx->stream, nullptr}, sc, t, shift, fn,
                            static_cast<const cpx<double>*>(x), static_cast<cpx<double>*>(y), &steps);
         } else if (dtype == MXP_C64) {
             const Sched& sc = get_sched(prob, t, shift, MXP_PREC_MIXED, 0, 0);
-            action<float>(prob, prob->ws, Emit<float>{prob->ctx->stream, nullptr}, sc, t, shift, psi,
+            action<float>(prob, prob->ws, Emit<float>{prob->ctx->stream, nullptr}, sc, t, shift, fn,
                           static_cast<const cpx<float>*>(x), static_cast<cpx<float>*>(y), &steps);
         } else {
             fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
@@ -1772,12 +1826,17 @@ static mxp_status apply_fn(mxp_problem* prob, double t, double shift, mxp_dtype 
 
 mxp_status mxp_apply_exp(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
                          void* y) {
-    return apply_fn(prob, t, shift, dtype, x, y, false);
+    return apply_fn(prob, t, shift, dtype, x, y, ACT_EXP);
 }
 
 mxp_status mxp_apply_psi1(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
                           void* y) {
-    return apply_fn(prob, t, shift, dtype, x, y, true);
+    return apply_fn(prob, t, shift, dtype, x, y, ACT_PSI1);
+}
+
+mxp_status mxp_apply_psi2(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
+                          void* y) {
+    return apply_fn(prob, t, shift, dtype, x, y, ACT_PSI2);
 }
 
 mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r, void* w,

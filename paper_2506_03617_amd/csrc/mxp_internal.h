@@ -77,4 +77,12 @@ void design_schedule(const GridInfo& g, double t, double shift, mxp_precision pr
 // Scalar psi_1(z) = (e^z - 1)/z with the power series near 0.
 cd psi1_scalar(cd z);
 
+// Scalar psi_2(z) = (e^z - 1 - z)/z^2 with the power series near 0.
+cd psi2_scalar(cd z);
+
+// Chebyshev series of tau^2 psi_2(i tau z), tau = t / sc.S, on the segment of
+// schedule sc: coef holds (re, im) pairs, m the degree.
+void design_psi2_series(const mxp_schedule& sc, double t, mxp_precision prec, std::vector<double>* coef,
+                        int* m);
+
 }  // namespace mxp

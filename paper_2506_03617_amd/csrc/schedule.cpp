@@ -200,6 +200,19 @@ void fov_box(const GridInfo& g, double shift, double box[4]) {
     box[3] = im1 + w2 * shift * g.dmax;
 }
 
+cd psi2_scalar(cd z) {
+    if (std::abs(z) < 1.0) {
+        cd sum = 0.0, term = 0.5;
+        for (int k = 1; k < 40; ++k) {
+            sum += term;
+            term *= z / double(k + 2);
+            if (std::abs(term) < 1e-19 * std::abs(sum)) break;
+        }
+        return sum;
+    }
+    return (std::exp(z) - 1.0 - z) / (z * z);
+}
+
 cd psi1_scalar(cd z) {
     if (std::abs(z) < 0.5) {
         cd sum = 0.0, term = 1.0;
@@ -341,7 +354,9 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 //   q_k = (2 - delta_k0) i^k int_0^tau exp(i sigma c0) J_k(sigma hw) d sigma,
 // integrated by composite Gauss--Legendre.  Every q_k keeps its relative
 // accuracy, so the super-exponential decay of the series survives.
-std::vector<cd> psi1_coefficients(cd c0, double hw, double tau, int kmax) {
+// With `second` set, the integrand carries the weight (tau - sigma), giving
+//   tau^2 psi_2(i tau z) = int_0^tau (tau - sigma) exp(i sigma z) d sigma.
+std::vector<cd> psi1_coefficients(cd c0, double hw, double tau, int kmax, bool second = false) {
     std::vector<cd> q(kmax + 1, cd(0.0, 0.0));
     std::vector<double> gx, gw, J;
     gauss_legendre(32, gx, gw);
@@ -351,7 +366,7 @@ std::vector<cd> psi1_coefficients(cd c0, double hw, double tau, int kmax) {
         const double a = tau * pnl / panels, b = tau * (pnl + 1) / panels;
         for (size_t j = 0; j < gx.size(); ++j) {
             const double sig = 0.5 * (b - a) * gx[j] + 0.5 * (a + b);
-            const double wt = 0.5 * (b - a) * gw[j];
+            const double wt = 0.5 * (b - a) * gw[j] * (second ? tau - sig : 1.0);
             bessel_j(sig * hw, kmax, J);
             const cd e = std::exp(cd(0.0, sig) * c0) * wt;
             for (int k = 0; k <= kmax; ++k) q[k] += e * J[k];
@@ -469,6 +484,34 @@ void design_schedule(const GridInfo& g, double t, double shift, mxp_precision pr
     for (int i = 0; i < 4; ++i) out->box[i] = box[i];
     out->trunc_bound = crouzeix * bS * berr;
     out->amplification = bamp;
+}
+
+void design_psi2_series(const mxp_schedule& sc, double t, mxp_precision prec, std::vector<double>* coef,
+                        int* m) {
+    const bool fp64 = (prec == MXP_PREC_FP64);
+    const double tol = fp64 ? 1e-12 : 1e-6;
+    const double amp_max = fp64 ? 1e3 : 8.0;
+    const double crouzeix = 1.0 + std::sqrt(2.0);
+    const double tau = t / sc.S;
+    const cd c0(sc.centre_re, sc.centre_im);
+    const double hw = sc.half_width;
+    const Boundary bd = box_boundary(sc.box);
+    const int kmax = std::min(511, sc.m + 60);
+    const std::vector<cd> qc = psi1_coefficients(c0, hw, tau, kmax, true);
+    std::vector<cd> fval(bd.z.size());
+    for (size_t q = 0; q < bd.z.size(); ++q) fval[q] = tau * tau * psi2_scalar(cd(0.0, tau) * bd.z[q]);
+    double err = 0, amp = 0;
+    // the series enters the action once, scaled by S / t^2: an error below
+    // tol tau^2 / (1 + sqrt 2) adds at most tol / ((1 + sqrt 2) S) to psi_2
+    const int mq = min_degree(qc, c0, hw, bd, fval, tol * tau * tau / crouzeix, amp_max * tau * tau, kmax,
+                              &err, &amp);
+    if (mq < 0) fail(MXP_ERR_UNSUPPORTED, "no psi_2 series within the term limit");
+    coef->assign(2 * size_t(mq + 1), 0.0);
+    for (int k = 0; k <= mq; ++k) {
+        (*coef)[2 * k] = qc[k].real();
+        (*coef)[2 * k + 1] = qc[k].imag();
+    }
+    *m = mq;
 }
 
 }  // namespace mxp

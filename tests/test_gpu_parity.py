@@ -348,3 +348,56 @@ def test_fixed_point_inner_solver(ctx, name, prec):
     # batched solves keep to GMRES
     with pytest.raises(mxp.MxpError):
         mxp.mxp_solve_batch(ctx, [P], [o], [fd[None, :]], [ud[None, :].clone()], 1)
+
+
+@pytest.mark.parametrize("name,tfac", [(n, 1.0) for n in CASES] + [("2d-inh", f) for f in (0.3, 0.15, 0.05)]
+                         + [("3d-ragged", f) for f in (0.3, 0.15, 0.05)])
+@pytest.mark.parametrize("dt,tol", [("c128", 1e-11), ("c64", 1e-5)])
+def test_apply_psi2(ctx, name, tfac, dt, tol):
+    # t scaled down so that the substep count runs through S = 1, 2, 3 and >= 5
+    prob = make(name)
+    announce("apply_psi2", name, tfac, dt)
+    P = mxp.Problem(ctx, prob)
+    t, s = prob.default_t() * tfac, prob.default_shift()
+    x = wl.random_vector(prob.npts, 13)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    xd = to_dev(x, tdt)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_psi2(P, t, s, xd, yd)
+    ref = matfun.phi2_action(op.helmholtz(prob, s), t, to_host(xd))
+    assert rel(to_host(yd), ref) <= tol
+
+
+@pytest.mark.parametrize("name,prec,inner", [("2d-inh", p, i) for p in (0, 1) for i in ("gmres", "fixed_point")]
+                         + [("3d-inh", p, "gmres") for p in (0, 1)])
+def test_psi2_form_inner_solver(ctx, name, prec, inner):
+    # the second inverse formula (I - psi_1) w = psi_2 r, by GMRES or by the
+    # time-averaged fixed-point map: one apply, then whole solves
+    prob = make(name)
+    announce("psi2 form", name, prec, inner)
+    P = mxp.Problem(ctx, prob)
+    o = P.default_opts()
+    o.precision = prec
+    o.inner_solver = mxp.MXP_INNER_PSI2_GMRES if inner == "gmres" else mxp.MXP_INNER_PSI2_FIXED_POINT
+    r = wl.random_vector(prob.npts, 14)
+    rd = to_dev(r)
+    wd = torch.empty_like(rd)
+    its = mxp.mxp_apply_precond(P, o, rd, wd)
+    ref = krylov.precond_apply(op.helmholtz(prob, o.shift), o.t, r, o.fprtol, inner=inner, form="psi2")
+    assert abs(its - ref.inner_iterations) <= 1
+    if its == ref.inner_iterations:
+        assert rel(to_host(wd), ref.w) <= (1e-10 if prec == 0 else 1e-5)
+    centre = tuple(m // 2 for m in prob.n)
+    f = wl.delta_source(prob, centre).ravel()
+    fd = to_dev(f)
+    ud = torch.zeros_like(fd)
+    st = mxp.mxp_solve(P, o, fd, ud)
+    sref = krylov.matexpre_solve(prob, f, o.t, o.shift, o.fprtol, o.rtol, inner_solver=inner, form="psi2")
+    assert st["status"] == mxp.MXP_OK and st["true_relres"] <= o.rtol
+    assert abs(st["outer_its"] - sref.outer_iterations) <= 1
+    assert abs(st["inner_mean"] - sref.inner_mean) <= 1.0
+    o.rtol = 1e-12
+    ud.zero_()
+    st = mxp.mxp_solve(P, o, fd, ud)
+    assert st["true_relres"] <= 1e-12
+    assert rel(to_host(ud), krylov.direct_solve(prob, f)) <= (1e-10 if prec == 0 else 1e-5)
