@@ -173,7 +173,7 @@ typedef struct {
     double inner_mean;        /* mean inner iterations per preconditioner apply   */
     double inner_std;         /* population standard deviation of the same        */
     int64_t stencil_steps;    /* stencil sweeps spent in matrix-function actions  */
-    int64_t fn_actions;       /* exp and psi_1 actions                            */
+    int64_t fn_actions;       /* matrix-function actions (exp, psi_1, psi_2)      */
     double true_relres;       /* ||b - A u|| / ||b|| of the returned u, in double */
     double seconds;           /* wall time of the call                            */
     int32_t restarts;         /* outer restart cycles after the first             */
