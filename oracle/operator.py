@@ -7,6 +7,9 @@ Paper passages followed:
   * three-point FD per axis; five-point 2D / seven-point 3D  (Section 3.3, Section 4 intro)
   * zero Dirichlet outside the layer                          (Section 4 intro)
   * shifted operator A_s = A + i omega^2 s D, D = diag(1/c^2)  (Section 3.4)
+  * absorbing potential instead of the layer: omega^2 u + c^2 Lap u + i W u
+    = -c^2 f, i.e. omega^2/c^2 u + Lap u + i (W/c^2) u = -f, with zero
+    Dirichlet values and W >= 0 vanishing inside      (Section 2.1, eq. helmholtz-absorbing)
 
 Readings where the paper is silent (also listed in the design notes):
   * multi-dimensional layer: sum over axes of (1/s_d) d_d((1/s_d) d_d u), each
@@ -15,7 +18,11 @@ Readings where the paper is silent (also listed in the design notes):
   * the layer is part of the given grid: the outermost L nodes of each face,
     delta = L h, distance measured from the inner edge x_a = L h,
     x_b = (N-1-L) h; ghost nodes at indices -1 and N are zero;
-  * C_pml = 20, power 2.
+  * C_pml = 20, power 2;
+  * the potential's profile: W/c^2 = 2 omega^2 sum_d sigma_d(x_d) with sigma_d
+    the layer profile above, so that a normally incident plane wave decays at
+    the stretch's rate to first order (k = sqrt(omega^2 + i W/c^2) ~ omega +
+    i omega sigma against k = omega (1 + i sigma)).
 
 Parity: pinned by the tests (plane-wave consistency of the interior stencil,
 second-order consistency of the 1D stretched operator against its analytic
@@ -83,6 +90,26 @@ def laplacian_pml(n, L, h, omega, C: float = 20.0, power: int = 2) -> sp.csr_mat
     return lap.tocsr()
 
 
+def cap_potential(prob) -> np.ndarray:
+    """W/c^2 per node, flattened (x fastest): 2 omega^2 times the sum over axes
+    of the layer profile at the node's coordinate."""
+    n = tuple(prob.n)
+    total = np.zeros(tuple(reversed(n)))
+    for ax, nd in enumerate(n):
+        sig = pml_sigma(np.arange(nd) * prob.h, nd, prob.layer, prob.h, prob.omega, prob.pml_C, prob.pml_power)
+        sh = [1] * len(n)
+        sh[len(n) - 1 - ax] = nd
+        total = total + sig.reshape(sh)
+    return (2.0 * prob.omega ** 2 * total).ravel()
+
+
+def _absorber(prob) -> str:
+    a = getattr(prob, "absorber", "pml")
+    if a not in ("pml", "cap"):
+        raise ValueError("absorber must be 'pml' or 'cap'")
+    return a
+
+
 def inverse_c2(prob) -> np.ndarray:
     """Diagonal of D = 1/c^2, flattened."""
     c = prob.c_array().ravel().astype(float)
@@ -90,10 +117,16 @@ def inverse_c2(prob) -> np.ndarray:
 
 
 def helmholtz(prob, shift: float = 0.0) -> sp.csr_matrix:
-    """A_s = omega^2 (1 + i s) D + Lap_PML; shift = 0 gives A itself."""
-    lap = laplacian_pml(prob.n, prob.layer, prob.h, prob.omega, prob.pml_C, prob.pml_power)
+    """A_s = omega^2 (1 + i s) D + Lap_PML; shift = 0 gives A itself.  With the
+    absorbing potential: A_s = omega^2 (1 + i s) D + Lap + i W/c^2."""
     D = inverse_c2(prob)
-    return (lap + sp.diags(prob.omega ** 2 * (1 + 1j * shift) * D)).tocsr()
+    diag = prob.omega ** 2 * (1 + 1j * shift) * D
+    if _absorber(prob) == "cap":
+        lap = laplacian_pml(prob.n, 0, prob.h, prob.omega)
+        diag = diag + 1j * cap_potential(prob)
+    else:
+        lap = laplacian_pml(prob.n, prob.layer, prob.h, prob.omega, prob.pml_C, prob.pml_power)
+    return (lap + sp.diags(diag)).tocsr()
 
 
 def rhs(f: np.ndarray) -> np.ndarray:
@@ -108,6 +141,7 @@ def apply_rows(prob, shift: float, x: np.ndarray, points: np.ndarray) -> np.ndar
     n = prob.n
     d = len(n)
     h, om, L = prob.h, prob.omega, prob.layer
+    cap = _absorber(prob) == "cap"
     D = inverse_c2(prob)
     out = np.empty(len(points), dtype=np.complex128)
     strides = [int(np.prod(n[:ax])) for ax in range(d)]
@@ -117,9 +151,14 @@ def apply_rows(prob, shift: float, x: np.ndarray, points: np.ndarray) -> np.ndar
         for ax in range(d):
             i = idx[ax]
             xi = i * h
-            s0 = 1 + 1j * pml_sigma(np.array([xi]), n[ax], L, h, om, prob.pml_C, prob.pml_power)[0]
-            sl = 1 + 1j * pml_sigma(np.array([xi - h / 2]), n[ax], L, h, om, prob.pml_C, prob.pml_power)[0]
-            sr = 1 + 1j * pml_sigma(np.array([xi + h / 2]), n[ax], L, h, om, prob.pml_C, prob.pml_power)[0]
+            sig = pml_sigma(np.array([xi - h / 2, xi, xi + h / 2]), n[ax], L, h, om, prob.pml_C, prob.pml_power)
+            if cap:
+                # the potential's share of this axis; no stretch
+                acc += 1j * 2.0 * om * om * sig[1] * x[p]
+                sig = np.zeros(3)
+            s0 = 1 + 1j * sig[1]
+            sl = 1 + 1j * sig[0]
+            sr = 1 + 1j * sig[2]
             wl = 1 / (s0 * sl * h * h)
             wr = 1 / (s0 * sr * h * h)
             um = x[p - strides[ax]] if i > 0 else 0.0

@@ -1,4 +1,5 @@
 """Pins for the oracle's operator assembly (oracle/operator.py)."""
+import dataclasses
 import math
 
 import numpy as np
@@ -145,5 +146,86 @@ def test_greens_function_2d_outgoing():
     rel = np.linalg.norm(sol[ann] - green) / np.linalg.norm(green)
     assert rel < 0.05, rel
     # incoming (H0^(2)) must be far off: guards the sign of the layer
+    wrong = 0.25j * np.conj(hankel1(0, prob.omega * r[ann]))
+    assert np.linalg.norm(sol[ann] - wrong) / np.linalg.norm(wrong) > 0.5
+
+
+def _cap(prob):
+    return dataclasses.replace(prob, absorber="cap")
+
+
+def test_cap_eigenvalues_follow_the_potential():
+    # Section 2.1 proposition, discrete form: A = omega^2 D + Lap + i W/c^2 with Lap real
+    # symmetric, so for A phi = lambda phi, Im(lambda) = sum (W/c^2)|phi|^2 / sum |phi|^2 >= 0
+    prob = _cap(wl.small_problem((12, 10), layer=3, ppw=10, inhomogeneous=True, seed=5))
+    A = op.helmholtz(prob, 0.0).toarray()
+    lam, V = np.linalg.eig(A)
+    W = op.cap_potential(prob)
+    assert W.min() == 0.0 and W.max() > 0.0
+    quot = (W[:, None] * np.abs(V) ** 2).sum(axis=0) / (np.abs(V) ** 2).sum(axis=0)
+    assert np.abs(lam.imag - quot).max() <= 1e-9 * W.max()
+    assert lam.imag.min() > 0.0
+    # the shift adds omega^2 s D to the same quotient
+    As = op.helmholtz(prob, 0.2).toarray()
+    lam_s, V_s = np.linalg.eig(As)
+    Dd = op.inverse_c2(prob)
+    quot_s = ((W + prob.omega**2 * 0.2 * Dd)[:, None] * np.abs(V_s) ** 2).sum(axis=0) / (np.abs(V_s) ** 2).sum(axis=0)
+    assert np.abs(lam_s.imag - quot_s).max() <= 1e-9 * W.max()
+
+
+def test_cap_is_the_plain_laplacian_plus_potential():
+    # no stretch: off-diagonal entries are 1/h^2 everywhere, the layer only in the diagonal
+    prob = _cap(wl.small_problem((9, 8, 7), layer=2, ppw=10, inhomogeneous=True, seed=6))
+    A = op.helmholtz(prob, 0.0).tocoo()
+    off = A.row != A.col
+    assert np.allclose(A.data[off], 1.0 / prob.h**2, rtol=0, atol=1e-9 / prob.h**2)
+    plain = op.helmholtz(dataclasses.replace(prob, layer=0), 0.0).toarray()
+    diff = np.diag(A.toarray() - plain)
+    assert np.allclose(diff, 1j * op.cap_potential(prob), rtol=1e-14, atol=0)
+
+
+def test_cap_decays_like_the_pml_inside_the_layer():
+    # the potential's scale: a wave crossing the layer loses amplitude at the stretch's
+    # rate, exp(-omega int sigma) to first order; with half the potential it would keep
+    # e^{+1.1} more amplitude at depth 30 cells here
+    import scipy.sparse.linalg as spla
+    n, L = 161, 40
+    sols = {}
+    for absorber in ("pml", "cap"):
+        prob = dataclasses.replace(wl.small_problem((n, n), layer=L, ppw=30), absorber=absorber)
+        f = wl.delta_source(prob, (n // 2, n // 2))
+        sols[absorber] = spla.splu(op.helmholtz(prob, 0.0).tocsc()).solve(op.rhs(f)).reshape(prob.shape)
+    row = n // 2
+    for depth in (0, 10, 20, 30):
+        i = n - 1 - L + depth
+        env = {k: np.sqrt(np.mean(np.abs(v[row, i - 7:i + 8]) ** 2)) for k, v in sols.items()}
+        assert 0.9 < env["cap"] / env["pml"] < 1.1, (depth, env)
+    # the PML itself decays by about exp(-omega int sigma) over those 30 cells
+    prob = wl.small_problem((n, n), layer=L, ppw=30)
+    x = np.arange(n) * prob.h
+    sig = op.pml_sigma(x, n, L, prob.h, prob.omega)
+    i0, i1 = n - 1 - L, n - 1 - L + 30
+    pred = prob.omega * sig[i0:i1].sum() * prob.h
+    env0 = np.sqrt(np.mean(np.abs(sols["pml"][row, i0 - 7:i0 + 8]) ** 2))
+    env1 = np.sqrt(np.mean(np.abs(sols["pml"][row, i1 - 7:i1 + 8]) ** 2))
+    # the 2D field also spreads (amplitude ~ r^-1/2) over that distance
+    spread = 0.5 * np.log((i1 - n // 2) / (i0 - n // 2))
+    assert abs(np.log(env0 / env1) - spread - pred) <= 0.25 * pred
+
+
+def test_greens_function_2d_outgoing_with_cap():
+    # as P6, with the absorbing potential (a wider layer: the potential reflects more)
+    from scipy.special import hankel1
+    import scipy.sparse.linalg as spla
+    n, L = 161, 40
+    prob = dataclasses.replace(wl.small_problem((n, n), layer=L, ppw=30), absorber="cap")
+    f = wl.delta_source(prob, (n // 2, n // 2))
+    sol = spla.splu(op.helmholtz(prob, 0.0).tocsc()).solve(op.rhs(f)).reshape(prob.shape)
+    h = prob.h
+    y, x = np.meshgrid(np.arange(n) * h, np.arange(n) * h, indexing="ij")
+    r = np.hypot(x - (n // 2) * h, y - (n // 2) * h)
+    ann = (r > 10 * h) & (r < 0.22)
+    green = 0.25j * hankel1(0, prob.omega * r[ann])
+    assert np.linalg.norm(sol[ann] - green) / np.linalg.norm(green) < 0.05
     wrong = 0.25j * np.conj(hankel1(0, prob.omega * r[ann]))
     assert np.linalg.norm(sol[ann] - wrong) / np.linalg.norm(wrong) > 0.5

@@ -40,6 +40,7 @@ class Problem:
     c_const: float = 1.0          # used when c is None
     pml_C: float = 20.0           # absorbing strength constant
     pml_power: int = 2            # quadratic profile
+    absorber: str = "pml"         # "pml" (coordinate stretch) or "cap" (absorbing potential)
 
     @property
     def dim(self) -> int:
