@@ -102,7 +102,21 @@ const char* mxp_version(void);
  * the number of absorbing-layer cells on the low/high face of axis d; those
  * are the outermost nodes of the given grid, delta = layer*h, and the stretch
  * distance is measured from the inner edge (layer*h, (n-1-layer)*h).  0 gives
- * a bare Dirichlet face. */
+ * a bare Dirichlet face.
+ *
+ * absorber selects what the layer does.  MXP_ABSORB_PML (0, the default of a
+ * zeroed struct) stretches the coordinates, s_d = 1 + i sigma_d(x_d) with
+ * sigma_d = pml_C/(delta omega) (dist/delta)^pml_power.  MXP_ABSORB_CAP (1) is
+ * the complex absorbing potential of Section 2.1 (eq. helmholtz-absorbing,
+ * divided by c^2): the plain Laplacian plus i W/c^2 with
+ * W/c^2 = 2 omega^2 sum_d sigma_d(x_d), the same profile, scaled so that a
+ * plane wave at normal incidence decays at the PML's rate to first order.
+ * Complex-float stepping (MXP_PREC_MIXED, MXP_C64 actions) needs the potential
+ * to stay below about the Laplacian's range (pi pml_C / (ppw layer) <= 1.25,
+ * ppw the points per wavelength); beyond it schedules fail with UNSUPPORTED. */
+#define MXP_ABSORB_PML 0
+#define MXP_ABSORB_CAP 1
+
 typedef struct {
     int32_t dim;            /* 2 or 3                                           */
     int64_t n[3];           /* nodes per axis, x first; n[2] = 1 in 2D; each >= 3 */
@@ -114,6 +128,7 @@ typedef struct {
     const void* c;          /* wave speed per node (host or device), or NULL    */
     mxp_dtype c_dtype;      /* MXP_F32 or MXP_F64 when c != NULL                */
     double c_const;         /* wave speed everywhere when c == NULL, > 0        */
+    int32_t absorber;       /* MXP_ABSORB_PML (default) or MXP_ABSORB_CAP      */
 } mxp_grid_desc;
 
 /* Copies the description, validates it (c finite and > 0 everywhere), builds

@@ -30,6 +30,7 @@ MXP_ERR_UNSUPPORTED = -6
 
 MXP_C64, MXP_C128, MXP_F32, MXP_F64 = 0, 1, 2, 3
 MXP_PREC_FP64, MXP_PREC_MIXED = 0, 1
+MXP_ABSORB_PML, MXP_ABSORB_CAP = 0, 1
 MXP_INNER_GMRES, MXP_INNER_FIXED_POINT, MXP_INNER_PSI2_GMRES, MXP_INNER_PSI2_FIXED_POINT = 0, 1, 2, 3
 
 
@@ -51,6 +52,7 @@ class mxp_grid_desc(ctypes.Structure):
         ("c", ctypes.c_void_p),
         ("c_dtype", ctypes.c_int),
         ("c_const", ctypes.c_double),
+        ("absorber", ctypes.c_int32),
     ]
 
 
@@ -221,6 +223,7 @@ def grid_desc(prob, c_host: Optional[np.ndarray] = None) -> mxp_grid_desc:
         d.layer[a][1] = L
     d.pml_C = prob.pml_C
     d.pml_power = prob.pml_power
+    d.absorber = {"pml": MXP_ABSORB_PML, "cap": MXP_ABSORB_CAP}[getattr(prob, "absorber", "pml")]
     c = c_host if c_host is not None else prob.c
     if c is None:
         d.c = None

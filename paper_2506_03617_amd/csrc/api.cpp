@@ -244,16 +244,17 @@ static void build_diag(mxp_problem* P, double shift, cd centre, DiagTables& dt) 
         off += g.n[d];
     }
     // Interior box: a node needs alpha = beta = 1/h^2 on its axis, i.e. the
-    // stretch is 1 at the node and both half-nodes.  Nodes 0 and n-1 are
+    // stretch is 1 at the node and both half-nodes (everywhere with the
+    // absorbing potential, which sits in the diagonal).  Nodes 0 and n-1 are
     // excluded so that every neighbour read stays inside the grid there.
     auto span = [&](int d, int64_t* lo, int64_t* hi) {
         const AxisLayer ax = g.axis(d);
         int64_t a0 = 1, a1 = g.n[d] - 1;
-        while (a0 < a1 && (ax.sigma(a0 * g.h) != 0.0 || ax.sigma((a0 - 0.5) * g.h) != 0.0 ||
-                           ax.sigma((a0 + 0.5) * g.h) != 0.0))
+        while (a0 < a1 && (ax.stretch(a0 * g.h) != 0.0 || ax.stretch((a0 - 0.5) * g.h) != 0.0 ||
+                           ax.stretch((a0 + 0.5) * g.h) != 0.0))
             ++a0;
-        while (a1 > a0 && (ax.sigma((a1 - 1) * g.h) != 0.0 || ax.sigma((a1 - 0.5) * g.h) != 0.0 ||
-                           ax.sigma((a1 - 1.5) * g.h) != 0.0))
+        while (a1 > a0 && (ax.stretch((a1 - 1) * g.h) != 0.0 || ax.stretch((a1 - 0.5) * g.h) != 0.0 ||
+                           ax.stretch((a1 - 1.5) * g.h) != 0.0))
             --a1;
         *lo = a0;
         *hi = a1;

@@ -31,13 +31,18 @@ struct AxisLayer {
     int32_t lo, hi;
     double h, omega, C;
     int32_t power;
+    int32_t absorber;  // MXP_ABSORB_PML or MXP_ABSORB_CAP
+    // the layer profile sigma(x) = C/(delta omega) (dist/delta)^power
     double sigma(double x) const;
+    // imaginary part of the coordinate stretch (zero for the potential)
+    double stretch(double x) const { return absorber == MXP_ABSORB_PML ? sigma(x) : 0.0; }
 };
 
 // Per-axis three-point coefficients of (1/s) d/dx((1/s) du/dx):
 //   (L u)_i = alpha_i u_{i-1} + beta_i u_{i+1} + gamma_i u_i,
 //   alpha_i = 1/(s_i s_{i-1/2} h^2), beta_i = 1/(s_i s_{i+1/2} h^2),
-//   gamma_i = -(alpha_i + beta_i).
+//   gamma_i = -(alpha_i + beta_i) + i 2 omega^2 sigma(x_i) (the last term
+//   only with the absorbing potential, where every stretch is 1).
 struct AxisTables {
     std::vector<cd> alpha, beta, gamma;
 };
@@ -49,13 +54,14 @@ struct GridInfo {
     int64_t n[3];
     double h, omega, pml_C;
     int32_t pml_power;
+    int32_t absorber;
     int32_t layer[3][2];
     bool homogeneous;
     double c_const;
     double dmin, dmax;  // range of D = 1/c^2
     int64_t npts() const { return n[0] * n[1] * n[2]; }
     AxisLayer axis(int d) const {
-        return AxisLayer{n[d], layer[d][0], layer[d][1], h, omega, pml_C, pml_power};
+        return AxisLayer{n[d], layer[d][0], layer[d][1], h, omega, pml_C, pml_power, absorber};
     }
 };
 

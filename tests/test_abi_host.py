@@ -47,7 +47,8 @@ def _desc(**kw):
 
 
 @pytest.mark.parametrize("field,value", [("dim", 4), ("h", 0.0), ("omega", -1.0), ("h", float("nan")),
-                                         ("pml_power", 0), ("c_const", 0.0), ("pml_C", -1.0)])
+                                         ("pml_power", 0), ("c_const", 0.0), ("pml_C", -1.0),
+                                         ("absorber", 2), ("absorber", -1)])
 def test_invalid_descriptions_rejected(field, value):
     d = _desc(**{field: value})
     with pytest.raises(mxp.MxpError) as e:
@@ -189,3 +190,33 @@ def test_designed_schedule_reproduces_dense_exponential(prec, tol):
     psi = acc / t
     ref = matfun.phi1_dense(op.helmholtz(prob, s), t)
     assert np.linalg.norm(psi - ref, 2) <= tol * max(1.0, np.linalg.norm(ref, 2))
+
+
+def test_cap_schedule_box_covers_the_potential():
+    # the absorbing potential moves the field-of-values box up by its range,
+    # 2 omega^2 sum_d sigma_d, and leaves the real range of the plain Laplacian
+    import dataclasses
+    from oracle import operator as op
+    prob = dataclasses.replace(wl.small_problem((20, 18), layer=4), absorber="cap")
+    W = op.cap_potential(prob)
+    sc = mxp.mxp_design_schedule(mxp.grid_desc(prob), prob.default_t(), 0.0, mxp.MXP_PREC_FP64)
+    box = list(sc.box)
+    assert box[2] <= 1e-9 * W.max() and box[3] >= W.max() * (1 - 1e-12)
+    assert box[3] <= W.max() * (1 + 1e-9) + 1e-9
+    lam = np.linalg.eigvals(op.helmholtz(prob, 0.0).toarray())
+    assert lam.real.min() >= box[0] - 1e-9 * abs(box[0]) and lam.real.max() <= box[1] + 1e-9 * abs(box[0])
+    assert lam.imag.min() >= box[2] - 1e-9 * W.max() and lam.imag.max() <= box[3] + 1e-9 * W.max()
+
+
+def test_complex_float_schedule_refused_for_a_tall_box():
+    # 3-cell absorbing-potential layer at ppw 10: box height about twice its width
+    import dataclasses
+    prob = dataclasses.replace(wl.small_problem((40, 36), layer=3), absorber="cap")
+    d = mxp.grid_desc(prob)
+    mxp.mxp_design_schedule(d, prob.default_t(), 0.0, mxp.MXP_PREC_FP64)
+    with pytest.raises(mxp.MxpError) as e:
+        mxp.mxp_design_schedule(d, prob.default_t(), 0.0, mxp.MXP_PREC_MIXED)
+    assert e.value.status == mxp.MXP_ERR_UNSUPPORTED
+    # a wider layer (8 cells) keeps it
+    prob = dataclasses.replace(prob, layer=8)
+    mxp.mxp_design_schedule(mxp.grid_desc(prob), prob.default_t(), 0.0, mxp.MXP_PREC_MIXED)

@@ -401,3 +401,88 @@ def test_psi2_form_inner_solver(ctx, name, prec, inner):
     st = mxp.mxp_solve(P, o, fd, ud)
     assert st["true_relres"] <= 1e-12
     assert rel(to_host(ud), krylov.direct_solve(prob, f)) <= (1e-10 if prec == 0 else 1e-5)
+
+
+CAP_CASES = {
+    "2d-inh": dict(n=(67, 45), layer=8),
+    # ragged x and y tiles and z chunks, as "3d-ragged", with a layer wide enough
+    # for complex-float stepping
+    "3d-ragged": dict(n=(70, 17, 37), layer=6),
+}
+
+
+@pytest.mark.parametrize("name", list(CAP_CASES))
+def test_cap_absorber(ctx, name):
+    # the complex absorbing potential in place of the stretch: the operator in both
+    # precisions, the exp action, one preconditioner apply and whole solves
+    import dataclasses
+    c = CAP_CASES[name]
+    prob = dataclasses.replace(wl.small_problem(c["n"], layer=c["layer"], ppw=10.0, inhomogeneous=True, seed=7,
+                                                name=name), absorber="cap")
+    announce("cap", name)
+    P = mxp.Problem(ctx, prob)
+    s = prob.default_shift()
+    As = op.helmholtz(prob, s)
+    x = wl.random_vector(prob.npts, 21)
+    for tdt, eps in ((torch.complex128, 2.0**-53), (torch.complex64, 2.0**-24)):
+        xd = to_dev(x, tdt)
+        yd = torch.empty_like(xd)
+        mxp.mxp_apply_A(P, s, xd, yd)
+        xr = to_host(xd)
+        bound = np.linalg.norm(abs(As) @ np.abs(xr))
+        assert np.linalg.norm(to_host(yd) - As @ xr) <= 16 * eps * bound
+    t = prob.default_t()
+    for tdt, tol in ((torch.complex128, 1e-11), (torch.complex64, 1e-5)):
+        xd = to_dev(x, tdt)
+        yd = torch.empty_like(xd)
+        mxp.mxp_apply_exp(P, t, s, xd, yd)
+        assert rel(to_host(yd), matfun.exp_action(As, t, to_host(xd))) <= tol
+    o = P.default_opts()
+    rd = to_dev(x)
+    wd = torch.empty_like(rd)
+    its = mxp.mxp_apply_precond(P, o, rd, wd)
+    ref = krylov.precond_apply(As, o.t, x, o.fprtol)
+    assert abs(its - ref.inner_iterations) <= 1
+    if its == ref.inner_iterations:
+        assert rel(to_host(wd), ref.w) <= 1e-10
+    centre = tuple(m // 2 for m in prob.n)
+    f = wl.delta_source(prob, centre).ravel()
+    fd = to_dev(f)
+    sref = krylov.matexpre_solve(prob, f, o.t, o.shift, o.fprtol, o.rtol)
+    for prec in (0, 1):
+        o = P.default_opts()
+        o.precision = prec
+        ud = torch.zeros_like(fd)
+        st = mxp.mxp_solve(P, o, fd, ud)
+        assert st["status"] == mxp.MXP_OK and st["true_relres"] <= o.rtol
+        assert abs(st["outer_its"] - sref.outer_iterations) <= 1
+        assert abs(st["inner_mean"] - sref.inner_mean) <= 1.0
+        o.rtol = 1e-12
+        ud.zero_()
+        st = mxp.mxp_solve(P, o, fd, ud)
+        assert st["true_relres"] <= 1e-12
+        assert rel(to_host(ud), krylov.direct_solve(prob, f)) <= (1e-10 if prec == 0 else 1e-5)
+
+
+def test_cap_thin_layer_refuses_complex_float_stepping(ctx):
+    # a 3-cell layer makes the potential taller than the Laplacian is wide: complex-float
+    # schedules are refused, while complex-double actions stay exact
+    import dataclasses
+    prob = dataclasses.replace(make("3d-ragged"), absorber="cap")
+    announce("cap thin layer")
+    P = mxp.Problem(ctx, prob)
+    t, s = prob.default_t(), prob.default_shift()
+    x = wl.random_vector(prob.npts, 22)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    mxp.mxp_apply_exp(P, t, s, xd, yd)
+    assert rel(to_host(yd), matfun.exp_action(op.helmholtz(prob, s), t, x)) <= 1e-11
+    with pytest.raises(mxp.MxpError) as e:
+        mxp.mxp_apply_exp(P, t, s, to_dev(x, torch.complex64), torch.empty(prob.npts, dtype=torch.complex64,
+                                                                            device="cuda:0"))
+    assert e.value.status == mxp.MXP_ERR_UNSUPPORTED
+    o = P.default_opts()
+    o.precision = mxp.MXP_PREC_MIXED
+    with pytest.raises(mxp.MxpError) as e:
+        mxp.mxp_solve(P, o, xd, torch.zeros_like(xd))
+    assert e.value.status == mxp.MXP_ERR_UNSUPPORTED
