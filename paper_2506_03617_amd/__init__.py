@@ -125,7 +125,7 @@ ABI_SYMBOLS = (
     "mxp_context_create", "mxp_context_destroy", "mxp_last_error", "mxp_version",
     "mxp_problem_create", "mxp_problem_destroy", "mxp_problem_size",
     "mxp_solve_opts_default", "mxp_design_schedule",
-    "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_psi2", "mxp_apply_precond", "mxp_solve",
+    "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_psi2", "mxp_apply_fn_krylov", "mxp_apply_precond", "mxp_solve",
     "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
     "mxp_cnn_num_params", "mxp_cnn_create", "mxp_cnn_destroy", "mxp_cnn_get_params", "mxp_cnn_set_params",
     "mxp_cnn_get_grads", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
@@ -158,6 +158,8 @@ def _load():
         "mxp_apply_exp": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_psi1": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_psi2": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
+        "mxp_apply_fn_krylov": (st, [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int32, P, P, ctypes.POINTER(ctypes.c_int32)]),
         "mxp_apply_precond": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(ctypes.c_int32)]),
         "mxp_solve": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(mxp_solve_stats)]),
         "mxp_set_tiles": (st, [P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -352,6 +354,17 @@ def mxp_apply_psi1(prob: Problem, t: float, shift: float, x, y) -> None:
 
 def mxp_apply_psi2(prob: Problem, t: float, shift: float, x, y) -> None:
     _check(lib.mxp_apply_psi2(prob.handle, t, shift, _dtype_of(x), _ptr(x), _ptr(y)))
+
+
+def mxp_apply_fn_krylov(prob: Problem, psi: bool, t: float, shift: float, tol: float, max_dim: int, x, y):
+    """Arnoldi action (complex double).  Returns (status, basis size); status is
+    MXP_OK or MXP_NOT_CONVERGED, other statuses raise."""
+    import torch
+    if x.dtype != torch.complex128 or y.dtype != torch.complex128:
+        raise TypeError("mxp_apply_fn_krylov takes complex128 vectors")
+    dim = ctypes.c_int32(0)
+    st = lib.mxp_apply_fn_krylov(prob.handle, int(psi), t, shift, tol, max_dim, _ptr(x), _ptr(y), ctypes.byref(dim))
+    return _check(st, allow_not_converged=True), dim.value
 
 
 def mxp_apply_precond(prob: Problem, opts: mxp_solve_opts, r, w) -> int:

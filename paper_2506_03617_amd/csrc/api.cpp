@@ -102,6 +102,7 @@ struct Workspace {
     // output, (f32) [7..8] casts, [9] the psi_2 action's first-substep term
     DevMem act64[10], act32[10];
     DevMem innerV, innerRh, innerTmp, innerRr;
+    DevMem krylovV;
     DevMem outerV, outerZ, outerR;
     DevMem partial, small;
     std::vector<cpx<double>> host_small;
@@ -1423,6 +1424,76 @@ static void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<dou
     launch_stencil(a, s);
 }
 
+// f(i t A_s) x with f = exp or psi_1 by the Arnoldi method, the route the
+// paper takes for its matrix functions (a Krylov method, Section 4
+// introduction), here unrestarted with a capped basis.  V spans the Krylov
+// space of A_s from x (classical Gram-Schmidt with a second pass, complex
+// double), H is the Hessenberg matrix of A_s on it, and
+// y = ||x|| V f(i t H) e_1 with the small exponential computed densely on the
+// host (psi_1 from the augmented matrix [[i t H, e_1], [0, 0]]).  Every 8
+// vectors the estimate h_{m+1,m} |e_m^T f(i t H_m) e_1| (relative to ||x||)
+// is compared with tol.  Returns the basis size; *ok is false if max_dim
+// vectors did not meet tol (y then holds the last approximation).
+static int krylov_action(Run& run, bool psi, double t, double shift, double tol, int max_dim,
+                         const cpx<double>* x, cpx<double>* y, bool* ok) {
+    mxp_problem* P = run.P;
+    Workspace& WS = *run.W;
+    const int64_t n = npts(P);
+    hipStream_t s = run.s;
+    *ok = false;
+    const double beta = norm2(run, x);
+    if (beta == 0.0) {
+        launch_zero<double>(y, n, s);
+        *ok = true;
+        return 0;
+    }
+    WS.krylovV.ensure(size_t(max_dim + 1) * n * sizeof(cpx<double>));
+    cpx<double>* V = WS.krylovV.as<cpx<double>>();
+    launch_scale({1.0 / beta, 0.0}, x, V, n, s);
+    const size_t ldh = size_t(max_dim) + 1;
+    std::vector<cd> H(ldh * max_dim, cd(0.0, 0.0));  // column j holds A_s v_j
+    std::vector<cd> h, f;
+    auto small_fn = [&](int k) {
+        const int q = psi ? k + 1 : k;
+        std::vector<cd> M(size_t(q) * q, cd(0.0, 0.0));
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i <= std::min(j + 1, k - 1); ++i) M[size_t(i) * q + j] = cd(0.0, t) * H[i + ldh * j];
+        if (psi) M[k] = 1.0;  // row 0, column k: e_1
+        expm_dense(q, M);
+        f.resize(k);
+        for (int i = 0; i < k; ++i) f[i] = M[size_t(i) * q + (psi ? k : 0)] * beta;
+    };
+    int m = 0;
+    for (int j = 0; j < max_dim; ++j) {
+        cpx<double>* vj = V + size_t(j) * n;
+        cpx<double>* vn = V + size_t(j + 1) * n;
+        apply_A64(P, s, shift, vj, vn, 1.0, nullptr, 0.0);
+        const double hn = cgs2(run, V, n, j + 1, vn, h);
+        double hmax = hn;
+        for (int i = 0; i <= j; ++i) {
+            H[i + ldh * j] = h[i];
+            hmax = std::max(hmax, std::abs(h[i]));
+        }
+        H[j + 1 + ldh * j] = hn;
+        m = j + 1;
+        const bool breakdown = hn <= 1e-13 * hmax;  // the space is invariant: f(i t H) is exact
+        if (!breakdown) launch_scale({1.0 / hn, 0.0}, vn, vn, n, s);
+        if (breakdown || m % 8 == 0 || m == max_dim) {
+            small_fn(m);
+            const double est = breakdown ? 0.0 : hn * std::abs(f[m - 1]) / beta;
+            if (!std::isfinite(est)) fail(MXP_ERR_NONFINITE, "non-finite Krylov estimate");
+            if (est <= tol) {
+                *ok = true;
+                break;
+            }
+        }
+    }
+    upload_coeffs(run, f);
+    launch_zero<double>(y, n, s);  // mcombine accumulates: y += V f
+    launch_mcombine(y, V, n, m, small_buffers(run).y, n, s);
+    return m;
+}
+
 static void check_opts(const mxp_solve_opts* o) {
     if (!o) fail(MXP_ERR_INVALID_ARG, "options are NULL");
     if (!(o->t > 0) || !std::isfinite(o->t)) fail(MXP_ERR_INVALID_ARG, "t must be positive");
@@ -1838,6 +1909,27 @@ mxp_status mxp_apply_psi1(mxp_problem* prob, double t, double shift, mxp_dtype d
 mxp_status mxp_apply_psi2(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
                           void* y) {
     return apply_fn(prob, t, shift, dtype, x, y, ACT_PSI2);
+}
+
+mxp_status mxp_apply_fn_krylov(mxp_problem* prob, int32_t psi, double t, double shift, double tol,
+                               int32_t max_dim, const void* x, void* y, int32_t* dim) {
+    return guard([&]() {
+        check_problem(prob);
+        if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
+        if (psi != 0 && psi != 1) fail(MXP_ERR_INVALID_ARG, "psi must be 0 (exp) or 1 (psi_1)");
+        if (!(t > 0) || !std::isfinite(t)) fail(MXP_ERR_INVALID_ARG, "t must be positive and finite");
+        if (!(shift >= 0) || !std::isfinite(shift)) fail(MXP_ERR_INVALID_ARG, "shift must be >= 0");
+        if (!(tol > 0) || !(tol < 1)) fail(MXP_ERR_INVALID_ARG, "tol must be in (0, 1)");
+        if (max_dim < 1 || max_dim > 250) fail(MXP_ERR_INVALID_ARG, "max_dim must be in 1..250");
+        Run run{prob, &prob->ws, prob->ctx->stream, nullptr, nullptr};
+        bool ok = false;
+        const int m = krylov_action(run, psi != 0, t, shift, tol, max_dim, static_cast<const cpx<double>*>(x),
+                                    static_cast<cpx<double>*>(y), &ok);
+        HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
+        if (dim) *dim = m;
+        if (!ok) g_last_error = "Krylov basis reached max_dim before the estimate met tol";
+        return ok ? MXP_OK : MXP_NOT_CONVERGED;
+    });
 }
 
 mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r, void* w,

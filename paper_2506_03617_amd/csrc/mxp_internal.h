@@ -86,6 +86,10 @@ cd psi1_scalar(cd z);
 // Scalar psi_2(z) = (e^z - 1 - z)/z^2 with the power series near 0.
 cd psi2_scalar(cd z);
 
+// exp(A) in place for a small dense n x n row-major matrix (scaling and
+// squaring with the [13/13] Pade approximant).
+void expm_dense(int n, std::vector<cd>& A);
+
 // Chebyshev series of tau^2 psi_2(i tau z), tau = t / sc.S, on the segment of
 // schedule sc: coef holds (re, im) pairs, m the degree.
 void design_psi2_series(const mxp_schedule& sc, double t, mxp_precision prec, std::vector<double>* coef,

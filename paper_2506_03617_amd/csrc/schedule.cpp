@@ -501,6 +501,100 @@ void design_schedule(const GridInfo& g, double t, double shift, mxp_precision pr
     out->amplification = bamp;
 }
 
+namespace {
+
+// C = A B, n x n row-major complex.
+void matmul(int n, const std::vector<cd>& A, const std::vector<cd>& B, std::vector<cd>& C) {
+    C.assign(size_t(n) * n, cd(0.0, 0.0));
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            const cd a = A[size_t(i) * n + k];
+            if (a == cd(0.0, 0.0)) continue;
+            const cd* b = &B[size_t(k) * n];
+            cd* c = &C[size_t(i) * n];
+            for (int j = 0; j < n; ++j) c[j] += a * b[j];
+        }
+}
+
+// X = D^{-1} N by Gaussian elimination with partial pivoting (N overwritten).
+void solve_in_place(int n, std::vector<cd> D, std::vector<cd>& N) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::abs(D[size_t(r) * n + c]) > std::abs(D[size_t(piv) * n + c])) piv = r;
+        if (D[size_t(piv) * n + c] == cd(0.0, 0.0)) fail(MXP_ERR_BREAKDOWN, "singular Pade denominator");
+        if (piv != c)
+            for (int j = 0; j < n; ++j) {
+                std::swap(D[size_t(piv) * n + j], D[size_t(c) * n + j]);
+                std::swap(N[size_t(piv) * n + j], N[size_t(c) * n + j]);
+            }
+        const cd inv = 1.0 / D[size_t(c) * n + c];
+        for (int r = c + 1; r < n; ++r) {
+            const cd f = D[size_t(r) * n + c] * inv;
+            if (f == cd(0.0, 0.0)) continue;
+            for (int j = c; j < n; ++j) D[size_t(r) * n + j] -= f * D[size_t(c) * n + j];
+            for (int j = 0; j < n; ++j) N[size_t(r) * n + j] -= f * N[size_t(c) * n + j];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        const cd inv = 1.0 / D[size_t(c) * n + c];
+        for (int j = 0; j < n; ++j) {
+            cd v = N[size_t(c) * n + j];
+            for (int k = c + 1; k < n; ++k) v -= D[size_t(c) * n + k] * N[size_t(k) * n + j];
+            N[size_t(c) * n + j] = v * inv;
+        }
+    }
+}
+
+}  // namespace
+
+// exp(A) of a small dense matrix by scaling and squaring with the diagonal
+// [13/13] Pade approximant (Higham, SIAM J. Matrix Anal. Appl. 26, 2005):
+// A is scaled by 2^-s so that its 1-norm is at most 5.37, and the
+// approximant's coefficients are (26-j)! 13! / (26! j! (13-j)!).
+void expm_dense(int n, std::vector<cd>& A) {
+    double norm1 = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double col = 0.0;
+        for (int i = 0; i < n; ++i) col += std::abs(A[size_t(i) * n + j]);
+        norm1 = std::max(norm1, col);
+    }
+    if (!std::isfinite(norm1)) fail(MXP_ERR_NONFINITE, "non-finite matrix in expm");
+    const int s = norm1 > 5.37 ? int(std::ceil(std::log2(norm1 / 5.37))) : 0;
+    const double scale = std::ldexp(1.0, -s);
+    for (cd& a : A) a *= scale;
+    double c[14];
+    c[0] = 1.0;
+    for (int j = 1; j <= 13; ++j) c[j] = c[j - 1] * double(13 - j + 1) / (double(j) * double(26 - j + 1));
+    const size_t nn = size_t(n) * n;
+    std::vector<cd> I(nn, cd(0.0, 0.0)), B2, B4, B6, T, U, V, W;
+    for (int i = 0; i < n; ++i) I[size_t(i) * n + i] = 1.0;
+    matmul(n, A, A, B2);
+    matmul(n, B2, B2, B4);
+    matmul(n, B2, B4, B6);
+    // U = A [B6 (c13 B6 + c11 B4 + c9 B2) + c7 B6 + c5 B4 + c3 B2 + c1 I]
+    T.assign(nn, 0.0);
+    for (size_t q = 0; q < nn; ++q) T[q] = c[13] * B6[q] + c[11] * B4[q] + c[9] * B2[q];
+    matmul(n, B6, T, W);
+    for (size_t q = 0; q < nn; ++q) W[q] += c[7] * B6[q] + c[5] * B4[q] + c[3] * B2[q] + c[1] * I[q];
+    matmul(n, A, W, U);
+    // V = B6 (c12 B6 + c10 B4 + c8 B2) + c6 B6 + c4 B4 + c2 B2 + c0 I
+    for (size_t q = 0; q < nn; ++q) T[q] = c[12] * B6[q] + c[10] * B4[q] + c[8] * B2[q];
+    matmul(n, B6, T, V);
+    for (size_t q = 0; q < nn; ++q) V[q] += c[6] * B6[q] + c[4] * B4[q] + c[2] * B2[q] + c[0] * I[q];
+    std::vector<cd> Nm(nn), Dm(nn);
+    for (size_t q = 0; q < nn; ++q) {
+        Nm[q] = V[q] + U[q];
+        Dm[q] = V[q] - U[q];
+    }
+    solve_in_place(n, Dm, Nm);
+    for (int k = 0; k < s; ++k) {
+        matmul(n, Nm, Nm, T);
+        Nm.swap(T);
+    }
+    A.swap(Nm);
+}
+
 void design_psi2_series(const mxp_schedule& sc, double t, mxp_precision prec, std::vector<double>* coef,
                         int* m) {
     const bool fp64 = (prec == MXP_PREC_FP64);

@@ -486,3 +486,46 @@ def test_cap_thin_layer_refuses_complex_float_stepping(ctx):
     with pytest.raises(mxp.MxpError) as e:
         mxp.mxp_solve(P, o, xd, torch.zeros_like(xd))
     assert e.value.status == mxp.MXP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["2d-inh", "3d-inh"])
+@pytest.mark.parametrize("psi", [False, True])
+def test_krylov_matrix_function(ctx, name, psi):
+    # the Arnoldi route to exp / psi_1 against the oracle's; the stop estimate is
+    # relative to ||x|| and conservative, so 1e-10 gives <= 1e-8 relative to the result
+    prob = make(name)
+    announce("krylov action", name, psi)
+    P = mxp.Problem(ctx, prob)
+    # in 3D, t ||A|| is about 1.5 times larger and the default t needs more than
+    # 250 vectors: half of it stays within the cap
+    t, s = prob.default_t() * (0.5 if prob.dim == 3 else 1.0), prob.default_shift()
+    x = wl.random_vector(prob.npts, 23)
+    xd = to_dev(x)
+    yd = torch.full_like(xd, 7.0)  # the output is overwritten, whatever it held
+    st, dim = mxp.mxp_apply_fn_krylov(P, psi, t, s, 1e-10, 250, xd, yd)
+    assert st == mxp.MXP_OK and 8 <= dim <= 250
+    As = op.helmholtz(prob, s)
+    ref = matfun.phi1_action(As, t, x) if psi else matfun.exp_action(As, t, x)
+    assert rel(to_host(yd), ref) <= 1e-8
+    # a capped basis reports NOT_CONVERGED with its size and leaves an approximation
+    st, dim = mxp.mxp_apply_fn_krylov(P, psi, t, s, 1e-10, 16, xd, yd)
+    assert st == mxp.MXP_NOT_CONVERGED and dim == 16
+    assert np.isfinite(to_host(yd)).all()
+
+
+def test_krylov_matrix_function_invariant_space(ctx):
+    # 3x3 nodes: the Krylov space is at most 9-dimensional, so the basis breaks
+    # down and the result is exact
+    prob = wl.small_problem((3, 3), layer=0)
+    announce("krylov breakdown 3x3")
+    P = mxp.Problem(ctx, prob)
+    t, s = prob.default_t(), 0.1
+    x = wl.random_vector(prob.npts, 24)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    st, dim = mxp.mxp_apply_fn_krylov(P, False, t, s, 1e-12, 50, xd, yd)
+    assert st == mxp.MXP_OK and dim <= 9
+    assert rel(to_host(yd), matfun.exp_dense(op.helmholtz(prob, s), t) @ x) <= 1e-11
+    zd = torch.zeros_like(xd)
+    st, dim = mxp.mxp_apply_fn_krylov(P, True, t, s, 1e-12, 50, zd, yd)
+    assert st == mxp.MXP_OK and dim == 0 and not to_host(yd).any()
