@@ -535,6 +535,107 @@ def bench_paper_tables(args, torch, mxp, wl):
     print(json.dumps(rec), flush=True)
 
 
+def bench_variants(args, torch, mxp, wl):
+    """The four inner systems/solvers of Algorithm 1 (inner_solver 0-3: GMRES
+    and the plain fixed-point iteration on the exp form, Theorem 2.1; the same
+    two on the psi_2 form, Section 3.1 and Theorem 2.2) on the 2D homogeneous
+    model with a dipole source, fprtol 0.01, outer tolerance 1e-5, complex
+    double: with the shift 1/freq at freq 40, 80, 160, and unshifted at freq
+    20 and 40 (inner iterations capped at 3000).  One step is the whole set;
+    value is the summed solve time."""
+    ctx = mxp.Context(0)
+    out, total = [], 0.0
+    cases = [(freq, None, (0, 1, 2, 3)) for freq in (40, 80, 160)] + [(freq, 0.0, (0, 1, 2, 3)) for freq in (20, 40)]
+    for freq, shift, solvers in cases:
+        prob = wl.homog_problem(2, freq)
+        fd = torch.from_numpy(wl.dipole_source(prob).ravel()).to("cuda:0")
+        for solver in solvers:
+            P = mxp.Problem(ctx, prob)
+            o = P.default_opts()
+            o.rtol = 1e-5
+            o.fprtol = 0.01
+            o.inner_solver = solver
+            o.max_inner = 3000
+            if shift is not None:
+                o.shift = shift
+            u = torch.zeros_like(fd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = mxp.mxp_solve(P, o, fd, u)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            total += sec
+            inner, _ = mxp.mxp_solve_history(P)
+            e = {"freq": freq, "shift": "1/freq" if shift is None else shift, "inner_solver": solver,
+                 "status": st["status"], "outer": st["outer_its"], "inner_mean": round(st["inner_mean"], 2),
+                 "inner": inner, "actions": st["fn_actions"], "relres": st["true_relres"], "seconds": round(sec, 3)}
+            out.append(e)
+            print(f"[bench] variants freq {freq} shift {e['shift']} solver {solver}: outer {e['outer']} "
+                  f"inner {inner} actions {e['actions']} {sec:.2f} s", file=sys.stderr, flush=True)
+            P.close()
+    rec = {
+        "metric": "s for the inner-solver variants (outer tolerance 1e-5); iteration counts per variant",
+        "value": round(total, 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(total * 1e3, 1), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic: the paper's 2D homogeneous model, dipole source",
+        "config": {"workload": "variants"}, "entries": out,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_matfun_krylov(args, torch, mxp, wl):
+    """One exp(i t A_s) action by the Chebyshev schedule (complex double and
+    complex float) and by the Arnoldi route (complex double, tolerances 1e-6
+    and 1e-10, at most 250 vectors) on the 128^2 homogeneous and 2048^2 GRF
+    workloads, each timed warm; value is the Arnoldi/Chebyshev time ratio at
+    2048^2 and 1e-6."""
+    ctx = mxp.Context(0)
+    out = []
+    for prob in (wl.config1(), wl.config2()):
+        P = mxp.Problem(ctx, prob)
+        t, s = prob.default_t(), prob.default_shift()
+        x = torch.from_numpy(wl.random_vector(prob.npts, 5)).to("cuda:0")
+        e = {"workload": prob.name, "grid": list(prob.n)}
+        ref = torch.empty_like(x)
+        for name, dt in (("chebyshev_c128_ms", torch.complex128), ("chebyshev_c64_ms", torch.complex64)):
+            xx = x.to(dt)
+            yy = torch.empty_like(xx)
+            mxp.mxp_apply_exp(P, t, s, xx, yy)  # warm (tile tuning)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mxp.mxp_apply_exp(P, t, s, xx, yy)
+            torch.cuda.synchronize()
+            e[name] = round(1e3 * (time.perf_counter() - t0), 3)
+            if dt == torch.complex128:
+                ref.copy_(yy)
+        sch = mxp.mxp_design_schedule(P.desc, t, s, mxp.MXP_PREC_FP64)
+        e["chebyshev_c128_levels"] = sch.S * sch.m
+        y = torch.empty_like(x)
+        mxp.mxp_apply_fn_krylov(P, False, t, s, 1e-6, 250, x, y)  # warm (basis allocation)
+        for tol in (1e-6, 1e-10):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, dim = mxp.mxp_apply_fn_krylov(P, False, t, s, tol, 250, x, y)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            e[f"arnoldi_{tol:g}"] = {"status": st, "vectors": dim, "ms": round(1e3 * sec, 1),
+                                     "rel_diff_to_chebyshev_c128": ((y - ref).norm() / ref.norm()).item()}
+        print(f"[bench] matfun-krylov {e}", file=sys.stderr, flush=True)
+        out.append(e)
+        P.close()
+        del x, y, ref
+        torch.cuda.empty_cache()
+    big = out[-1]
+    rec = {
+        "metric": "Arnoldi / Chebyshev time for one exp(i t A_s) action (2048^2, tol 1e-6)",
+        "value": round(big["arnoldi_1e-06"]["ms"] / big["chebyshev_c128_ms"], 1), "unit": "x",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": big["arnoldi_1e-06"]["ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic (seeded random input vector)", "config": {"workload": "matfun-krylov"}, "entries": out,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -542,7 +643,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d-grf-2048",
                     choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256", "3d-layered-batch", "3d-learned",
-                             "paper-tables"])
+                             "paper-tables", "variants", "matfun-krylov"])
     ap.add_argument("--train-models", type=int, default=6, help="3d-learned: 128^3 training models")
     ap.add_argument("--train-steps", type=int, default=1500, help="3d-learned: Adam steps")
     ap.add_argument("--eval-restart", type=int, default=60, help="3d-learned: FGMRES restart of the evaluation")
@@ -577,6 +678,12 @@ def main():
         return
     if args.workload == "paper-tables":
         bench_paper_tables(args, torch, mxp, wl)
+        return
+    if args.workload == "variants":
+        bench_variants(args, torch, mxp, wl)
+        return
+    if args.workload == "matfun-krylov":
+        bench_matfun_krylov(args, torch, mxp, wl)
         return
     prob = {"2d-grf-2048": wl.config2, "2d-homog-128": wl.config1, "3d-homog-256": wl.config3}[args.workload]()
     centre = tuple(m // 2 for m in prob.n)
