@@ -220,3 +220,33 @@ def test_complex_float_schedule_refused_for_a_tall_box():
     # a wider layer (8 cells) keeps it
     prob = dataclasses.replace(prob, layer=8)
     mxp.mxp_design_schedule(mxp.grid_desc(prob), prob.default_t(), 0.0, mxp.MXP_PREC_MIXED)
+
+
+def test_complex_float_clenshaw_replay_at_the_largest_accepted_box():
+    # the refusal threshold's other side: a 6-cell absorbing-potential layer at ppw 10
+    # (box height/width 1.01) keeps its complex-float schedule, and that schedule,
+    # replayed by Clenshaw in complex float on the CPU, meets the 1e-5 bar of the
+    # GPU parity tests against the oracle's action
+    import dataclasses
+    import scipy.sparse as sp
+    from oracle import matfun, operator as op
+    prob = dataclasses.replace(wl.small_problem((67, 45), layer=6, ppw=10, inhomogeneous=True, seed=7),
+                               absorber="cap")
+    t, s = prob.default_t(), prob.default_shift()
+    sc = mxp.mxp_design_schedule(mxp.grid_desc(prob), t, s, mxp.MXP_PREC_MIXED)
+    box = list(sc.box)
+    assert 0.9 < (box[3] - box[2]) / (box[1] - box[0]) <= 1.25
+    As = op.helmholtz(prob, s).tocsr()
+    x = wl.random_vector(prob.npts, 21)
+    ref = matfun.exp_action(As, t, x)
+    c = np.array(sc.coef[:2 * (sc.m + 1)]).view(complex).astype(np.complex64)
+    X = ((As - complex(sc.centre_re, sc.centre_im) * sp.identity(prob.npts)) / sc.half_width)
+    X = X.astype(np.complex64).tocsr()
+    y = x.astype(np.complex64)
+    for _ in range(sc.S):
+        b1 = np.zeros_like(y)
+        b2 = np.zeros_like(y)
+        for k in range(sc.m, 0, -1):
+            b1, b2 = (c[k] * y + np.complex64(2) * (X @ b1) - b2).astype(np.complex64), b1
+        y = (c[0] * y + X @ b1 - b2).astype(np.complex64)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-5
