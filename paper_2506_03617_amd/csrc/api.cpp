@@ -9,7 +9,13 @@
 //     (I - exp(i t A_s)) w = psi_1(i t A_s) r to relative tolerance fprtol;
 //   * Section 3.4: complex shift A_s = A + i omega^2 s D; outer flexible GMRES
 //     (constant -i t dropped);
-//   * Section 4 introduction: restart 30 for both solvers.
+//   * Section 4 introduction: restart 30 for both solvers;
+//   * variants of Algorithm 1: the plain fixed-point iteration (Section 2.1,
+//     Theorem 2.1) and the second inverse formula
+//     (I - psi_1(i t A_s)) w = psi_2(i t A_s) r (Section 3.1; its fixed-point
+//     map is Theorem 2.2's), with the psi_2 action on the exp substeps;
+//   * the matrix functions by the Arnoldi method, the paper's own route
+//     (Section 4 introduction), as an alternative building block.
 // Orthogonalisation is classical Gram--Schmidt with one re-orthogonalisation
 // (CGS2: two fused multi-dot / multi-update passes); the small least-squares
 // problems use Givens rotations on the host in double.

@@ -1,6 +1,8 @@
-// Host-side problem set-up: absorbing-layer tables, field-of-values bounds and
-// the design of the substepped Chebyshev schedule for exp(i t A_s) and
-// psi_1(i t A_s).  Nothing here touches the GPU.
+// Host-side problem set-up: absorbing-layer tables (coordinate stretch, or the
+// complex absorbing potential of Section 2.1), field-of-values bounds, the
+// design of the substepped Chebyshev schedule for exp(i t A_s), psi_1(i t A_s)
+// and psi_2(i t A_s), and a small dense matrix exponential for the Arnoldi
+// route.  Nothing here touches the GPU.
 //
 // Matrix-function evaluation scheme (the library's own choice; the paper uses
 // a restarted Krylov method for the same actions, Section 4 introduction):
