@@ -172,8 +172,7 @@ typedef struct {
                                2 GMRES(inner_restart) on (I - psi_1(i t A_s)) w = psi_2(i t A_s) r,
                                  the second inverse formula of Section 3.1;
                                3 its fixed-point iteration w <- psi_1(i t A_s) w + psi_2 r, the
-                                 time-averaged map of Section 2.2, Theorem 2.2.
-                               Nonzero values: single solves only */
+                                 time-averaged map of Section 2.2, Theorem 2.2. */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per

@@ -1020,7 +1020,7 @@ struct ActionReq {
     Run* run;
     const Sched* sd;
     double t, shift;
-    bool psi;
+    int fn;  // ActFn
     mxp_precision prec;
     const cpx<double>* x;
     cpx<double>* y;
@@ -1162,7 +1162,7 @@ class Batcher {
         size_t L = 0;
         for (size_t i = 0; i < nq; ++i) {
             ActionReq* q = reqs[i];
-            action64_on(q->run->P, *q->run->W, s_, *q->sd, q->t, q->shift, q->psi, q->prec, q->x, q->y, &q->steps,
+            action64_on(q->run->P, *q->run->W, s_, *q->sd, q->t, q->shift, q->fn, q->prec, q->x, q->y, &q->steps,
                         &r64[i], &r32[i]);
             L = std::max(L, r64[i].size() + r32[i].size());
         }
@@ -1284,14 +1284,13 @@ static void action64(Run& run, const Sched& sc, double t, double shift, int fn, 
             action64_on(run.P, *run.W, run.s, sc, t, shift, fn, prec, x, y, steps);
         return;
     }
-    if (fn == ACT_PSI2) fail(MXP_ERR_UNSUPPORTED, "batched solves apply exp and psi_1 actions only");
-    const bool psi = fn == ACT_PSI1;
+
     ActionReq r;
     r.run = &run;
     r.sd = &sc;
     r.t = t;
     r.shift = shift;
-    r.psi = psi;
+    r.fn = fn;
     r.prec = prec;
     r.x = x;
     r.y = y;
@@ -1549,7 +1548,6 @@ static mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f,
     }
     if (o.use_learned && !P->net) fail(MXP_ERR_INVALID_ARG, "use_learned needs a network (mxp_problem_set_learned)");
     if (o.use_learned && run.batch) fail(MXP_ERR_UNSUPPORTED, "the learned stage runs in single solves only");
-    if (o.inner_solver != 0 && run.batch) fail(MXP_ERR_UNSUPPORTED, "the inner-solver variants run in single solves only");
     int misses = 0;
     // cost-aware acceptance: mean log residual reduction and wall time of the
     // MatExPre iterations so far, wall time of the last network try
@@ -2017,8 +2015,6 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             if (P->ctx->device != ctx->device) fail(MXP_ERR_INVALID_ARG, "batch: problem on another device");
             check_opts(&opts[q]);
             if (opts[q].use_learned) fail(MXP_ERR_UNSUPPORTED, "batch: the learned stage runs in single solves only");
-            if (opts[q].inner_solver != 0)
-                fail(MXP_ERR_UNSUPPORTED, "batch: the fixed-point inner solver runs in single solves only");
             if (nrhs[q] < 0) fail(MXP_ERR_INVALID_ARG, "batch: nrhs must be >= 0");
             if (nrhs[q] == 0) continue;
             if (!f[q] || !u[q] || f[q] == u[q]) fail(MXP_ERR_INVALID_ARG, "batch: f and u must be distinct non-NULL");
@@ -2028,10 +2024,13 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             const size_t vec = size_t(n) * sizeof(cpx<double>);
             size_t bytes = vec * (size_t(2 * o.outer_restart + 2) + size_t(o.inner_restart + 4));
             bytes += o.precision == MXP_PREC_FP64 ? 7 * vec : 9 * vec / 2;
+            if (o.inner_solver >= 2) bytes += o.precision == MXP_PREC_FP64 ? vec : vec / 2;  // psi_2's y_1
             bytes += size_t(reduce_blocks(n)) * 256 * sizeof(cpx<double>) + (1 << 20);
             // set up once, outside the threads: schedules, diagonal tables and
             // 2D tiles are shared read-only by every right-hand side of P
             const Sched& sd = get_sched(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
+            if (o.inner_solver >= 2 && sd.m_psi2 < 0)
+                design_psi2_series(sd.s, sd.t, sd.prec, &sd.coef_psi2, &sd.m_psi2);
             (void)plain_diag(P, 0.0);
             if (P->g.dim == 2) {
                 if (o.precision == MXP_PREC_FP64 && P->tiles[0].K == 0)

@@ -91,6 +91,38 @@ def test_batch_equals_separate_solves_bit_for_bit(ctx, prec, two_level):
         h.close()
 
 
+@pytest.mark.parametrize("inner_solver", [1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_inner_solver_variants_equal_separate_solves(ctx, prec, inner_solver):
+    # the fixed-point and psi_2 forms of Algorithm 1 in a batch: the same actions,
+    # recorded per right-hand side and launched together, give the separate solves' bits
+    probs, rhs = uneven_set()
+    probs, rhs = [probs[1], probs[3]], [rhs[1], rhs[3]]
+    announce("batch variants", prec, inner_solver)
+    handles = [mxp.Problem(ctx, p) for p in probs]
+    opts = []
+    for h in handles:
+        o = h.default_opts()
+        o.precision = prec
+        o.inner_solver = inner_solver
+        opts.append(o)
+    status, stats, us = run_batch(ctx, handles, opts, rhs)
+    assert status == mxp.MXP_OK
+    k = 0
+    for q, h in enumerate(handles):
+        for r in range(rhs[q].shape[0]):
+            fd = to_dev(rhs[q][r])
+            ud = torch.zeros_like(fd)
+            st = mxp.mxp_solve(h, opts[q], fd, ud)
+            assert st["status"] == mxp.MXP_OK and stats[k]["status"] == mxp.MXP_OK
+            for key in ("outer_its", "inner_its_total", "stencil_steps", "fn_actions", "true_relres"):
+                assert stats[k][key] == st[key], (q, r, key)
+            assert np.array_equal(us[q][r], to_host(ud)), (q, r)
+            k += 1
+    for h in handles:
+        h.close()
+
+
 def test_batch_against_oracle_and_admission_limits(ctx):
     probs, rhs = uneven_set()
     announce("batch vs oracle")

@@ -345,9 +345,6 @@ def test_fixed_point_inner_solver(ctx, name, prec):
     st = mxp.mxp_solve(P, o, fd, ud)
     assert st["true_relres"] <= 1e-12
     assert rel(to_host(ud), krylov.direct_solve(prob, f)) <= (1e-10 if prec == 0 else 1e-5)
-    # batched solves keep to GMRES
-    with pytest.raises(mxp.MxpError):
-        mxp.mxp_solve_batch(ctx, [P], [o], [fd[None, :]], [ud[None, :].clone()], 1)
 
 
 @pytest.mark.parametrize("name,tfac", [(n, 1.0) for n in CASES] + [("2d-inh", f) for f in (0.3, 0.15, 0.05)]
