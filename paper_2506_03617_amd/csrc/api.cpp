@@ -108,6 +108,7 @@ struct Workspace {
     // output, (f32) [7..8] casts, [9] the psi_2 action's first-substep term
     DevMem act64[10], act32[10];
     DevMem innerV, innerRh, innerTmp, innerRr;
+    DevMem innerV32;  // complex-float inner basis of the mixed form
     DevMem krylovV;
     DevMem outerV, outerZ, outerR;
     DevMem partial, small;
@@ -832,8 +833,8 @@ static double norm2(Run& run, const cpx<double>* v) {
 
 // CGS2: orthogonalise w against V_0..V_{nv-1}; h receives the projection
 // coefficients and the returned value is ||w|| afterwards.
-static double cgs2(Run& run, const cpx<double>* V, int64_t ld, int nv, cpx<double>* w,
-                   std::vector<cd>& h) {
+template <typename TV>
+static double cgs2(Run& run, const TV* V, int64_t ld, int nv, cpx<double>* w, std::vector<cd>& h) {
     const int64_t n = npts(run.P);
     hipStream_t s = run.s;
     Small sm = small_buffers(run);
@@ -1323,7 +1324,9 @@ static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<
     hipStream_t s = run.s;
     const Sched& sc = get_sched(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
     const int m = o.inner_restart;
-    WS.innerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
+    // complex-double basis: GMRES in the FP64 form; otherwise one direction vector
+    const bool basis64 = o.precision == MXP_PREC_FP64 && (o.inner_solver == 0 || o.inner_solver == 2);
+    WS.innerV.ensure(size_t(basis64 ? m + 1 : 1) * n * sizeof(cpx<double>));
     WS.innerRh.ensure(size_t(n) * sizeof(cpx<double>));
     WS.innerTmp.ensure(size_t(n) * sizeof(cpx<double>));
     WS.innerRr.ensure(size_t(n) * sizeof(cpx<double>));
@@ -1370,30 +1373,50 @@ static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<
         }
         return its;
     }
+    // The mixed form keeps the inner basis in complex float: the system is
+    // only solved to fprtol, and its actions run in complex float anyway.
+    // The new direction and the Gram-Schmidt sums stay in complex double; a
+    // float basis vector is widened into `rr` (free within a cycle) as the
+    // action's input.  It halves the basis traffic of CGS2.
+    const bool v32 = !basis64;
+    cpx<float>* V32 = nullptr;
+    if (v32) {
+        WS.innerV32.ensure(size_t(m + 1) * n * sizeof(cpx<float>));
+        V32 = WS.innerV32.as<cpx<float>>();
+    }
     const cpx<double>* rcur = rhat;
     double beta = z;
     int its = 0;
     Givens gv(m);
     std::vector<cd> h;
     while (true) {
-        launch_scale({1.0 / beta, 0.0}, rcur, V, n, s);
+        if (v32) launch_scale_to_c64({1.0 / beta, 0.0}, rcur, V32, n, s);
+        else launch_scale({1.0 / beta, 0.0}, rcur, V, n, s);
         gv.reset(beta);
         int k = 0;
         bool conv = false;
         for (int j = 0; j < m; ++j) {
             cpx<double>* vj = V + size_t(j) * n;
-            cpx<double>* vn = V + size_t(j + 1) * n;
+            // the new direction: the basis' next slot, or (float basis) V's first
+            cpx<double>* vn = v32 ? V : V + size_t(j + 1) * n;
+            if (v32) {
+                launch_to_c128(V32 + size_t(j) * n, rr, n, s);
+                vj = rr;
+            }
             action64(run, sc, o.t, o.shift, fn_op, o.precision, vj, tmp, &cnt.steps);
             cnt.actions++;
             // v_{j+1} <- v_j - E v_j
             launch_scale(one, vj, vn, n, s);
             launch_axpby(mone, tmp, one, vn, n, s);
-            const double hn = cgs2(run, V, n, j + 1, vn, h);
+            const double hn = v32 ? cgs2(run, V32, n, j + 1, vn, h) : cgs2(run, V, n, j + 1, vn, h);
             ++its;
             const double res = gv.add_column(j, h, hn);
             if (!std::isfinite(res)) fail(MXP_ERR_NONFINITE, "non-finite inner residual estimate");
             const bool breakdown = hn <= 1e-14 * beta;
-            if (!breakdown) launch_scale({1.0 / hn, 0.0}, vn, vn, n, s);
+            if (!breakdown) {
+                if (v32) launch_scale_to_c64({1.0 / hn, 0.0}, vn, V32 + size_t(j + 1) * n, n, s);
+                else launch_scale({1.0 / hn, 0.0}, vn, vn, n, s);
+            }
             k = j + 1;
             if (res <= tol || breakdown) {
                 conv = true;
@@ -1403,7 +1426,8 @@ static int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<
         }
         const std::vector<cd> y = gv.solve(k);
         upload_coeffs(run, y);
-        launch_mcombine(w, V, n, k, small_buffers(run).y, n, s);
+        if (v32) launch_mcombine(w, static_cast<const cpx<float>*>(V32), n, k, small_buffers(run).y, n, s);
+        else launch_mcombine(w, static_cast<const cpx<double>*>(V), n, k, small_buffers(run).y, n, s);
         if (conv || its >= o.max_inner) break;
         // restart: r = r_hat - (w - E w)
         action64(run, sc, o.t, o.shift, fn_op, o.precision, w, tmp, &cnt.steps);

@@ -129,15 +129,22 @@ void launch_cheb2d(const ChebPassArgs<R>& a, int K, int NX, hipStream_t s);
 // kernel sums them in a fixed order, so results are bitwise reproducible.
 int reduce_blocks(int64_t n);  // number of partial sums used for length n
 
-// out[i] = sum_p conj(V_i[p]) * w[p], i < nv   (complex double, out on device)
-void launch_mdot(const cpx<double>* V, int64_t ld, int nv, const cpx<double>* w, int64_t n,
+// TV, the basis' element type: cpx<double>, or cpx<float> for a complex-float
+// basis (widened exactly; w and the sums stay complex double).
+// out[i] = sum_p conj(V_i[p]) * w[p], i < nv   (out on device)
+template <typename TV>
+void launch_mdot(const TV* V, int64_t ld, int nv, const cpx<double>* w, int64_t n,
                  cpx<double>* partial, cpx<double>* out, hipStream_t s);
 // w[p] -= sum_i h[i] * V_i[p]   (h on device)
-void launch_mupdate(cpx<double>* w, const cpx<double>* V, int64_t ld, int nv,
+template <typename TV>
+void launch_mupdate(cpx<double>* w, const TV* V, int64_t ld, int nv,
                     const cpx<double>* h, int64_t n, hipStream_t s);
 // w[p] += sum_i y[i] * V_i[p]   (y on device)
-void launch_mcombine(cpx<double>* w, const cpx<double>* V, int64_t ld, int nv,
+template <typename TV>
+void launch_mcombine(cpx<double>* w, const TV* V, int64_t ld, int nv,
                      const cpx<double>* y, int64_t n, hipStream_t s);
+// y = a*x rounded to complex float
+void launch_scale_to_c64(cpx<double> a, const cpx<double>* x, cpx<float>* y, int64_t n, hipStream_t s);
 // out[0].re = sum_p |w[p]|^2
 void launch_nrm2sq(const cpx<double>* w, int64_t n, cpx<double>* partial, cpx<double>* out,
                    hipStream_t s);

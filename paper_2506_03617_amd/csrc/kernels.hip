@@ -270,15 +270,22 @@ __device__ __forceinline__ cpx<double> block_sum(cpx<double> v) {
 constexpr int kRedThreads = 256;
 constexpr int kMaxBlocks = 1024;
 
-__global__ __launch_bounds__(256) void k_mdot_partial(const cpx<double>* __restrict__ V, int64_t ld,
+// A basis vector entry in double (a complex-float basis is widened exactly).
+__device__ __forceinline__ cpx<double> widen(cpx<double> v) { return v; }
+__device__ __forceinline__ cpx<double> widen(cpx<float> v) { return {double(v.re), double(v.im)}; }
+
+// TV: the basis' element type (complex double, or complex float for the
+// inner GMRES of the mixed form); w and all arithmetic are complex double.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_mdot_partial(const TV* __restrict__ V, int64_t ld,
                                                       const cpx<double>* __restrict__ w, int64_t n,
                                                       cpx<double>* __restrict__ partial) {
     const int vi = blockIdx.y;
-    const cpx<double>* __restrict__ Vi = V + int64_t(vi) * ld;
+    const TV* __restrict__ Vi = V + int64_t(vi) * ld;
     cpx<double> acc{0.0, 0.0};
     const int64_t stride = int64_t(gridDim.x) * kRedThreads;
     for (int64_t p = int64_t(blockIdx.x) * kRedThreads + threadIdx.x; p < n; p += stride) {
-        const cpx<double> a = Vi[p], b = w[p];
+        const cpx<double> a = widen(Vi[p]), b = w[p];
         // conj(a) * b
         acc.re = fma(a.re, b.re, fma(a.im, b.im, acc.re));
         acc.im = fma(a.re, b.im, fma(-a.im, b.re, acc.im));
@@ -311,9 +318,9 @@ __global__ __launch_bounds__(256) void k_partial_sum(const cpx<double>* __restri
 
 constexpr int kMaxVec = 256;
 
-template <bool kSub>
+template <typename TV, bool kSub>
 __global__ __launch_bounds__(256) void k_mupdate(cpx<double>* __restrict__ w,
-                                                 const cpx<double>* __restrict__ V, int64_t ld, int nv,
+                                                 const TV* __restrict__ V, int64_t ld, int nv,
                                                  const cpx<double>* __restrict__ h, int64_t n) {
     __shared__ cpx<double> hs[kMaxVec];
     for (int q = threadIdx.x; q < nv; q += blockDim.x) hs[q] = h[q];
@@ -321,7 +328,7 @@ __global__ __launch_bounds__(256) void k_mupdate(cpx<double>* __restrict__ w,
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += stride) {
         cpx<double> acc{0.0, 0.0};
-        for (int q = 0; q < nv; ++q) acc = cfma(hs[q], V[int64_t(q) * ld + p], acc);
+        for (int q = 0; q < nv; ++q) acc = cfma(hs[q], widen(V[int64_t(q) * ld + p]), acc);
         cpx<double> o = w[p];
         if (kSub) {
             o.re -= acc.re;
@@ -346,6 +353,15 @@ __global__ __launch_bounds__(256) void k_scale(cpx<double> a, const cpx<double>*
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += stride)
         y[p] = cmul(a, x[p]);
+}
+
+__global__ __launch_bounds__(256) void k_scale_to_c64(cpx<double> a, const cpx<double>* __restrict__ x,
+                                                      cpx<float>* __restrict__ y, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const cpx<double> v = cmul(a, x[p]);
+        y[p] = {float(v.re), float(v.im)};
+    }
 }
 
 __global__ __launch_bounds__(256) void k_to_c64(const cpx<double>* __restrict__ x,
@@ -437,26 +453,46 @@ int reduce_blocks(int64_t n) {
     return int(b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b));
 }
 
-void launch_mdot(const cpx<double>* V, int64_t ld, int nv, const cpx<double>* w, int64_t n,
+template <typename TV>
+void launch_mdot(const TV* V, int64_t ld, int nv, const cpx<double>* w, int64_t n,
                  cpx<double>* partial, cpx<double>* out, hipStream_t s) {
     const int nb = reduce_blocks(n);
-    hipLaunchKernelGGL(k_mdot_partial, dim3(nb, nv), dim3(kRedThreads), 0, s, V, ld, w, n, partial);
+    hipLaunchKernelGGL(k_mdot_partial<TV>, dim3(nb, nv), dim3(kRedThreads), 0, s, V, ld, w, n, partial);
     hipLaunchKernelGGL(k_partial_sum, dim3(nv), dim3(kRedThreads), 0, s, partial, nb, out);
     check_launch("mdot");
 }
+template void launch_mdot<cpx<double>>(const cpx<double>*, int64_t, int, const cpx<double>*, int64_t,
+                                       cpx<double>*, cpx<double>*, hipStream_t);
+template void launch_mdot<cpx<float>>(const cpx<float>*, int64_t, int, const cpx<double>*, int64_t,
+                                      cpx<double>*, cpx<double>*, hipStream_t);
 
-void launch_mupdate(cpx<double>* w, const cpx<double>* V, int64_t ld, int nv, const cpx<double>* h,
+template <typename TV>
+void launch_mupdate(cpx<double>* w, const TV* V, int64_t ld, int nv, const cpx<double>* h,
                     int64_t n, hipStream_t s) {
     if (nv > kMaxVec) fail(MXP_ERR_INVALID_ARG, "too many basis vectors");
-    hipLaunchKernelGGL(k_mupdate<true>, dim3(stream_blocks(n)), dim3(256), 0, s, w, V, ld, nv, h, n);
+    hipLaunchKernelGGL((k_mupdate<TV, true>), dim3(stream_blocks(n)), dim3(256), 0, s, w, V, ld, nv, h, n);
     check_launch("mupdate");
 }
+template void launch_mupdate<cpx<double>>(cpx<double>*, const cpx<double>*, int64_t, int, const cpx<double>*,
+                                          int64_t, hipStream_t);
+template void launch_mupdate<cpx<float>>(cpx<double>*, const cpx<float>*, int64_t, int, const cpx<double>*,
+                                         int64_t, hipStream_t);
 
-void launch_mcombine(cpx<double>* w, const cpx<double>* V, int64_t ld, int nv, const cpx<double>* y,
+template <typename TV>
+void launch_mcombine(cpx<double>* w, const TV* V, int64_t ld, int nv, const cpx<double>* y,
                      int64_t n, hipStream_t s) {
     if (nv > kMaxVec) fail(MXP_ERR_INVALID_ARG, "too many basis vectors");
-    hipLaunchKernelGGL(k_mupdate<false>, dim3(stream_blocks(n)), dim3(256), 0, s, w, V, ld, nv, y, n);
+    hipLaunchKernelGGL((k_mupdate<TV, false>), dim3(stream_blocks(n)), dim3(256), 0, s, w, V, ld, nv, y, n);
     check_launch("mcombine");
+}
+template void launch_mcombine<cpx<double>>(cpx<double>*, const cpx<double>*, int64_t, int, const cpx<double>*,
+                                           int64_t, hipStream_t);
+template void launch_mcombine<cpx<float>>(cpx<double>*, const cpx<float>*, int64_t, int, const cpx<double>*,
+                                          int64_t, hipStream_t);
+
+void launch_scale_to_c64(cpx<double> a, const cpx<double>* x, cpx<float>* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_to_c64, dim3(stream_blocks(n)), dim3(256), 0, s, a, x, y, n);
+    check_launch("scale_to_c64");
 }
 
 void launch_nrm2sq(const cpx<double>* w, int64_t n, cpx<double>* partial, cpx<double>* out,
