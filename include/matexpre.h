@@ -71,8 +71,9 @@ typedef enum {
 
 typedef enum {
     MXP_PREC_FP64 = 0,  /* every step in complex double                              */
-    MXP_PREC_MIXED = 1  /* matrix-function actions in complex float; Krylov bases,     */
-                        /* Hessenberg, true residual and the outer iteration in double */
+    MXP_PREC_MIXED = 1  /* matrix-function actions and the inner GMRES basis in       */
+                        /* complex float; Gram-Schmidt sums, Hessenberg, the outer    */
+                        /* FGMRES bases, true residual and outer iteration in double  */
 } mxp_precision;
 
 typedef struct mxp_context mxp_context;
@@ -267,7 +268,7 @@ mxp_status mxp_apply_fn_krylov(mxp_problem* prob, int32_t psi, double t, double 
 /* w = M(r), Algorithm 1 (Section 3.4): psi_1 action, then GMRES from w = 0 on
  * (I - exp(i t A_s)) w = psi_1(i t A_s) r until the residual estimate is
  * <= fprtol * ||psi_1(i t A_s) r||.  r and w are complex double; with
- * MXP_PREC_MIXED the matrix-function actions run in complex float.
+ * MXP_PREC_MIXED the matrix-function actions and the inner basis are complex float.
  * opts->inner_solver selects the inner system and solver (the psi_2 form
  * returns w ~ (I - psi_1(i t A_s))^{-1} psi_2(i t A_s) r).
  * *inner_its (may be NULL) receives the inner iteration count. */
