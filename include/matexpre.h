@@ -252,16 +252,19 @@ mxp_status mxp_apply_psi2(mxp_problem* prob, double t, double shift, mxp_dtype d
 
 /* y = exp(i t A_s) x (psi = 0) or psi_1(i t A_s) x (psi = 1) by the Arnoldi
  * method, the Krylov route the paper takes for its matrix functions (Section 4
- * introduction), as an alternative to the Chebyshev schedule; unrestarted,
- * with at most max_dim (1..250) basis vectors of n complex doubles each,
- * allocated by the library and kept with the problem.  The basis of A_s from
- * x is orthogonalised by classical Gram-Schmidt with a second pass; y =
- * ||x|| V f(i t H) e_1 with the small exponential computed on the host.  The
- * basis grows until h_{m+1,m} |e_m^T f(i t H_m) e_1| <= tol (relative to
- * ||x||; tested every 8 vectors).  x, y: distinct complex double device
- * vectors; *dim (may be NULL) receives the basis size.  Errors: INVALID_ARG;
- * NOT_CONVERGED (positive) if max_dim vectors did not meet tol, y then holds
- * the max_dim approximation. */
+ * introduction), as an alternative to the Chebyshev schedule.  A basis of A_s
+ * (at most max_dim, 1..250, vectors of n complex doubles, allocated by the
+ * library and kept with the problem) is orthogonalised by classical
+ * Gram-Schmidt with a second pass, and y = ||x|| V f(i t H) e_1 with the small
+ * exponential computed on the host.  A basis grows until
+ * h_{m+1,m} |e_m^T f(i t H_m) e_1| <= tol (relative to its start vector;
+ * tested every 8 vectors).  If max_dim vectors do not suffice, the action is
+ * restarted by time stepping: t is split into q = 2, 4, ..., 64 substeps with
+ * a fresh basis each, to tolerance tol / q (psi_1 by variation of constants).
+ * x, y: distinct complex double device vectors; *dim (may be NULL) receives
+ * the number of basis vectors built in all.  Errors: INVALID_ARG;
+ * NOT_CONVERGED (positive) if 64 substeps did not suffice, y then holds that
+ * approximation. */
 mxp_status mxp_apply_fn_krylov(mxp_problem* prob, int32_t psi, double t, double shift, double tol,
                                int32_t max_dim, const void* x, void* y, int32_t* dim);
 

@@ -109,7 +109,7 @@ struct Workspace {
     DevMem act64[10], act32[10];
     DevMem innerV, innerRh, innerTmp, innerRr;
     DevMem innerV32;  // complex-float inner basis of the mixed form
-    DevMem krylovV;
+    DevMem krylovV, krylovP;
     DevMem outerV, outerZ, outerR;
     DevMem partial, small;
     std::vector<cpx<double>> host_small;
@@ -1453,17 +1453,18 @@ static void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<dou
     launch_stencil(a, s);
 }
 
-// f(i t A_s) x with f = exp or psi_1 by the Arnoldi method, the route the
+// f(i t A_s) x with f = exp or psi_1 from one Arnoldi basis, the route the
 // paper takes for its matrix functions (a Krylov method, Section 4
-// introduction), here unrestarted with a capped basis.  V spans the Krylov
-// space of A_s from x (classical Gram-Schmidt with a second pass, complex
-// double), H is the Hessenberg matrix of A_s on it, and
-// y = ||x|| V f(i t H) e_1 with the small exponential computed densely on the
-// host (psi_1 from the augmented matrix [[i t H, e_1], [0, 0]]).  Every 8
-// vectors the estimate h_{m+1,m} |e_m^T f(i t H_m) e_1| (relative to ||x||)
-// is compared with tol.  Returns the basis size; *ok is false if max_dim
-// vectors did not meet tol (y then holds the last approximation).
-static int krylov_action(Run& run, bool psi, double t, double shift, double tol, int max_dim,
+// introduction).  V spans the Krylov space of A_s from x (classical
+// Gram-Schmidt with a second pass, complex double), H is the Hessenberg
+// matrix of A_s on it, and y = ||x|| V f(i t H) e_1 with the small
+// exponential computed densely on the host (psi_1 from the augmented matrix
+// [[i t H, e_1], [0, 0]]).  Every 8 vectors the estimate
+// h_{m+1,m} |e_m^T f(i t H_m) e_1| (relative to ||x||) is compared with tol.
+// x may equal y (the basis holds x before y is written).  Returns the basis
+// size; *ok is false if max_dim vectors did not meet tol (y then holds the
+// last approximation).
+static int arnoldi_action(Run& run, bool psi, double t, double shift, double tol, int max_dim,
                          const cpx<double>* x, cpx<double>* y, bool* ok) {
     mxp_problem* P = run.P;
     Workspace& WS = *run.W;
@@ -1521,6 +1522,47 @@ static int krylov_action(Run& run, bool psi, double t, double shift, double tol,
     launch_zero<double>(y, n, s);  // mcombine accumulates: y += V f
     launch_mcombine(y, V, n, m, small_buffers(run).y, n, s);
     return m;
+}
+
+// The Arnoldi route restarted by time stepping: with tau = t/q,
+//   exp(i t A_s) x = (exp(i tau A_s))^q x, a fresh basis per substep, and
+//   psi_1(i t A_s) x = (1/q) sum_{k<q} exp(i k tau A_s) p, p = psi_1(i tau A_s) x
+// (the variation-of-constants split the Chebyshev schedule also uses), by
+// y <- exp(i tau A_s) y + p.  q starts at 1 and doubles, up to 64, until every
+// substep's basis meets tol / q within max_dim vectors.  Returns the vectors
+// built over all attempts; *ok is false if q = 64 did not suffice.
+static int krylov_action(Run& run, bool psi, double t, double shift, double tol, int max_dim,
+                         const cpx<double>* x, cpx<double>* y, bool* ok) {
+    const int64_t n = npts(run.P);
+    hipStream_t s = run.s;
+    int total = 0;
+    *ok = false;
+    for (int q = 1; q <= 64 && !*ok; q *= 2) {
+        const double tau = t / q, tq = tol / q;
+        bool all = true, step_ok = false;
+        if (!psi) {
+            const cpx<double>* cur = x;
+            for (int k = 0; k < q && all; ++k) {
+                total += arnoldi_action(run, false, tau, shift, tq, max_dim, cur, y, &step_ok);
+                all = step_ok;
+                cur = y;
+            }
+        } else {
+            run.W->krylovP.ensure(size_t(n) * sizeof(cpx<double>));
+            cpx<double>* p = run.W->krylovP.as<cpx<double>>();
+            total += arnoldi_action(run, true, tau, shift, tq, max_dim, x, p, &step_ok);
+            all = step_ok;
+            launch_scale({1.0, 0.0}, p, y, n, s);
+            for (int k = 1; k < q && all; ++k) {
+                total += arnoldi_action(run, false, tau, shift, tq, max_dim, y, y, &step_ok);
+                all = step_ok;
+                launch_axpby({1.0, 0.0}, p, {1.0, 0.0}, y, n, s);
+            }
+            if (q > 1) launch_scale({1.0 / q, 0.0}, y, y, n, s);
+        }
+        *ok = all;
+    }
+    return total;
 }
 
 static void check_opts(const mxp_solve_opts* o) {
