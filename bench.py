@@ -586,7 +586,8 @@ def bench_variants(args, torch, mxp, wl):
 def bench_matfun_krylov(args, torch, mxp, wl):
     """One exp(i t A_s) action by the Chebyshev schedule (complex double and
     complex float) and by the Arnoldi route (complex double, tolerances 1e-6
-    and 1e-10, at most 250 vectors) on the 128^2 homogeneous and 2048^2 GRF
+    and 1e-10, at most 250 vectors per basis, restarted by time stepping
+    beyond that) on the 128^2 homogeneous and 2048^2 GRF
     workloads, each timed warm; value is the Arnoldi/Chebyshev time ratio at
     2048^2 and 1e-6."""
     ctx = mxp.Context(0)
