@@ -120,8 +120,10 @@ def test_spectrum_upper_half_plane_and_shift():
     assert d.max() <= 1e-8 * np.abs(ev).max()
 
 
-def test_apply_rows_matches_assembled_matrix():
-    prob = wl.small_problem((13, 11, 9), layer=3, inhomogeneous=True, seed=3)
+@pytest.mark.parametrize("absorber", ["pml", "cap"])
+def test_apply_rows_matches_assembled_matrix(absorber):
+    prob = dataclasses.replace(wl.small_problem((13, 11, 9), layer=3, inhomogeneous=True, seed=3),
+                               absorber=absorber)
     x = wl.random_vector(prob.npts, 7)
     As = op.helmholtz(prob, 0.07)
     pts = np.array([0, 5, 100, 500, prob.npts - 1, 13 * 11 * 4 + 13 * 5 + 6])
