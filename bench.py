@@ -199,7 +199,7 @@ def bench_layered_batch(args, torch, mxp, wl):
         "metric": "s to 1e-6 rel. residual (plain vs FP32/learned); stencil HBM GB/s vs peak",
         "value": round(s_per, 3), "unit": "s", "n_gpus": 1, "steps": len(times), "warmup": args.warmup,
         "ms_per_step": round(s_per * 1e3, 1), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 stepping + c128 Krylov",
+        "vs_baseline": None, "dtype": "c64 stepping and inner basis + c128 Krylov sums and outer solve",
         "data": "synthetic (seeded layered speeds with two lenses, point sources)",
         "config": {"workload": "3d-layered-batch", "main_grid": list(main_p.n), "main_sources": args.rhs,
                    "extra_grids": [list(p.n) for p in extras], "right_hand_sides": n_rhs,
@@ -386,7 +386,7 @@ def bench_learned(args, torch, mxp, wl):
         "metric": "s to 1e-6 rel. residual (plain vs FP32/learned); stencil HBM GB/s vs peak",
         "value": round(res["learned"]["wall"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(res["learned"]["wall"] * 1e3, 1), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16 network + c64 stepping + c128 Krylov",
+        "vs_baseline": None, "dtype": "bf16 network + c64 stepping and inner basis + c128 Krylov sums and outer solve",
         "data": "synthetic (seeded layered models, point sources); pairs generated by the solver",
         "config": {"workload": "3d-learned", "train_grid": [128, 128, 128], "train_models": args.train_models,
                    "pairs": n_pairs, "crops": 2 * n_pairs, "crop": list(crop), "train_steps": args.train_steps,
@@ -526,7 +526,7 @@ def bench_paper_tables(args, torch, mxp, wl):
         "metric": "s for the paper's iteration-count experiments (outer tolerance 1e-5); outer/inner counts vs the paper's tables",
         "value": round(total, 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(total * 1e3, 1), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c128 (c64 stepping above 2.5e7 nodes) + c128 Krylov",
+        "vs_baseline": None, "dtype": "c128 (c64 stepping and inner basis above 2.5e7 nodes) + c128 Krylov sums and outer solve",
         "data": "synthetic: the paper's homogeneous and converging-lens models, recomputed from their definitions",
         "config": {"workload": "paper-tables", "entries": n, "skipped": skipped},
         "matches": {"outer_exact": exact, "outer_and_inner_within_1": near, "entries": n},
@@ -768,7 +768,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 stepping + c128 Krylov",
+        "dtype": "c64 stepping and inner basis + c128 Krylov sums and outer solve",
         "data": "synthetic (seeded GRF speed, point source)" if prob.c is not None
                 else "synthetic (constant speed, point source)",
         "config": {"workload": prob.name, "grid": list(prob.n), "omega": round(prob.omega, 3),
