@@ -763,7 +763,8 @@ static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream
     HIP_CHECK(hipEventCreate(&e1));
     // short segments and single levels give small grids enough wavefronts
     const int Ks[] = {1, 2, 3, 4, 6, 8};
-    const int Lys[] = {4, 8, 16, 32, 64, 128};
+    // (intermediate lengths let the workgroup count fit the compute units)
+    const int Lys[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128};
     for (int NX = 1; NX <= 2; ++NX) {
         for (int K : Ks) {
             if (sizeof(R) == 8 && NX == 2 && K > 3) continue;  // register-limited
