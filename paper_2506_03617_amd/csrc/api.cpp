@@ -763,14 +763,32 @@ static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream
     HIP_CHECK(hipEventCreate(&e1));
     // short segments and single levels give small grids enough wavefronts
     const int Ks[] = {1, 2, 3, 4, 6, 8};
-    // (intermediate lengths let the workgroup count fit the compute units)
+    // Every workgroup (4 wavefronts) is resident at once, so the compute units
+    // holding one more of them than the others set the time.  Besides the
+    // fixed lengths, each (K, NX) tries the segment lengths whose workgroup
+    // count is just below c times the CU count, c = 1..6.
     const int Lys[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128};
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        fail(MXP_ERR_HIP, "cannot query the compute-unit count");
     for (int NX = 1; NX <= 2; ++NX) {
         for (int K : Ks) {
             if (sizeof(R) == 8 && NX == 2 && K > 3) continue;  // register-limited
-            for (int Ly : Lys) {
+            const int64_t W = int64_t(NX) * 64 - 2 * K;
+            const int64_t strips = (P->g.n[0] + W - 1) / W;
+            std::vector<int> lys(std::begin(Lys), std::end(Lys));
+            for (int c = 1; c <= 6; ++c) {
+                const int64_t segs = (4 * int64_t(c) * cus) / strips;  // waves <= 4 c CUs
+                if (segs < 1) continue;
+                const int64_t ly = (P->g.n[1] + segs - 1) / segs;
+                if (ly >= 2 && ly <= 256) lys.push_back(int(ly));
+            }
+            std::sort(lys.begin(), lys.end());
+            lys.erase(std::unique(lys.begin(), lys.end()), lys.end());
+            for (int Ly : lys) {
                 // segments longer than the grid only repeat the one-segment case
-                if (Ly != Lys[0] && Ly / 2 >= P->g.n[1]) continue;
+                if (Ly != lys.front() && Ly / 2 >= P->g.n[1]) continue;
                 cheb2d_geometry<R>(a, K, NX, Ly);
                 if (a.W <= 0) continue;
                 launch_cheb2d<R>(a, K, NX, s);  // warm
