@@ -258,7 +258,7 @@ mxp_status mxp_apply_psi2(mxp_problem* prob, double t, double shift, mxp_dtype d
  * Gram-Schmidt with a second pass, and y = ||x|| V f(i t H) e_1 with the small
  * exponential computed on the host.  A basis grows until
  * h_{m+1,m} |e_m^T f(i t H_m) e_1| <= tol (relative to its start vector;
- * tested every 8 vectors).  If max_dim vectors do not suffice, the action is
+ * tested at 8, 16, 24, 32 vectors and every 16 after).  If max_dim vectors do not suffice, the action is
  * restarted by time stepping: t is split into q = 2, 4, ..., 64 substeps with
  * a fresh basis each, to tolerance tol / q (psi_1 by variation of constants).
  * x, y: distinct complex double device vectors; *dim (may be NULL) receives

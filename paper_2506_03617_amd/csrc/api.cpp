@@ -1478,8 +1478,9 @@ static void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<dou
 // Gram-Schmidt with a second pass, complex double), H is the Hessenberg
 // matrix of A_s on it, and y = ||x|| V f(i t H) e_1 with the small
 // exponential computed densely on the host (psi_1 from the augmented matrix
-// [[i t H, e_1], [0, 0]]).  Every 8 vectors the estimate
-// h_{m+1,m} |e_m^T f(i t H_m) e_1| (relative to ||x||) is compared with tol.
+// [[i t H, e_1], [0, 0]]).  At m = 8, 16, 24, 32 and then every 16 vectors the
+// estimate h_{m+1,m} |e_m^T f(i t H_m) e_1| (relative to ||x||) is compared
+// with tol.
 // x may equal y (the basis holds x before y is written).  Returns the basis
 // size; *ok is false if max_dim vectors did not meet tol (y then holds the
 // last approximation).
@@ -1527,7 +1528,7 @@ static int arnoldi_action(Run& run, bool psi, double t, double shift, double tol
         m = j + 1;
         const bool breakdown = hn <= 1e-13 * hmax;  // the space is invariant: f(i t H) is exact
         if (!breakdown) launch_scale({1.0 / hn, 0.0}, vn, vn, n, s);
-        if (breakdown || m % 8 == 0 || m == max_dim) {
+        if (breakdown || (m % 8 == 0 && (m <= 32 || m % 16 == 0)) || m == max_dim) {
             small_fn(m);
             const double est = breakdown ? 0.0 : hn * std::abs(f[m - 1]) / beta;
             if (!std::isfinite(est)) fail(MXP_ERR_NONFINITE, "non-finite Krylov estimate");

@@ -505,17 +505,24 @@ void design_schedule(const GridInfo& g, double t, double shift, mxp_precision pr
 
 namespace {
 
-// C = A B, n x n row-major complex.
+// C = A B, n x n row-major complex.  The products are written out in real
+// arithmetic: std::complex multiplication keeps the full IEEE inf/NaN
+// treatment, several times slower, and nothing here is infinite.
 void matmul(int n, const std::vector<cd>& A, const std::vector<cd>& B, std::vector<cd>& C) {
     C.assign(size_t(n) * n, cd(0.0, 0.0));
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
+        double* c = reinterpret_cast<double*>(&C[size_t(i) * n]);
         for (int k = 0; k < n; ++k) {
-            const cd a = A[size_t(i) * n + k];
-            if (a == cd(0.0, 0.0)) continue;
-            const cd* b = &B[size_t(k) * n];
-            cd* c = &C[size_t(i) * n];
-            for (int j = 0; j < n; ++j) c[j] += a * b[j];
+            const double ar = A[size_t(i) * n + k].real(), ai = A[size_t(i) * n + k].imag();
+            if (ar == 0.0 && ai == 0.0) continue;
+            const double* b = reinterpret_cast<const double*>(&B[size_t(k) * n]);
+            for (int j = 0; j < n; ++j) {
+                const double br = b[2 * j], bi = b[2 * j + 1];
+                c[2 * j] += ar * br - ai * bi;
+                c[2 * j + 1] += ar * bi + ai * br;
+            }
         }
+    }
 }
 
 // X = D^{-1} N by Gaussian elimination with partial pivoting (N overwritten).
