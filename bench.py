@@ -517,7 +517,7 @@ def bench_paper_tables(args, torch, mxp, wl):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         weak.append({"freq": freq, "grid": list(prob.n), "seconds": round(sec, 3),
-                     "paper": "40-50 s on ceil((freq/20)^3) cluster nodes (weak-scaling figure, Section 5.2)"})
+                     "paper": "40-50 s on ceil((freq/20)^3) cluster nodes (weak-scaling figure, Section 4.2.2)"})
         print(f"[bench] psi_1 + one fixed-point step, 3D homogeneous {prob.n}: {sec:.3f} s", file=sys.stderr, flush=True)
         P.close()
         del x, y, z

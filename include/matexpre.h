@@ -310,7 +310,7 @@ mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* 
 
 /* Per-outer-iteration record of the last single solve on the problem
  * (mxp_solve or mxp_collect_pairs; batched solves leave it unchanged), as
- * the paper tabulates it (Section 5.1.2): inner_its[k] = inner GMRES
+ * the paper tabulates it (Section 4.1.2): inner_its[k] = inner GMRES
  * iterations of outer iteration k (-1 where a network direction was kept)
  * and relres[k] = the Arnoldi estimate of the relative residual after it.
  * *count receives the number of iterations recorded; min(cap, count) entries

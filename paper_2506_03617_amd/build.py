@@ -5,6 +5,7 @@ Run as `python paper_2506_03617_amd/build.py` or through __graft_entry__.build()
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -15,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmatexpre.so")
 
-SOURCES = ["kernels.hip", "cheb2d.hip", "cheb3d.hip", "cnn.hip", "schedule.cpp", "api.cpp", "network.cpp"]
+SOURCES = ["kernels.hip", "cheb2d.hip", "cheb3d.hip", "cnn.hip", "schedule.cpp", "action.cpp", "krylov.cpp",
+           "batch.cpp", "api.cpp", "network.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
@@ -39,16 +41,21 @@ def build(verbose: bool = False) -> str:
     cc = hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [cc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), *lang, "-c",
-               os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([cc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), *lang, "-c",
+                     os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # the translation units compile independently
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+        for fut in [pool.submit(subprocess.run, cmd, check=True) for cmd in cmds]:
+            fut.result()
     tmp = LIB + ".tmp"
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

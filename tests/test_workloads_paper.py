@@ -10,7 +10,7 @@ import workloads as wl
 
 
 def test_lens_model_matches_its_definition():
-    # Section 5.3.1: c_min = 1/2 at x0, h = 1/(20 freq), 20-point layer outside
+    # Section 4.3.1: c_min = 1/2 at x0, h = 1/(20 freq), 20-point layer outside
     for dim, freq, dofs in ((2, 40, 840), (3, 10, 240)):
         p = wl.lens_problem(dim, freq)
         assert abs(p.h - 1.0 / (20 * freq)) < 1e-15 and p.layer == 20
@@ -59,6 +59,6 @@ def test_stored_paper_tables_are_well_formed():
     assert len(d["shift_2d"]["rows"]) == 16 and len(d["fprtol_3d"]["rows"]) == 12 and len(d["lens"]["rows"]) == 6
     assert [len(r["inner"]) for r in d["noshift_2d"]["rows"]] == [3, 4, 4, 4]
     for key in ("shift_2d", "fprtol_3d", "lens"):
-        assert d[key]["citation"].startswith("Section 5.")
+        assert d[key]["citation"].startswith("Section 4.")
         for r in d[key]["rows"]:
             assert r["outer"] >= 1 and r["inner"] >= 1.0 and r["std"] >= 0.0

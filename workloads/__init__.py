@@ -214,7 +214,7 @@ def small_problem(n: Tuple[int, ...], layer: int, ppw: float = 10.0,
 
 
 def lens_problem(dim: int, freq: float, layer: int = 20) -> Problem:
-    """Converging-lens model (paper, Section 5.3.1, converging lens models):
+    """Converging-lens model (paper, Section 4.3.1, converging lens models):
     c = 1 - exp(-|x - x0|^2 / (2 sigma^2)) / 2 on the unit square or cube,
     sigma = 1/32, x0 = (0.5, 0.1) in 2D and (0.5, 0.25, 0.5) in 3D, so
     c_min = 1/2; h = 1/(20 freq) gives 10 points per wavelength at c_min.
@@ -263,8 +263,8 @@ def homog_problem(dim: int, freq: float) -> Problem:
 def dipole_source(prob: Problem) -> np.ndarray:
     """The homogeneous experiments' source: pairs of normalised Gaussians
     (standard deviation 3h) at the unit domain's centre -+ 6h, the lower one
-    negative; along x in 2D (Section 5.1), along each axis in 3D (Section
-    5.2).  Coordinates of the unit domain start at the inner edge of the
+    negative; along x in 2D (Section 4.1), along each axis in 3D (Section
+    4.2).  Coordinates of the unit domain start at the inner edge of the
     absorbing layer."""
     h, L = prob.h, prob.layer
     centre = 0.5 + L * h  # the unit domain's centre in grid coordinates
