@@ -1,13 +1,16 @@
-"""Benchmark: time to solve the 2D inhomogeneous Helmholtz workload
-(2048^2 grid, Gaussian-random-field speed in [1, 3], ppw 8 at c_min,
-32-cell absorbing layer, one point source) to 1e-6 relative residual with
-MatExPre-preconditioned FGMRES on one MI355X.  `--workload` selects the
-2D homogeneous 128^2 or the 3D homogeneous 256^3 workload instead.
+"""Benchmark: seconds to solve the 3D homogeneous Helmholtz workload (256^3
+grid, c = 1, ppw 8, 20-cell absorbing layer, Gaussian-smoothed point source
+of standard deviation 2 cells) to 1e-6 relative residual with
+MatExPre-preconditioned FGMRES(20) on one MI355X.  `--workload` selects the
+2D random-field 2048^2 or the 2D homogeneous 128^2 workload instead, or one
+of the other measurements (layered batch, learned stage, paper tables, ...).
 
-One step = one complete solve (outer FGMRES, every preconditioner apply,
-every exp / psi_1 action) in the chosen mixed form (complex-float stepping,
-complex-double Krylov bases and true residual).  The plain complex-double
-solve is timed beside it.  Prints one JSON line.
+One step = one complete solve in the paper's arithmetic, complex double
+(outer FGMRES, every preconditioner apply, every exp / psi_1 action): its
+mean is `value`.  Each step also solves the same system in the mixed form
+(complex-float stepping, complex-double Krylov bases and true residual),
+alternating with the double solve, and the line reports that form's time,
+speed-up and solution error against the double solve.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -82,76 +85,69 @@ def cpu_baseline(prob, f, actions_per_solve: int, fraction: int = 16):
     }
 
 
-def measure_roofline(mxp, torch, P, prob, o, reps):
-    """Roofline of the dominant kernel of the mixed solve: the complex-float
-    Clenshaw kernel.  Its average launch duration comes from HIP events around
-    complete exp actions on the library's stream (torch's current stream),
-    divided by the launches those actions make."""
-    sch = mxp.mxp_design_schedule(P.desc, o.t, o.shift, mxp.MXP_PREC_MIXED)
-    x32 = torch.randn(prob.npts, dtype=torch.complex64, device="cuda:0")
-    y32 = torch.empty_like(x32)
-    mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)  # tunes the tiles if needed
+def measure_roofline(mxp, torch, P, prob, o, reps, prec):
+    """Roofline of the dominant kernel of a solve in precision `prec`: the
+    Clenshaw kernel of its exp actions.  Its average launch duration comes
+    from HIP events around complete exp actions on the library's stream
+    (torch's current stream), divided by the launches those actions make."""
+    c64 = prec == mxp.MXP_PREC_MIXED
+    tdt, tag, R = (torch.complex64, "c64", "float") if c64 else (torch.complex128, "c128", "double")
+    z = 8 if c64 else 16          # bytes per complex value
+    sch = mxp.mxp_design_schedule(P.desc, o.t, o.shift, prec)
+    x = torch.randn(prob.npts, dtype=tdt, device="cuda:0")
+    y = torch.empty_like(x)
+    mxp.mxp_apply_exp(P, o.t, o.shift, x, y)  # tunes the tiles if needed
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
     for _ in range(reps):
-        mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)
+        mxp.mxp_apply_exp(P, o.t, o.shift, x, y)
     ev1.record()
     torch.cuda.synchronize()
     t_action = ev0.elapsed_time(ev1) * 1e-3 / reps
     t_full = t_action  # whole action (every launch)
-    rd_D = 0 if prob.c is None else 4
+    rd_D = 0 if prob.c is None else z // 2
     m = sch.m
     if prob.dim == 2:
-        # fused pass k_cheb2d<float, K, NX>: K Clenshaw levels per launch
-        tiles = mxp.mxp_get_tiles(P, mxp.MXP_PREC_MIXED)
+        # fused pass k_cheb2d<R, K, NX>: K Clenshaw levels per launch
+        tiles = mxp.mxp_get_tiles(P, prec)
         K = tiles["K"]
         passes = -(-(m + 1) // K)   # passes per series (m + 1 Clenshaw levels)
-        # per point: inputs L_{-2}, L_{-1} (8 B each, absent in the first pass),
-        # x (8 B), D; outputs two levels (8 B each; one in the final pass)
-        rd_xD = 8 + rd_D
+        # per point: inputs L_{-2}, L_{-1} (absent in the first pass), x, D;
+        # outputs two levels (one in the final pass)
+        rd_xD = z + rd_D
         if passes == 1:
-            per_series = rd_xD + 8
+            per_series = rd_xD + z
         else:
-            per_series = (rd_xD + 16) + (passes - 2) * (16 + rd_xD + 16) + (16 + rd_xD + 8)
+            per_series = (rd_xD + 2 * z) + (passes - 2) * (2 * z + rd_xD + 2 * z) + (2 * z + rd_xD + z)
         launches_per_series = passes
-        kernel = f"k_cheb2d<float,{K},{tiles['NX']}> (fused Clenshaw pass, Ly={tiles['Ly']})"
-        key = f"cheb2d_c64_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}"
+        kernel = f"k_cheb2d<{R},{K},{tiles['NX']}> (fused Clenshaw pass, Ly={tiles['Ly']})"
+        key = f"cheb2d_{tag}_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}"
         extra = {"levels_per_launch": K}
     else:
-        # single-level z-marching sweep k_stencil3d<float, OPS>: one level per
+        # single-level z-marching sweep k_stencil3d<R, OPS>: one level per
         # launch.  Per point: the first sweep reads x and writes b_{m-1}; the
         # second reads b_{m-1}, x; every later one reads b_{k+1}, b_{k+2}, x;
-        # each reads D and writes one level (8 B per complex-float value).
-        per_series = (16 + rd_D) + (24 + rd_D) + (m - 2) * (32 + rd_D)
+        # each reads D and writes one level.
+        per_series = (2 * z + rd_D) + (3 * z + rd_D) + (m - 2) * (4 * z + rd_D)
         launches_per_series = m
-        kernel = "k_stencil3d<float,OPS> (z-marching Clenshaw step)"
-        key = "stencil3d_c64"
+        kernel = f"k_stencil3d<{R},OPS> (z-marching Clenshaw step)"
+        key = f"stencil3d_{tag}"
         extra = {"levels_per_launch": 1}
-        # the two-level pass (mxp_set_tiles K = 2) timed beside it
-        mxp.mxp_set_tiles(P, mxp.MXP_PREC_MIXED, 2, 1, 1)
-        mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)
-        ev0.record()
-        for _ in range(reps):
-            mxp.mxp_apply_exp(P, o.t, o.shift, x32, y32)
-        ev1.record()
-        torch.cuda.synchronize()
-        extra["two_level_pass_action_ms"] = round(ev0.elapsed_time(ev1) / reps, 3)
-        extra["single_level_action_ms"] = round(t_full * 1e3, 3)
-        mxp.mxp_set_tiles(P, mxp.MXP_PREC_MIXED, 0, 1, 32)
     launches = sch.S * launches_per_series
     bytes_per_launch = per_series * prob.npts / launches_per_series
     avg_launch_s = t_action / launches
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    # the same work as unfused Clenshaw steps (32 / 36 B per point per step)
-    unfused_equiv = (32 + rd_D) * prob.npts * sch.S * m / t_full / 1e9
+    # the same work as unfused Clenshaw steps (4 values + D per point per step)
+    unfused_equiv = (4 * z + rd_D) * prob.npts * sch.S * m / t_full / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(key, prob.name),
             "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "bytes_per_launch": round(bytes_per_launch), **extra,
+            "action_ms": round(t_full * 1e3, 3),
             "us_per_clenshaw_level": round(t_full / (sch.S * m) * 1e6, 3),
             "unfused_step_equivalent_GBps": round(unfused_equiv, 1),
-            "schedule_c64": {"S": sch.S, "m": m, "m_psi": sch.m_psi}}
+            f"schedule_{tag}": {"S": sch.S, "m": m, "m_psi": sch.m_psi}}
 
 
 def bench_layered_batch(args, torch, mxp, wl):
@@ -642,7 +638,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="2d-grf-2048",
+    ap.add_argument("--workload", default="3d-homog-256",
                     choices=["2d-grf-2048", "2d-homog-128", "3d-homog-256", "3d-layered-batch", "3d-learned",
                              "paper-tables", "variants", "matfun-krylov"])
     ap.add_argument("--train-models", type=int, default=6, help="3d-learned: 128^3 training models")
@@ -652,7 +648,10 @@ def main():
                     help="3d-learned: time the network alone (forward at 256^3, training steps on 4 x 64^3)")
     ap.add_argument("--rhs", type=int, default=2,
                     help="3d-layered-batch: surface sources on the 512x512x256 grid (of 32)")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain complex-double solve")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-form solves beside the double ones")
+    ap.add_argument("--fp64-below", type=float, default=None,
+                    help="mixed form: relative residual below which its actions run in double "
+                         "(default: the library's default options)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-reps", type=int, default=3)
     ap.add_argument("--graphs", action="store_true", help="replay matrix-function actions from HIP graphs")
@@ -696,23 +695,28 @@ def main():
     ctx = mxp.Context(0)
     P = mxp.Problem(ctx, prob)
     fd = torch.from_numpy(f.ravel()).to("cuda:0")
-    ud = torch.zeros_like(fd)
-    o_mixed = P.default_opts()
-    o_mixed.precision = mxp.MXP_PREC_MIXED
-    o_mixed.use_graphs = 1 if args.graphs else 0
+    u64 = torch.zeros_like(fd)
+    u32 = torch.zeros_like(fd)
+    o64 = P.default_opts()
+    o64.use_graphs = 1 if args.graphs else 0
     if prob.dim == 3:
-        o_mixed.outer_restart = 20   # FGMRES(20) for the 3D workloads
+        o64.outer_restart = 20   # FGMRES(20) for the 3D workloads
+    o_mixed = P.default_opts()
+    o_mixed.outer_restart = o64.outer_restart
+    o_mixed.use_graphs = o64.use_graphs
+    o_mixed.precision = mxp.MXP_PREC_MIXED
+    if args.fp64_below is not None:
+        o_mixed.fp64_below = args.fp64_below
     if args.tiles:
         K_, NX_, Ly_ = (int(v) for v in args.tiles.split(","))
         for prec in (mxp.MXP_PREC_FP64, mxp.MXP_PREC_MIXED):
             mxp.mxp_set_tiles(P, prec, K_, NX_, Ly_)
-    print(f"[bench] {prob.name}: n={prob.n} omega={prob.omega:.2f} t={o_mixed.t:.3e} "
-          f"s={o_mixed.shift:.4f}", file=sys.stderr, flush=True)
+    print(f"[bench] {prob.name}: n={prob.n} omega={prob.omega:.2f} t={o64.t:.3e} "
+          f"s={o64.shift:.4f}", file=sys.stderr, flush=True)
 
     if args.roofline_only:
         args.warmup = 0
         args.steps = 0
-        args.no_fp64 = True
         args.no_cpu = True
         # plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
         src = torch.ones(1 << 26, dtype=torch.complex128, device="cuda:0")
@@ -720,41 +724,56 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    def solve(o, u):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = mxp.mxp_solve(P, o, fd, u)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
+    # warm-up: both forms, so that tiles, schedules and workspaces of each are
+    # set up before the timed steps
     for w in range(args.warmup):
-        ud.zero_()
-        st = mxp.mxp_solve(P, o_mixed, fd, ud)
-        print(f"[bench] warmup {w}: {st}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
+        for label, o, u in (("fp64", o64, u64), ("mixed", o_mixed, u32)):
+            sec, st = solve(o, u)
+            print(f"[bench] warmup {w} {label}: {sec:.3f} s {st}", file=sys.stderr, flush=True)
+    # timed steps: a double solve (the step) and, alternating with it, the mixed
+    # form; each solve is bracketed by device synchronisation
+    t64, t32, st64, st32 = [], [], None, None
+    t_begin = time.perf_counter()
     for k in range(args.steps):
-        ud.zero_()
-        st = mxp.mxp_solve(P, o_mixed, fd, ud)
-        stats.append(st)
-        print(f"[bench] step {k}: {st}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    s_per_solve = elapsed / max(args.steps, 1)
-    st = stats[-1] if stats else None
+        sec, st64 = solve(o64, u64)
+        t64.append(sec)
+        print(f"[bench] step {k} fp64: {sec:.3f} s {st64}", file=sys.stderr, flush=True)
+        if not args.no_mixed:
+            sec, st32 = solve(o_mixed, u32)
+            t32.append(sec)
+            print(f"[bench] step {k} mixed: {sec:.3f} s {st32}", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t_begin
+    s_per_solve = sum(t64) / max(len(t64), 1)
+    keys = ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions", "true_relres")
+    forms = {}
+    if t64:
+        forms["fp64"] = {"seconds_mean": round(s_per_solve, 4), "seconds_median": round(float(np.median(t64)), 4),
+                         **{k: st64[k] for k in keys}}
+    if t32:
+        m32 = sum(t32) / len(t32)
+        err = ((u32 - u64).norm() / u64.norm()).item()
+        forms["mixed"] = {"seconds_mean": round(m32, 4), "seconds_median": round(float(np.median(t32)), 4),
+                          "speedup_vs_fp64": round(s_per_solve / m32, 3), "rel_err_vs_fp64": err,
+                          "outer_its_minus_fp64": st32["outer_its"] - st64["outer_its"],
+                          "fp64_below": o_mixed.fp64_below, "fp64_its": st32["fp64_its"],
+                          **{k: st32[k] for k in keys}}
+    forms["learned"] = None  # the layered workloads only: `--workload 3d-learned`
 
-    fp64 = None
-    if not args.no_fp64:
-        o64 = P.default_opts()
-        o64.outer_restart = o_mixed.outer_restart
-        ud.zero_()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        st64 = mxp.mxp_solve(P, o64, fd, ud)
-        torch.cuda.synchronize()
-        fp64 = {"seconds": time.perf_counter() - t1, **{k: st64[k] for k in
-                ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions", "true_relres")}}
-        print(f"[bench] fp64: {fp64}", file=sys.stderr, flush=True)
-
-    roofline = measure_roofline(mxp, torch, P, prob, o_mixed, args.roofline_reps)
+    roofline = measure_roofline(mxp, torch, P, prob, o64, args.roofline_reps, mxp.MXP_PREC_FP64)
+    roofline_c64 = measure_roofline(mxp, torch, P, prob, o_mixed, args.roofline_reps, mxp.MXP_PREC_MIXED)
 
     cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(prob, f, int(st["fn_actions"]))
+    if not args.no_cpu and st64 is not None:
+        cpu = cpu_baseline(prob, f, int(st64["fn_actions"]))
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
     line = {
@@ -768,18 +787,19 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 stepping and inner basis + c128 Krylov sums and outer solve",
+        "dtype": "c128",
         "data": "synthetic (seeded GRF speed, point source)" if prob.c is not None
+                else "synthetic (constant speed, Gaussian-smoothed point source)" if prob.dim == 3
                 else "synthetic (constant speed, point source)",
         "config": {"workload": prob.name, "grid": list(prob.n), "omega": round(prob.omega, 3),
-                   "layer": prob.layer, "t": o_mixed.t, "shift": o_mixed.shift, "fprtol": o_mixed.fprtol,
-                   "rtol": o_mixed.rtol, "outer_restart": o_mixed.outer_restart,
-                   "inner_restart": o_mixed.inner_restart, "precision": "mixed",
+                   "layer": prob.layer, "t": o64.t, "shift": o64.shift, "fprtol": o64.fprtol,
+                   "rtol": o64.rtol, "outer_restart": o64.outer_restart,
+                   "inner_restart": o64.inner_restart, "precision": "fp64 (value); mixed beside it",
                    "graphs": bool(args.graphs)},
-        "solve": {k: st[k] for k in ("outer_its", "inner_mean", "inner_std", "stencil_steps", "fn_actions",
-                                     "true_relres")} if st else None,
-        "plain_fp64": fp64,
+        "forms": forms,
+        "timed_wall_s": round(wall, 2),
         "roofline": roofline,
+        "roofline_c64": roofline_c64,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -81,10 +81,40 @@ typedef struct mxp_problem mxp_problem;
 
 /* ---------------------------------------------------------------- context */
 
+/* Device-memory hooks.  alloc returns `bytes` of device memory on the
+ * context's device (NULL on failure, which the library reports as OOM);
+ * release gives back a pointer alloc returned.  `user` is passed through.
+ * The library calls them from the calling thread, or from the worker
+ * threads of mxp_solve_batch, and only for memory whose device work has
+ * completed when it is released (every call is synchronous on return), so a
+ * stream-ordered caching allocator such as PyTorch's may recycle it at once. */
+typedef void* (*mxp_alloc_fn)(size_t bytes, void* user);
+typedef void (*mxp_free_fn)(void* ptr, void* user);
+
 /* Binds `device` and borrows `hip_stream` (a hipStream_t, or NULL for the
- * null stream) for all later work.  *out receives the context.
- * Errors: INVALID_ARG (no such device, out == NULL), HIP. */
-mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out);
+ * null stream) for all later work.  Every device buffer the library keeps
+ * (problem tables, solver workspaces, network state) is taken through
+ * alloc / release, both NULL for hipMalloc / hipFree; the two must be given
+ * together.  A call reserves what it needs when it starts (problem set-up at
+ * mxp_problem_create, workspaces at the entry of a solve, an action or a
+ * preconditioner apply), never in the middle of its device work; buffers are
+ * kept with the problem for later calls and released by the destroy calls.
+ * The hooks and `user` must stay valid until every problem and network made
+ * on the context is destroyed.  *out receives the context.
+ * Errors: INVALID_ARG (no such device, out == NULL, only one hook), HIP. */
+mxp_status mxp_context_create(int device, void* hip_stream, mxp_alloc_fn alloc, mxp_free_fn release,
+                              void* user, mxp_context** out);
+
+/* Device allocations made through a context and the problems and networks
+ * created on it: calls of alloc and release, bytes held now and at most, and
+ * `late`, the allocations a call made after it had reserved its workspace
+ * (zero unless a buffer was missed by the reservation). */
+typedef struct {
+    int64_t allocs, frees;
+    int64_t bytes_live, bytes_peak;
+    int64_t late;
+} mxp_alloc_stats;
+mxp_status mxp_context_alloc_stats(const mxp_context* ctx, mxp_alloc_stats* out);
 
 /* Frees the context.  Problems created on it must be destroyed first. */
 void mxp_context_destroy(mxp_context* ctx);
@@ -174,6 +204,15 @@ typedef struct {
                                  the second inverse formula of Section 3.1;
                                3 its fixed-point iteration w <- psi_1(i t A_s) w + psi_2 r, the
                                  time-averaged map of Section 2.2, Theorem 2.2. */
+    double fp64_below;      /* MXP_PREC_MIXED only, in [0, 1): outer iterations that start with
+                               the residual estimate below fp64_below * ||f|| run the
+                               preconditioner's matrix-function actions in complex double
+                               (the inner basis stays complex float).  0 = never. */
+    int32_t fp64_first;     /* MXP_PREC_MIXED only, >= 0: the first fp64_first outer iterations
+                               of the solve run the preconditioner's actions in complex double.
+                               Complex-float stepping noise in z_j enters the iterate with z_j's
+                               FGMRES coefficient, which is largest for the first directions.
+                               0 = complex float throughout. */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per
@@ -195,6 +234,7 @@ typedef struct {
     int32_t status;           /* this solve's outcome (mxp_status)                */
     int32_t learned_its;      /* outer iterations preconditioned by the network   */
     int32_t fallbacks;        /* network tries rejected (MatExPre used instead)   */
+    int32_t fp64_its;         /* mixed form: outer iterations with actions in double */
 } mxp_solve_stats;
 
 /* --------------------------------------------------------------- schedule */
@@ -270,12 +310,14 @@ mxp_status mxp_apply_fn_krylov(mxp_problem* prob, int32_t psi, double t, double 
 
 /* w = M(r), Algorithm 1 (Section 3.4): psi_1 action, then GMRES from w = 0 on
  * (I - exp(i t A_s)) w = psi_1(i t A_s) r until the residual estimate is
- * <= fprtol * ||psi_1(i t A_s) r||.  r and w are complex double; with
- * MXP_PREC_MIXED the matrix-function actions and the inner basis are complex float.
- * opts->inner_solver selects the inner system and solver (the psi_2 form
- * returns w ~ (I - psi_1(i t A_s))^{-1} psi_2(i t A_s) r).
+ * <= fprtol * ||psi_1(i t A_s) r||.  r and w are vectors of dtype (MXP_C128 or
+ * MXP_C64); the inner GMRES sums and Hessenberg matrix are complex double
+ * either way (complex-float vectors are widened on entry and w is rounded on
+ * return).  With MXP_PREC_MIXED the matrix-function actions and the inner
+ * basis are complex float.  opts->inner_solver selects the inner system and
+ * solver (the psi_2 form returns w ~ (I - psi_1(i t A_s))^{-1} psi_2(i t A_s) r).
  * *inner_its (may be NULL) receives the inner iteration count. */
-mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r,
+mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, mxp_dtype dtype, const void* r,
                              void* w, int32_t* inner_its);
 
 /* ------------------------------------------------------------ tiling */
@@ -291,7 +333,8 @@ mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, cons
  * precision selects the complex-double (MXP_PREC_FP64) or complex-float
  * (MXP_PREC_MIXED) kernels.  On 3D grids K = 2 selects passes of two
  * Clenshaw levels (k_cheb3d) and any other value single-level z-marching
- * sweeps, the default (measured faster at 256^3); NX and Ly are unused there.
+ * sweeps, the default (measured faster at 256^3); K = 1 fixes the sweeps'
+ * z segments to Ly planes (K = 0: chosen from the grid); NX is unused there.
  * Errors: INVALID_ARG. */
 mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, int32_t NX, int32_t Ly);
 mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32_t* K, int32_t* NX,
@@ -300,12 +343,15 @@ mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32
 /* ------------------------------------------------------------------ solve */
 
 /* Solves A u = -f by FGMRES(outer_restart) preconditioned by Algorithm 1
- * (Section 3.4).  f and u are complex double device vectors; u is read as the
- * initial guess (zero it for the plain solve) and overwritten.  Stops when the
- * true residual ||-f - A u|| <= rtol ||f||; the outer Krylov basis, Hessenberg
- * matrix and true residual are always complex double.  stats may be NULL.
+ * (Section 3.4).  f and u are device vectors of dtype (MXP_C128, or MXP_C64
+ * for complex-float data); u is read as the initial guess (zero it for the
+ * plain solve) and overwritten.  Stops when the true residual
+ * ||-f - A u|| <= rtol ||f||.  The outer Krylov basis, Hessenberg matrix,
+ * iterate and true residual are always complex double: complex-float f and
+ * u are widened on entry and u is rounded once on return (stats then report
+ * the residual of the double iterate).  stats may be NULL.
  * Returns OK, NOT_CONVERGED (max_outer reached), or an error. */
-mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
+mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, mxp_dtype dtype, const void* f, void* u,
                      mxp_solve_stats* stats);
 
 /* Per-outer-iteration record of the last single solve on the problem
@@ -380,6 +426,13 @@ mxp_status mxp_cnn_forward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int
  * read them with mxp_cnn_get_grads. */
 mxp_status mxp_cnn_backward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
                             const float* gout);
+/* Copies the stored activations of hidden layer `layer` (1..5, after its
+ * ReLU) from the last mxp_cnn_backward or mxp_cnn_train_step to host memory:
+ * bf16 bits [voxel][32], `voxels` = nb*nz*ny*nx of that call.  The data
+ * gradient of that call masked layer `layer` by (activation > 0).
+ * Errors: INVALID_ARG (layer out of range, voxels not those of the last
+ * training-shape call), HIP. */
+mxp_status mxp_cnn_get_activations(const mxp_cnn* net, int32_t layer, int64_t voxels, uint16_t* host);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error
  * of network(in) against target (float [voxel][2]); *loss (host, may be NULL)
  * receives the loss before the step.  Errors: INVALID_ARG, NONFINITE, HIP. */

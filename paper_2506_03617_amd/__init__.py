@@ -73,6 +73,8 @@ class mxp_solve_opts(ctypes.Structure):
         ("stall_ratio", ctypes.c_double),
         ("use_graphs", ctypes.c_int32),
         ("inner_solver", ctypes.c_int32),
+        ("fp64_below", ctypes.c_double),
+        ("fp64_first", ctypes.c_int32),
     ]
 
 
@@ -90,10 +92,29 @@ class mxp_solve_stats(ctypes.Structure):
         ("status", ctypes.c_int32),
         ("learned_its", ctypes.c_int32),
         ("fallbacks", ctypes.c_int32),
+        ("fp64_its", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class mxp_alloc_stats(ctypes.Structure):
+    _fields_ = [
+        ("allocs", ctypes.c_int64),
+        ("frees", ctypes.c_int64),
+        ("bytes_live", ctypes.c_int64),
+        ("bytes_peak", ctypes.c_int64),
+        ("late", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# device-memory hooks of mxp_context_create
+MXP_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+MXP_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class mxp_schedule(ctypes.Structure):
@@ -122,13 +143,13 @@ class mxp_schedule(ctypes.Structure):
 
 # C-ABI symbols declared in include/matexpre.h
 ABI_SYMBOLS = (
-    "mxp_context_create", "mxp_context_destroy", "mxp_last_error", "mxp_version",
+    "mxp_context_create", "mxp_context_destroy", "mxp_context_alloc_stats", "mxp_last_error", "mxp_version",
     "mxp_problem_create", "mxp_problem_destroy", "mxp_problem_size",
     "mxp_solve_opts_default", "mxp_design_schedule",
     "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_psi2", "mxp_apply_fn_krylov", "mxp_apply_precond", "mxp_solve",
     "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
     "mxp_cnn_num_params", "mxp_cnn_create", "mxp_cnn_destroy", "mxp_cnn_get_params", "mxp_cnn_set_params",
-    "mxp_cnn_get_grads", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
+    "mxp_cnn_get_grads", "mxp_cnn_get_activations", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
     "mxp_collect_pairs", "mxp_problem_set_learned", "mxp_cnn_save", "mxp_cnn_load", "mxp_solve_history",
 )
 
@@ -144,7 +165,8 @@ def _load():
     P = ctypes.c_void_p
     st = ctypes.c_int
     sig = {
-        "mxp_context_create": (st, [ctypes.c_int, P, ctypes.POINTER(P)]),
+        "mxp_context_create": (st, [ctypes.c_int, P, MXP_ALLOC_FN, MXP_FREE_FN, P, ctypes.POINTER(P)]),
+        "mxp_context_alloc_stats": (st, [P, ctypes.POINTER(mxp_alloc_stats)]),
         "mxp_context_destroy": (None, [P]),
         "mxp_last_error": (ctypes.c_char_p, []),
         "mxp_version": (ctypes.c_char_p, []),
@@ -160,8 +182,9 @@ def _load():
         "mxp_apply_psi2": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_fn_krylov": (st, [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int32, P, P, ctypes.POINTER(ctypes.c_int32)]),
-        "mxp_apply_precond": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(ctypes.c_int32)]),
-        "mxp_solve": (st, [P, ctypes.POINTER(mxp_solve_opts), P, P, ctypes.POINTER(mxp_solve_stats)]),
+        "mxp_apply_precond": (st, [P, ctypes.POINTER(mxp_solve_opts), ctypes.c_int, P, P,
+                                   ctypes.POINTER(ctypes.c_int32)]),
+        "mxp_solve": (st, [P, ctypes.POINTER(mxp_solve_opts), ctypes.c_int, P, P, ctypes.POINTER(mxp_solve_stats)]),
         "mxp_set_tiles": (st, [P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "mxp_get_tiles": (st, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
@@ -174,6 +197,7 @@ def _load():
         "mxp_cnn_get_params": (st, [P, P]),
         "mxp_cnn_set_params": (st, [P, P]),
         "mxp_cnn_get_grads": (st, [P, P]),
+        "mxp_cnn_get_activations": (st, [P, ctypes.c_int32, ctypes.c_int64, P]),
         "mxp_cnn_save": (st, [P, ctypes.c_char_p]),
         "mxp_cnn_load": (st, [P, ctypes.c_char_p]),
         "mxp_cnn_forward": (st, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]),
@@ -283,19 +307,66 @@ def _close_all():
         obj.close()
 
 
-class Context:
-    """mxp_context bound to a CUDA/HIP device and (by default) torch's current stream."""
+class TorchAllocator:
+    """mxp_context_create hooks backed by PyTorch's caching allocator: the
+    library's workspaces come from the same pool as torch tensors, on the
+    context's device and stream."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int, stream):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.stream = stream
+        self.alloc = MXP_ALLOC_FN(self._alloc)
+        self.free = MXP_FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            return self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:  # out of memory: the library reports MXP_ERR_OOM
+            return None
+
+    def _free(self, ptr, user):
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+
+# Hooks stay alive for the whole process: problems and networks may outlive
+# the Context object that made them.
+_HOOKS = []
+
+
+class Context:
+    """mxp_context bound to a CUDA/HIP device and (by default) torch's current
+    stream.  allocator: "torch" (default) takes the library's device memory
+    from PyTorch's caching allocator, "hip" from hipMalloc, or pass an object
+    with `alloc` / `free` attributes of types MXP_ALLOC_FN / MXP_FREE_FN."""
+
+    def __init__(self, device: int = 0, stream=None, allocator="torch"):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self._stream = stream
+        if allocator == "torch":
+            allocator = TorchAllocator(device, stream)
+        if allocator == "hip":
+            self.allocator = None
+            alloc, free = MXP_ALLOC_FN(), MXP_FREE_FN()
+        else:
+            self.allocator = allocator
+            alloc, free = allocator.alloc, allocator.free
+            _HOOKS.append(allocator)
         handle = ctypes.c_void_p()
-        _check(lib.mxp_context_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(handle)))
+        _check(lib.mxp_context_create(device, ctypes.c_void_p(stream.cuda_stream), alloc, free, None,
+                                      ctypes.byref(handle)))
         self.handle = handle
         self.device = device
         _LIVE_CONTEXTS.add(self)
+
+    def alloc_stats(self) -> dict:
+        """Device allocations through this context (mxp_context_alloc_stats)."""
+        out = mxp_alloc_stats()
+        _check(lib.mxp_context_alloc_stats(self.handle, ctypes.byref(out)))
+        return out.as_dict()
 
     def close(self):
         if self.handle:
@@ -367,15 +438,24 @@ def mxp_apply_fn_krylov(prob: Problem, psi: bool, t: float, shift: float, tol: f
     return _check(st, allow_not_converged=True), dim.value
 
 
+def _same_dtype(a, b) -> int:
+    dt = _dtype_of(a)
+    if _dtype_of(b) != dt:
+        raise TypeError("both vectors must have the same dtype")
+    return dt
+
+
 def mxp_apply_precond(prob: Problem, opts: mxp_solve_opts, r, w) -> int:
     its = ctypes.c_int32(0)
-    _check(lib.mxp_apply_precond(prob.handle, ctypes.byref(opts), _ptr(r), _ptr(w), ctypes.byref(its)))
+    _check(lib.mxp_apply_precond(prob.handle, ctypes.byref(opts), _same_dtype(r, w), _ptr(r), _ptr(w),
+                                 ctypes.byref(its)))
     return its.value
 
 
 def mxp_solve(prob: Problem, opts: mxp_solve_opts, f, u) -> dict:
     st = mxp_solve_stats()
-    status = _check(lib.mxp_solve(prob.handle, ctypes.byref(opts), _ptr(f), _ptr(u), ctypes.byref(st)),
+    status = _check(lib.mxp_solve(prob.handle, ctypes.byref(opts), _same_dtype(f, u), _ptr(f), _ptr(u),
+                                  ctypes.byref(st)),
                     allow_not_converged=True)
     out = st.as_dict()
     out["status"] = status
@@ -435,6 +515,13 @@ class Network:
     def get_grads(self) -> np.ndarray:
         a = np.empty(self.num_params(), dtype=np.float32)
         _check(lib.mxp_cnn_get_grads(self.handle, a.ctypes.data))
+        return a
+
+    def get_activations(self, layer: int, voxels: int) -> np.ndarray:
+        """bf16 bits [voxels, 32] of hidden layer `layer` (1..5) from the last
+        backward or training step."""
+        a = np.empty((voxels, 32), dtype=np.uint16)
+        _check(lib.mxp_cnn_get_activations(self.handle, layer, voxels, a.ctypes.data))
         return a
 
     def save(self, path) -> None:

@@ -148,6 +148,9 @@ static StencilArgs<R> base_args(mxp_problem* P, double shift, const DiagTables& 
         a.Dconst = R(0);
     }
     a.Dref = R(P->Dref);
+    // 3D sweeps: z segment length fixed by mxp_set_tiles (K = 1), else chosen per grid
+    const TileCfg& tc = P->tiles[sizeof(R) == 4 ? 1 : 0];
+    a.zc = (g.dim == 3 && tc.K == 1) ? tc.Ly : 0;
     const double w2 = g.omega * g.omega;
     a.kD = {R(w2), R(w2 * shift)};
     a.g = {R(1), R(0)};
@@ -653,6 +656,26 @@ void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x
 
 // f(i t A_s) x with f = exp or psi_1 from one Arnoldi basis, the route the
 // paper takes for its matrix functions (a Krylov method, Section 4
+
+void reserve_action(mxp_problem* P, Workspace& ws, const Sched& sd, bool psi2, bool graphs, hipStream_t s) {
+    const size_t n = size_t(npts(P));
+    if (sd.prec == MXP_PREC_FP64) {
+        // [0..5] pass and substep buffers, [6] the psi addend, [7..8] graph
+        // staging, [9] the psi_2 action's first-substep term
+        for (int q = 0; q < 7; ++q) ws.act64[q].ensure(n * sizeof(cpx<double>));
+        if (graphs) {
+            ws.act64[7].ensure(n * sizeof(cpx<double>));
+            ws.act64[8].ensure(n * sizeof(cpx<double>));
+        }
+        if (psi2) ws.act64[9].ensure(n * sizeof(cpx<double>));
+    } else {
+        // as above, with [7..8] the casts of complex-double arguments
+        for (int q = 0; q < 9; ++q) ws.act32[q].ensure(n * sizeof(cpx<float>));
+        if (psi2) ws.act32[9].ensure(n * sizeof(cpx<float>));
+    }
+    if (psi2 && sd.m_psi2 < 0) design_psi2_series(sd.s, sd.t, sd.prec, &sd.coef_psi2, &sd.m_psi2);
+    ensure_tiles(P, ws, sd, s);
+}
 
 void ensure_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s) {
     if (P->g.dim != 2) return;

@@ -13,6 +13,8 @@
 namespace mxp {
 
 thread_local std::string g_last_error;
+thread_local const Allocator* t_alloc = nullptr;
+thread_local bool t_reserved = false;
 
 template <typename R>
 static void upload_tables(mxp_problem* P, DevMem& mem, DevTables<R>& t) {
@@ -56,6 +58,8 @@ void context_info(const mxp_context* ctx, int* device, hipStream_t* stream) {
     *stream = ctx->stream;
 }
 
+const Allocator& context_alloc(const mxp_context* ctx) { return ctx->alloc; }
+
 }  // namespace mxp
 
 using namespace mxp;
@@ -66,10 +70,13 @@ const char* mxp_last_error(void) { return g_last_error.c_str(); }
 
 const char* mxp_version(void) { return "matexpre-mi355x 0.1.0 (gfx950)"; }
 
-mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out) {
+mxp_status mxp_context_create(int device, void* hip_stream, mxp_alloc_fn alloc, mxp_free_fn release, void* user,
+                              mxp_context** out) {
     return guard([&]() {
         if (!out) fail(MXP_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
+        if ((alloc == nullptr) != (release == nullptr))
+            fail(MXP_ERR_INVALID_ARG, "alloc and release hooks must be given together");
         int count = 0;
         const hipError_t ce = hipGetDeviceCount(&count);
         if (ce != hipSuccess || count <= 0) {
@@ -80,7 +87,8 @@ mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out) {
         if (device < 0 || device >= count) fail(MXP_ERR_INVALID_ARG, "no such device");
         HIP_CHECK(hipSetDevice(device));
         const char* v = std::getenv("MXP_VERBOSE");
-        auto* c = new mxp_context{device, static_cast<hipStream_t>(hip_stream), (v && *v && *v != '0') ? 1 : 0};
+        auto* c = new mxp_context{device, static_cast<hipStream_t>(hip_stream), (v && *v && *v != '0') ? 1 : 0,
+                                  Allocator{alloc, release, user, std::make_shared<AllocStats>()}};
         *out = c;
         return MXP_OK;
     });
@@ -88,12 +96,26 @@ mxp_status mxp_context_create(int device, void* hip_stream, mxp_context** out) {
 
 void mxp_context_destroy(mxp_context* ctx) { delete ctx; }
 
+mxp_status mxp_context_alloc_stats(const mxp_context* ctx, mxp_alloc_stats* out) {
+    return guard([&]() {
+        if (!ctx || !out) fail(MXP_ERR_INVALID_ARG, "context or out is NULL");
+        const AllocStats& a = *ctx->alloc.stats;
+        out->allocs = a.allocs.load();
+        out->frees = a.frees.load();
+        out->bytes_live = a.live.load();
+        out->bytes_peak = a.peak.load();
+        out->late = a.late.load();
+        return MXP_OK;
+    });
+}
+
 mxp_status mxp_problem_create(mxp_context* ctx, const mxp_grid_desc* desc, mxp_problem** out) {
     return guard([&]() {
         if (!ctx || !out) fail(MXP_ERR_INVALID_ARG, "context or out is NULL");
         *out = nullptr;
         GridInfo g = validate_grid(desc);
         use_device(ctx);
+        AllocScope scope(ctx->alloc);
         auto P = std::make_unique<mxp_problem>();
         P->ctx_copy = *ctx;
         P->ctx = &P->ctx_copy;
@@ -175,6 +197,8 @@ mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out
         out->stall_ratio = 0.0;
         out->use_graphs = 0;
         out->inner_solver = 0;
+        out->fp64_below = 0.0;
+        out->fp64_first = 0;
         return MXP_OK;
     });
 }
@@ -196,6 +220,7 @@ mxp_status mxp_design_schedule(const mxp_grid_desc* desc, double t, double shift
 mxp_status mxp_apply_A(mxp_problem* prob, double shift, mxp_dtype dtype, const void* x, void* y) {
     return guard([&]() {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
         if (!(shift >= 0) || !std::isfinite(shift)) fail(MXP_ERR_INVALID_ARG, "shift must be >= 0");
         apply_A(prob, prob->ctx->stream, shift, dtype, x, y);
@@ -208,10 +233,13 @@ static mxp_status apply_fn(mxp_problem* prob, double t, double shift, mxp_dtype 
                            void* y, int fn) {
     return guard([&]() {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
         int64_t steps = 0;
         if (dtype != MXP_C128 && dtype != MXP_C64) fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
         const Sched& sc = get_sched(prob, t, shift, dtype == MXP_C128 ? MXP_PREC_FP64 : MXP_PREC_MIXED, 0, 0);
+        reserve_action(prob, prob->ws, sc, fn == ACT_PSI2, false, prob->ctx->stream);
+        t_reserved = true;
         apply_action(prob, prob->ws, prob->ctx->stream, sc, t, shift, fn, dtype, x, y, &steps);
         HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
         return MXP_OK;
@@ -237,6 +265,7 @@ mxp_status mxp_apply_fn_krylov(mxp_problem* prob, int32_t psi, double t, double 
                                int32_t max_dim, const void* x, void* y, int32_t* dim) {
     return guard([&]() {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         if (!x || !y || x == y) fail(MXP_ERR_INVALID_ARG, "x and y must be distinct non-NULL pointers");
         if (psi != 0 && psi != 1) fail(MXP_ERR_INVALID_ARG, "psi must be 0 (exp) or 1 (psi_1)");
         if (!(t > 0) || !std::isfinite(t)) fail(MXP_ERR_INVALID_ARG, "t must be positive and finite");
@@ -254,16 +283,33 @@ mxp_status mxp_apply_fn_krylov(mxp_problem* prob, int32_t psi, double t, double 
     });
 }
 
-mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, const void* r, void* w,
+mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, mxp_dtype dtype, const void* r, void* w,
                              int32_t* inner_its) {
     return guard([&]() {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         check_opts(opts);
         if (!r || !w || r == w) fail(MXP_ERR_INVALID_ARG, "r and w must be distinct non-NULL pointers");
+        if (dtype != MXP_C128 && dtype != MXP_C64) fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
         Counters cnt;
         Run run{prob, &prob->ws, prob->ctx->stream, nullptr, nullptr};
-        const int its = precond(run, *opts, static_cast<const cpx<double>*>(r), static_cast<cpx<double>*>(w), cnt);
-        HIP_CHECK(hipStreamSynchronize(prob->ctx->stream));
+        run.graphs = opts->use_graphs != 0;
+        const int64_t n = npts(prob);
+        hipStream_t s = prob->ctx->stream;
+        const cpx<double>* r64 = static_cast<const cpx<double>*>(r);
+        cpx<double>* w64 = static_cast<cpx<double>*>(w);
+        if (dtype == MXP_C64) {  // complex-double copies of the complex-float arguments
+            prob->ws.io[0].ensure(size_t(n) * sizeof(cpx<double>));
+            prob->ws.io[1].ensure(size_t(n) * sizeof(cpx<double>));
+            r64 = prob->ws.io[0].as<cpx<double>>();
+            w64 = prob->ws.io[1].as<cpx<double>>();
+        }
+        reserve_precond(run, *opts);
+        t_reserved = true;
+        if (dtype == MXP_C64) launch_to_c128(static_cast<const cpx<float>*>(r), prob->ws.io[0].as<cpx<double>>(), n, s);
+        const int its = precond(run, *opts, r64, w64, cnt, opts->precision);
+        if (dtype == MXP_C64) launch_to_c64(w64, static_cast<cpx<float>*>(w), n, s);
+        HIP_CHECK(hipStreamSynchronize(s));
         if (inner_its) *inner_its = its;
         return MXP_OK;
     });
@@ -300,21 +346,37 @@ mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32
     });
 }
 
-mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, const void* f, void* u,
+mxp_status mxp_solve(mxp_problem* prob, const mxp_solve_opts* opts, mxp_dtype dtype, const void* f, void* u,
                      mxp_solve_stats* stats) {
-    return guard([&]() {
+    return guard([&]() -> mxp_status {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         check_opts(opts);
         if (!f || !u || f == u) fail(MXP_ERR_INVALID_ARG, "f and u must be distinct non-NULL pointers");
+        if (dtype != MXP_C128 && dtype != MXP_C64) fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
         Run run{prob, &prob->ws, prob->ctx->stream, nullptr, nullptr};
-        return solve(run, *opts, static_cast<const cpx<double>*>(f), static_cast<cpx<double>*>(u), stats);
+        if (dtype == MXP_C128)
+            return solve(run, *opts, static_cast<const cpx<double>*>(f), static_cast<cpx<double>*>(u), stats);
+        // complex-float data: the solve runs on complex-double copies
+        const int64_t n = npts(prob);
+        hipStream_t s = prob->ctx->stream;
+        prob->ws.io[0].ensure(size_t(n) * sizeof(cpx<double>));
+        prob->ws.io[1].ensure(size_t(n) * sizeof(cpx<double>));
+        cpx<double>* f64 = prob->ws.io[0].as<cpx<double>>();
+        cpx<double>* u64 = prob->ws.io[1].as<cpx<double>>();
+        launch_to_c128(static_cast<const cpx<float>*>(f), f64, n, s);
+        launch_to_c128(static_cast<const cpx<float>*>(u), u64, n, s);
+        const mxp_status st = solve(run, *opts, f64, u64, stats);
+        launch_to_c64(u64, static_cast<cpx<float>*>(u), n, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        return st;
     });
 }
-
 
 mxp_status mxp_problem_set_learned(mxp_problem* prob, mxp_cnn* net, double out_scale) {
     return guard([&]() {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         if (net && !(out_scale > 0 && std::isfinite(out_scale)))
             fail(MXP_ERR_INVALID_ARG, "out_scale must be positive");
         prob->net = net;
@@ -328,6 +390,7 @@ mxp_status mxp_collect_pairs(mxp_problem* prob, const mxp_solve_opts* opts, cons
                              int32_t* npairs, mxp_solve_stats* stats) {
     return guard([&]() {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         check_opts(opts);
         if (!f || !u || f == u) fail(MXP_ERR_INVALID_ARG, "f and u must be distinct non-NULL pointers");
         if (max_pairs < 0 || (max_pairs > 0 && (!r_out || !z_out || !rnorm || !znorm)))
@@ -345,6 +408,7 @@ mxp_status mxp_cnn_make_sample(mxp_problem* prob, const void* r, const void* z, 
                                const int32_t crop[3], double rscale, double zscale, void* in, float* target) {
     return guard([&]() {
         check_problem(prob);
+        AllocScope scope(prob->ctx->alloc);
         if (!r || !z || !offset || !crop || !in || !target) fail(MXP_ERR_INVALID_ARG, "NULL argument");
         for (int d = 0; d < 3; ++d)
             if (crop[d] < 1 || offset[d] < 0 || offset[d] + crop[d] > prob->g.n[d])

@@ -73,6 +73,9 @@ class Batcher {
         if (r.failed) fail(r.status, r.msg);
     }
     int64_t launches() const { return launches_; }
+    // Device room for the job tables of one lockstep action, taken before
+    // the solves start (a larger action grows it, counted as late).
+    void reserve(size_t bytes) { table_.ensure(bytes); }
 
   private:
     void maybe_run(std::unique_lock<std::mutex>& lk) {
@@ -153,7 +156,7 @@ class Batcher {
         for (size_t q = 0; q < sw.size(); ++q) {
             jobs[q].a = *sw[q];
             jobs[q].geom = sweep3d_geometry(*sw[q]);
-            jobs[q].blocks = int64_t(jobs[q].geom.tiles_x) * jobs[q].geom.tiles_y * jobs[q].geom.zchunks;
+            jobs[q].blocks = jobs[q].geom.blocks;
         }
         add_table(buf, g, jobs);
     }
@@ -321,6 +324,7 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             fail(MXP_ERR_INVALID_ARG, "batch: context, problem, rhs and option arrays must be given");
         if (max_resident < 0) fail(MXP_ERR_INVALID_ARG, "max_resident must be >= 0");
         use_device(ctx);
+        AllocScope scope(ctx->alloc);
         struct Item {
             mxp_problem* P;
             const mxp_solve_opts* o;
@@ -329,6 +333,7 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             size_t bytes;
         };
         std::vector<Item> items;
+        size_t table_steps = 0, table_per_rhs = 0;
         for (int q = 0; q < nprob; ++q) {
             mxp_problem* P = problems[q];
             if (!P) fail(MXP_ERR_INVALID_ARG, "batch: problem is NULL");
@@ -345,6 +350,8 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             size_t bytes = vec * (size_t(2 * o.outer_restart + 2) + size_t(o.inner_restart + 4));
             bytes += o.precision == MXP_PREC_FP64 ? 7 * vec : 9 * vec / 2;
             if (o.inner_solver >= 2) bytes += o.precision == MXP_PREC_FP64 ? vec : vec / 2;  // psi_2's y_1
+            const bool switches = o.precision == MXP_PREC_MIXED && (o.fp64_below > 0 || o.fp64_first > 0);
+            if (switches) bytes += (o.inner_solver >= 2 ? 8 : 7) * vec;  // the double actions' buffers
             bytes += size_t(reduce_blocks(n)) * 256 * sizeof(cpx<double>) + (1 << 20);
             // set up once, outside the threads: schedules, diagonal tables and
             // 2D tiles are shared read-only by every right-hand side of P
@@ -353,9 +360,27 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
                 design_psi2_series(sd.s, sd.t, sd.prec, &sd.coef_psi2, &sd.m_psi2);
             (void)plain_diag(P, 0.0);
             ensure_tiles(P, P->ws, sd, P->ctx->stream);
+            if (switches) {  // the double schedule the late outer iterations switch to
+                const Sched& s64 = get_sched(P, o.t, o.shift, MXP_PREC_FP64, o.cheb_S, o.cheb_m);
+                if (o.inner_solver >= 2 && s64.m_psi2 < 0)
+                    design_psi2_series(s64.s, s64.t, s64.prec, &s64.coef_psi2, &s64.m_psi2);
+                ensure_tiles(P, P->ws, s64, P->ctx->stream);
+            }
             for (int r = 0; r < nrhs[q]; ++r)
                 items.push_back({P, &o, static_cast<const cpx<double>*>(f[q]) + size_t(r) * n,
                                  static_cast<cpx<double>*>(u[q]) + size_t(r) * n, bytes});
+            if (P->g.dim == 3) {
+                // job-table bytes per right-hand side and step: the job, two
+                // alignments and one lookup entry per 64 workgroups (tiles no
+                // smaller than 62 x 4 nodes, z segments of at least 8 planes)
+                const int mmax = std::max(std::max(sd.s.m, sd.s.m_psi), std::max(sd.m_psi2, 0));
+                const size_t steps = size_t(sd.s.S + 2) * size_t(mmax + 1);
+                const int64_t blocks = ((P->g.n[0] + 61) / 62) * ((P->g.n[1] + 3) / 4) * ((P->g.n[2] + 7) / 8);
+                const size_t per = sizeof(Cheb3DJob<double>) + sizeof(Sweep3DJob<double>) + 1024 +
+                                   4 * size_t(blocks / 64 + 1);
+                table_steps = std::max(table_steps, steps);
+                table_per_rhs = std::max(table_per_rhs, per);
+            }
         }
         HIP_CHECK(hipStreamSynchronize(ctx->stream));
         size_t free_b = 0, total_b = 0;
@@ -364,6 +389,10 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
         const int cap = max_resident > 0 ? max_resident : int(items.size());
 
         Batcher B(ctx->device, ctx->stream);
+        if (table_steps > 0) {
+            const size_t resident = std::min(size_t(cap), items.size());
+            B.reserve(std::min(table_steps * table_per_rhs * resident, size_t(64) << 20));
+        }
         std::mutex mu;
         std::condition_variable cv;
         int running = 0;
@@ -385,6 +414,7 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             threads.emplace_back([&, k, dev]() {
                 const Item& it = items[k];
                 try {
+                    AllocScope thread_scope(ctx->alloc);
                     HIP_CHECK(hipSetDevice(dev));
                     Workspace W;
                     hipStream_t s = nullptr;

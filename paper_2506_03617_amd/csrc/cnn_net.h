@@ -19,6 +19,7 @@ constexpr int kChannels[kLayers + 1] = {3, 32, 32, 32, 32, 32, 2};
 struct mxp_cnn {
     int device;
     hipStream_t stream;
+    mxp::Allocator alloc;  // the context's device-memory hooks
     // master parameters, gradients and Adam moments (float), flattened layer
     // by layer: W [cout][cin][27] then b [cout]
     mxp::DevMem params, grads, adam_m, adam_v;
@@ -28,6 +29,7 @@ struct mxp_cnn {
     bool packed = false;
     // activation workspace (voxels of the last shape used)
     mxp::DevMem act[mxp::kLayers];  // act[1..5]: bf16 [V][32]; act[0] unused (the input is the caller's)
+    int64_t kept_voxels = 0;        // V of the last forward that kept every activation
     mxp::DevMem out;                // float [V][2]
     mxp::DevMem g6, gA, gB;         // bf16 gradients
     mxp::DevMem wpart, bpart, lpart, lsum;
@@ -36,8 +38,11 @@ struct mxp_cnn {
 
 namespace mxp {
 
-// Device and stream of a context (defined with the context).
+// Device, stream and allocator of a context (defined with the context).
 void context_info(const mxp_context* ctx, int* device, hipStream_t* stream);
+const Allocator& context_alloc(const mxp_context* ctx);
+// Reserves the network's inference buffers for volumes of `s`.
+void cnn_reserve(mxp_cnn* net, const ConvShape& s, hipStream_t st);
 
 // Network forward; with keep = true every activation is kept for backward,
 // else two buffers alternate.  in: bf16 [V][8] device; out: float [V][2], or

@@ -25,7 +25,8 @@
 struct mxp_context {
     int device;
     hipStream_t stream;
-    int verbose;  // MXP_VERBOSE=1: one line per outer iteration on stderr
+    int verbose;           // MXP_VERBOSE=1: one line per outer iteration on stderr
+    mxp::Allocator alloc;  // device memory of the context's problems and networks
 };
 
 namespace mxp {
@@ -93,6 +94,7 @@ struct Workspace {
     DevMem krylovV, krylovP;
     DevMem outerV, outerZ, outerR;
     DevMem partial, small;
+    DevMem io[2];  // complex-double copies of complex-float arguments
     std::vector<cpx<double>> host_small;
     // captured actions, keyed by (schedule, function, precision); the stream they
     // replay on and the events that order it with the solve's stream
@@ -173,6 +175,7 @@ inline int64_t npts(const mxp_problem* P) { return P->g.npts(); }
 struct Counters {
     int64_t steps = 0, actions = 0;
     int learned = 0, fallbacks = 0;
+    int fp64_its = 0;  // mixed form: outer iterations whose actions ran in double
 };
 
 template <typename R>
@@ -261,7 +264,15 @@ void action64(Run& run, const Sched& sc, double t, double shift, int fn, mxp_pre
 // ---------------------------------------------------------------- krylov.cpp
 
 void check_opts(const mxp_solve_opts* o);
-int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt);
+// Everything an action, a preconditioner apply or a solve with these options
+// allocates, taken at the entry of the call; afterwards the thread is marked
+// reserved, and a later allocation counts as late in the context's statistics.
+void reserve_action(mxp_problem* P, Workspace& ws, const Sched& sd, bool psi2, bool graphs, hipStream_t s);
+void reserve_precond(Run& run, const mxp_solve_opts& o);
+void reserve_solve(Run& run, const mxp_solve_opts& o);
+// Algorithm 1 with the matrix-function actions in precision ap.
+int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt,
+            mxp_precision ap);
 int krylov_action(Run& run, bool psi, double t, double shift, double tol, int max_dim, const cpx<double>* x,
                   cpx<double>* y, bool* ok);
 mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u, mxp_solve_stats* st);

@@ -46,14 +46,18 @@ struct StencilArgs {
     const cpx<R>* b2;
     const cpx<R>* b3;
     cpx<R>* out;
+    int zc;  // 3D sweeps: z segment length (0 = chosen from the grid)
 };
 
 template <typename R>
 void launch_stencil(const StencilArgs<R>& a, hipStream_t s);
 
-// Geometry of the 3D sweep: 64 x 4 column tiles, chunks of zc planes.
+// Geometry of the 3D sweep: tiles of 256 columns x `rows` rows, segments of
+// zc planes; `tiles` tiles launched as `blocks` workgroups (padded to a
+// multiple of eight for the XCD-aware tile order).
 struct Sweep3DGeom {
-    int tiles_x, tiles_y, zchunks, zc;
+    int tiles_x, tiles_y, zchunks, zc, rows;
+    int64_t tiles, blocks;
 };
 template <typename R>
 Sweep3DGeom sweep3d_geometry(const StencilArgs<R>& a);

@@ -36,6 +36,7 @@ __device__ __forceinline__ cpx<R> cscale(R s, cpx<R> a) {
 
 constexpr int kBX = 64;
 constexpr int kBY = 4;
+constexpr int kSweepW = 256;  // columns of a 3D sweep tile (four wavefronts)
 
 
 // 2D sweep: one work-item per node, 64 x 4 workgroups.
@@ -126,101 +127,194 @@ __device__ __forceinline__ T sload_words(const T* p) {
     return __builtin_bit_cast(T, w);
 }
 
-// 3D sweep marching along z.  A workgroup owns a 64 x 4 column tile and a
-// chunk of zc planes.  Each work-item carries v at planes k-1 and k in
-// registers and loads plane k+1, so v is fetched about once per chunk and
-// the x/y neighbours come from the caches.  The x/y weights are
-// loop-invariant: a ghost neighbour gets weight zero and a clamped offset (no
-// branch around a load); the z boundary and the z tables are uniform.  OPS
-// marks the operands present (1: x, 2: b2, 4: b3, 8: D), so absent ones cost
-// no load.  Measured on 256^3: 64 x 4 tiles with chunks of 16 planes in plain
-// workgroup order (taller tiles, 8-plane chunks and an XCD-contiguous
-// renumbering were as fast or slower: the halo rows are served by L1 and the
-// last-level cache, not a shared L2).
-// (at most four wavefronts per SIMD: with the default target of eight the
-// compiler serialises the complex-double loads to save registers)
-template <typename R, int OPS>
-__device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGeom& m, int tile) {
+// DPP wavefront shifts: lane l receives lane l-1 (from_below) or lane l+1
+// (from_above); with bound_ctrl set, lanes without a source read 0.
+__device__ __forceinline__ float dpp_f(float v, bool below) {
+    const int iv = __builtin_bit_cast(int, v);
+    const int r = below ? __builtin_amdgcn_mov_dpp(iv, 0x138, 0xf, 0xf, true)
+                        : __builtin_amdgcn_mov_dpp(iv, 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(float, r);
+}
+__device__ __forceinline__ double dpp_d(double v, bool below) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = int(b & 0xffffffffll), hi = int(b >> 32);
+    int rlo, rhi;
+    if (below) {
+        rlo = __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true);
+        rhi = __builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true);
+    } else {
+        rlo = __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true);
+        rhi = __builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true);
+    }
+    const long long r = (long long)(unsigned(rlo)) | ((long long)rhi << 32);
+    return __builtin_bit_cast(double, r);
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> from_below(cpx<R> v) {
+    if constexpr (sizeof(R) == 4) return {dpp_f(v.re, true), dpp_f(v.im, true)};
+    else return {dpp_d(v.re, true), dpp_d(v.im, true)};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> from_above(cpx<R> v) {
+    if constexpr (sizeof(R) == 4) return {dpp_f(v.re, false), dpp_f(v.im, false)};
+    else return {dpp_d(v.re, false), dpp_d(v.im, false)};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> csel(bool c, cpx<R> a, cpx<R> b) {
+    return {c ? a.re : b.re, c ? a.im : b.im};
+}
+
+// Tile of workgroup `b` among `tiles` tiles padded to `padded` (a multiple of
+// eight): consecutive workgroups go round-robin to the eight XCDs, each with
+// its own L2, so XCD q is given the q-th contiguous eighth of the tiles.  Tiles
+// are numbered y fastest, so the rows one tile reads beyond its own edges were
+// loaded by a tile on the same XCD.  Returns -1 for padding.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t tiles, int64_t padded) {
+    const int64_t t = (b & 7) * (padded >> 3) + (b >> 3);
+    return t < tiles ? t : -1;
+}
+
+// 3D sweep marching along z.  A workgroup's four wavefronts lie side by side
+// along x: work-item c owns column c of a tile of kSweepW columns and TY rows
+// and keeps those TY values of v for planes k-1, k and k+1 in registers.  So
+// per plane v is loaded once for the tile's rows plus one halo row on either
+// side; y-neighbours inside the tile come from the work-item's own registers
+// and x-neighbours from the adjacent lanes by DPP wavefront shifts (lanes 0
+// and 63 load theirs: it lies in the neighbouring wavefront, or tile).  The
+// plane loop is unrolled by three so that the three plane slots rotate by
+// renaming.  The x weights are loop-invariant per lane, the y and z tables
+// are uniform (scalar cache); ghost neighbours get weight zero and clamped
+// addresses (no branch around a load).  OPS marks the operands present (1: x,
+// 2: b2, 4: b3, 8: D), so absent ones cost no load.
+template <typename R, int OPS, int TY>
+__device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGeom& m, int64_t tile) {
     constexpr bool HX = OPS & 1, H2 = OPS & 2, H3 = OPS & 4, HD = OPS & 8;
-    const int tx = tile % m.tiles_x;
-    const int rest = tile / m.tiles_x;
-    const int ty = rest % m.tiles_y;
-    const int tz = rest / m.tiles_y;
-    const int64_t i = int64_t(tx) * kBX + threadIdx.x;
-    const int64_t j = int64_t(ty) * kBY + threadIdx.y;
-    if (i >= a.n0 || j >= a.n1) return;
-    const int64_t z0 = int64_t(tz) * m.zc;
+    const int64_t ty = tile % m.tiles_y;
+    const int64_t rest = tile / m.tiles_y;
+    const int64_t tz = rest % m.zchunks;
+    const int64_t tx = rest / m.zchunks;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tx * kSweepW + threadIdx.x;
+    const bool col_ok = i < a.n0;
+    const int64_t ic = col_ok ? i : a.n0 - 1;  // clamped column for loads
+    const int64_t j0 = ty * TY;
+    const int64_t z0 = tz * m.zc;
     const int64_t z1 = z0 + m.zc < a.n2 ? z0 + m.zc : a.n2;
     const int64_t sy = a.n0;
     const int64_t sz = a.n0 * a.n1;
     const cpx<R>* __restrict__ v = a.b1;
     const cpx<R> zero{R(0), R(0)};
-    const int64_t oxm = i > 0 ? -1 : 0, oxp = i < a.n0 - 1 ? 1 : 0;
-    const int64_t oym = j > 0 ? -sy : 0, oyp = j < a.n1 - 1 ? sy : 0;
-    const cpx<R> wxm = keep_if(i > 0, gload(a.alpha[0], i));
-    const cpx<R> wxp = keep_if(i < a.n0 - 1, gload(a.beta[0], i));
-    const cpx<R> wym = keep_if(j > 0, gload(a.alpha[1], j));
-    const cpx<R> wyp = keep_if(j < a.n1 - 1, gload(a.beta[1], j));
-    const cpx<R> gxy = cadd(gload(a.gamma[0], i), gload(a.gamma[1], j));
-    int64_t p = i + sy * j + sz * z0;
-    cpx<R> vm = gload(v, z0 > 0 ? p - sz : p);
-    if (z0 == 0) vm = zero;
-    cpx<R> vc = gload(v, p);
-    for (int64_t k = z0; k < z1; ++k, p += sz) {
+    // x weights (zero for ghosts and for columns beyond the grid)
+    const cpx<R> wxm = keep_if(col_ok && i > 0, gload(a.alpha[0], ic));
+    const cpx<R> wxp = keep_if(col_ok && i < a.n0 - 1, gload(a.beta[0], ic));
+    const cpx<R> gx = gload(a.gamma[0], ic);
+    // lanes 0 and 63 read their outer x-neighbour from memory (offset 0 when it is a ghost)
+    const int64_t eoff = (lane == 0 && ic > 0) ? -1 : ((lane == 63 && ic < a.n0 - 1) ? 1 : 0);
+    // row offsets, clamped to the grid
+    int64_t roff[TY];
+#pragma unroll
+    for (int r = 0; r < TY; ++r) roff[r] = sy * (j0 + r < a.n1 ? j0 + r : a.n1 - 1);
+    const int64_t hlo = sy * (j0 > 0 ? j0 - 1 : 0);
+    const int64_t hhi = sy * (j0 + TY < a.n1 ? j0 + TY : a.n1 - 1);
+    const bool has_lo = j0 > 0, has_hi = j0 + TY < a.n1;
+    cpx<R> P0[TY], P1[TY], P2[TY];
+    // planes z0 - 1 and z0
+#pragma unroll
+    for (int r = 0; r < TY; ++r) {
+        P0[r] = keep_if(z0 > 0, gload(v, ic + roff[r] + sz * (z0 > 0 ? z0 - 1 : z0)));
+        P1[r] = gload(v, ic + roff[r] + sz * z0);
+    }
+    // one plane: prev = k-1, cur = k, next receives k+1
+    auto plane = [&](int64_t k, const cpx<R>(&prev)[TY], const cpx<R>(&cur)[TY], cpx<R>(&next)[TY]) {
         const bool up = k + 1 < a.n2;
-        cpx<R> vp = gload(v, up ? p + sz : p);
-        const cpx<R> vxm = gload(v, p + oxm), vxp = gload(v, p + oxp);
-        const cpx<R> vym = gload(v, p + oym), vyp = gload(v, p + oyp);
-        R Draw = a.Dconst;
-        if constexpr (HD) Draw = gload(a.D, p);
-        cpx<R> xv = zero, b2v = zero, b3v = zero;
-        if constexpr (HX) xv = gload(a.x, p);
-        if constexpr (H2) b2v = gload(a.b2, p);
-        if constexpr (H3) b3v = gload(a.b3, p);
-        vp = keep_if(up, vp);
-        cpx<R> diag = cadd(gxy, sload(a.gamma[2], k));
-        diag = cadd(diag, cscale(Draw - a.Dref, a.kD));
-        cpx<R> s = cmul(diag, vc);
-        s = cfma(wxm, vxm, s);
-        s = cfma(wxp, vxp, s);
-        s = cfma(wym, vym, s);
-        s = cfma(wyp, vyp, s);
-        s = cfma(sload(a.alpha[2], k), vm, s);
-        s = cfma(sload(a.beta[2], k), vp, s);
-        cpx<R> o = cmul(a.g, s);
-        if constexpr (HX) o = cfma(a.cx, xv, o);
-        if constexpr (H2) o = cfma(a.e2, b2v, o);
-        if constexpr (H3) o = cfma(a.e3, b3v, o);
-        gstore(a.out, p, o);
-        vm = vc;
-        vc = vp;
+        const int64_t pk = ic + sz * k;
+        const int64_t pn = ic + sz * (up ? k + 1 : k);
+        cpx<R> hm = gload(v, pk + hlo);
+        cpx<R> xe[TY], xv[TY], b2v[TY], b3v[TY];
+        R Dv[TY];
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            next[r] = gload(v, pn + roff[r]);
+            xe[r] = gload(v, pk + roff[r] + eoff);
+            if constexpr (HX) xv[r] = gload(a.x, pk + roff[r]);
+            if constexpr (H2) b2v[r] = gload(a.b2, pk + roff[r]);
+            if constexpr (H3) b3v[r] = gload(a.b3, pk + roff[r]);
+            if constexpr (HD) Dv[r] = gload(a.D, pk + roff[r]);
+        }
+        cpx<R> hp = gload(v, pk + hhi);
+        hm = keep_if(has_lo, hm);
+        hp = keep_if(has_hi, hp);
+        const cpx<R> az = sload(a.alpha[2], k), bz = sload(a.beta[2], k);
+        const cpx<R> gxz = cadd(gx, sload(a.gamma[2], k));
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            next[r] = keep_if(up, next[r]);
+            const int64_t j = j0 + r;
+            if (j >= a.n1) break;  // uniform: rows beyond the grid
+            cpx<R> xm = from_below(cur[r]), xp = from_above(cur[r]);
+            xm = csel(lane == 0, xe[r], xm);
+            xp = csel(lane == 63, xe[r], xp);
+            const cpx<R> ym = r > 0 ? cur[r - 1] : hm;
+            const cpx<R> yp = r < TY - 1 ? cur[r + 1] : hp;
+            const cpx<R> wym = keep_if(j > 0, sload(a.alpha[1], j));
+            const cpx<R> wyp = keep_if(j < a.n1 - 1, sload(a.beta[1], j));
+            R Draw = a.Dconst;
+            if constexpr (HD) Draw = Dv[r];
+            cpx<R> diag = cadd(gxz, sload(a.gamma[1], j));
+            diag = cadd(diag, cscale(Draw - a.Dref, a.kD));
+            cpx<R> s = cmul(diag, cur[r]);
+            s = cfma(wxm, xm, s);
+            s = cfma(wxp, xp, s);
+            s = cfma(wym, ym, s);
+            s = cfma(wyp, yp, s);
+            s = cfma(az, prev[r], s);
+            s = cfma(bz, next[r], s);
+            cpx<R> o = cmul(a.g, s);
+            if constexpr (HX) o = cfma(a.cx, xv[r], o);
+            if constexpr (H2) o = cfma(a.e2, b2v[r], o);
+            if constexpr (H3) o = cfma(a.e3, b3v[r], o);
+            if (col_ok) gstore(a.out, pk + roff[r], o);
+        }
+    };
+    for (int64_t k = z0; k < z1; k += 3) {
+        plane(k, P0, P1, P2);
+        if (k + 1 >= z1) break;
+        plane(k + 1, P1, P2, P0);
+        if (k + 2 >= z1) break;
+        plane(k + 2, P2, P0, P1);
     }
 }
 
+// rows per work-item: complex float 8, complex double 4 (register budget)
+template <typename R>
+constexpr int sweep_rows() { return sizeof(R) == 4 ? 8 : 4; }
+
 template <typename R, int OPS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_stencil3d(StencilArgs<R> a,
-                                                                                             Sweep3DGeom m) {
-    sweep3d<R, OPS>(a, m, blockIdx.x);
+__global__ __launch_bounds__(256) void k_stencil3d(StencilArgs<R> a, Sweep3DGeom m) {
+    const int64_t t = xcd_tile(blockIdx.x, m.tiles, m.blocks);
+    if (t < 0) return;
+    sweep3d<R, OPS, sweep_rows<R>()>(a, m, t);
 }
 
 // Batched form: the job of a workgroup comes from a lookup table with one
 // entry per 64 workgroups, and its description is read through the scalar
 // cache (uniform across the workgroup).
 template <typename R, int OPS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_stencil3d_batch(
-    const Sweep3DJob<R>* jobs, const uint32_t* lut) {
+__global__ __launch_bounds__(256) void k_stencil3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut) {
     const int b = blockIdx.x;
     const __attribute__((address_space(4))) uint32_t* lq = (const __attribute__((address_space(4))) uint32_t*)(lut);
     const int q = lq[b >> 6];
     const Sweep3DJob<R> job = sload_words(jobs + q);
     const int64_t local = int64_t(b) - job.block0;
-    if (local >= job.blocks) return;
-    sweep3d<R, OPS>(job.a, job.geom, int(local));
+    if (local >= job.geom.blocks) return;
+    const int64_t t = xcd_tile(local, job.geom.tiles, job.geom.blocks);
+    if (t < 0) return;
+    sweep3d<R, OPS, sweep_rows<R>()>(job.a, job.geom, t);
 }
 
 template <typename R, int OPS>
 void launch_3d_ops(const StencilArgs<R>& a, const Sweep3DGeom& m, unsigned nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_stencil3d<R, OPS>), dim3(nb), dim3(kBX, kBY, 1), 0, s, a, m);
+    hipLaunchKernelGGL((k_stencil3d<R, OPS>), dim3(nb), dim3(kSweepW, 1, 1), 0, s, a, m);
 }
 
 template <typename R, int... OPS>
@@ -231,7 +325,7 @@ void launch_3d(const StencilArgs<R>& a, const Sweep3DGeom& m, unsigned nb, int o
 
 template <typename R, int OPS>
 void launch_3d_batch_ops(const Sweep3DJob<R>* jobs, const uint32_t* lut, unsigned nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_stencil3d_batch<R, OPS>), dim3(nb), dim3(kBX, kBY, 1), 0, s, jobs, lut);
+    hipLaunchKernelGGL((k_stencil3d_batch<R, OPS>), dim3(nb), dim3(kSweepW, 1, 1), 0, s, jobs, lut);
 }
 
 template <typename R, int... OPS>
@@ -413,9 +507,8 @@ void launch_stencil(const StencilArgs<R>& a, hipStream_t s) {
     const dim3 block(kBX, kBY, 1);
     if (a.dim == 3) {
         const Sweep3DGeom m = sweep3d_geometry(a);
-        const int64_t nb = int64_t(m.tiles_x) * m.tiles_y * m.zchunks;
-        if (nb > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "grid too large for the 3D sweep");
-        launch_3d<R>(a, m, unsigned(nb), sweep_ops(a), s, std::make_integer_sequence<int, 16>{});
+        if (m.blocks > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "grid too large for the 3D sweep");
+        launch_3d<R>(a, m, unsigned(m.blocks), sweep_ops(a), s, std::make_integer_sequence<int, 16>{});
     } else {
         const dim3 grid(unsigned((a.n0 + kBX - 1) / kBX), unsigned((a.n1 + kBY - 1) / kBY), 1);
         hipLaunchKernelGGL((k_stencil<R, 2>), grid, block, 0, s, a);
@@ -427,10 +520,23 @@ template void launch_stencil<double>(const StencilArgs<double>&, hipStream_t);
 template <typename R>
 Sweep3DGeom sweep3d_geometry(const StencilArgs<R>& a) {
     Sweep3DGeom m;
-    m.tiles_x = int((a.n0 + kBX - 1) / kBX);
-    m.tiles_y = int((a.n1 + kBY - 1) / kBY);
-    m.zc = 16;
+    constexpr int TY = sweep_rows<R>();
+    m.rows = TY;
+    m.tiles_x = int((a.n0 + kSweepW - 1) / kSweepW);
+    m.tiles_y = int((a.n1 + TY - 1) / TY);
+    // z segments: the caller's length, else about four workgroups per compute
+    // unit of a 256-CU device, in 8..32 planes
+    int zc = a.zc;
+    if (zc <= 0) {
+        const int64_t cols = int64_t(m.tiles_x) * m.tiles_y;
+        const int64_t want = (4 * 256 + cols - 1) / cols;  // segments wanted
+        zc = int((a.n2 + want - 1) / want);
+        zc = zc < 8 ? 8 : (zc > 32 ? 32 : zc);
+    }
+    m.zc = zc;
     m.zchunks = int((a.n2 + m.zc - 1) / m.zc);
+    m.tiles = int64_t(m.tiles_x) * m.tiles_y * m.zchunks;
+    m.blocks = (m.tiles + 7) / 8 * 8;
     return m;
 }
 template Sweep3DGeom sweep3d_geometry<double>(const StencilArgs<double>&);

@@ -152,13 +152,16 @@ static void learned_apply(Run& run, const cpx<double>* v, double vnorm, cpx<doub
 }
 
 // Algorithm 1.  r, w: complex double device vectors.
-int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt) {
+int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt,
+            mxp_precision ap) {
     mxp_problem* P = run.P;
     run.graphs = o.use_graphs != 0 && !run.batch;
     Workspace& WS = *run.W;
     const int64_t n = npts(P);
     hipStream_t s = run.s;
-    const Sched& sc = get_sched(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
+    // ap: precision of the matrix-function actions (the inner basis follows
+    // o.precision: complex double only in the FP64 form)
+    const Sched& sc = get_sched(P, o.t, o.shift, ap, o.cheb_S, o.cheb_m);
     const int m = o.inner_restart;
     // complex-double basis: GMRES in the FP64 form; otherwise one direction vector
     const bool basis64 = o.precision == MXP_PREC_FP64 && (o.inner_solver == 0 || o.inner_solver == 2);
@@ -180,7 +183,7 @@ int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>
     const int fn_rhs = form2 ? ACT_PSI2 : ACT_PSI1;
     const int fn_op = form2 ? ACT_PSI1 : ACT_EXP;
     // r_hat = psi_1(i t A_s) r (or psi_2); z = ||r_hat||
-    action64(run, sc, o.t, o.shift, fn_rhs, o.precision, r, rhat, &cnt.steps);
+    action64(run, sc, o.t, o.shift, fn_rhs, ap, r, rhat, &cnt.steps);
     cnt.actions++;
     const double z = norm2(run, rhat);
     launch_zero<double>(w, n, s);
@@ -197,7 +200,7 @@ int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>
         launch_scale(one, rhat, w, n, s);
         int its = 0;
         while (its < o.max_inner) {
-            action64(run, sc, o.t, o.shift, fn_op, o.precision, w, d, &cnt.steps);
+            action64(run, sc, o.t, o.shift, fn_op, ap, w, d, &cnt.steps);
             cnt.actions++;
             ++its;
             launch_axpby(one, rhat, one, d, n, s);  // E w + r_hat
@@ -239,7 +242,7 @@ int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>
                 launch_to_c128(V32 + size_t(j) * n, rr, n, s);
                 vj = rr;
             }
-            action64(run, sc, o.t, o.shift, fn_op, o.precision, vj, tmp, &cnt.steps);
+            action64(run, sc, o.t, o.shift, fn_op, ap, vj, tmp, &cnt.steps);
             cnt.actions++;
             // v_{j+1} <- v_j - E v_j
             launch_scale(one, vj, vn, n, s);
@@ -266,7 +269,7 @@ int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>
         else launch_mcombine(w, static_cast<const cpx<double>*>(V), n, k, small_buffers(run).y, n, s);
         if (conv || its >= o.max_inner) break;
         // restart: r = r_hat - (w - E w)
-        action64(run, sc, o.t, o.shift, fn_op, o.precision, w, tmp, &cnt.steps);
+        action64(run, sc, o.t, o.shift, fn_op, ap, w, tmp, &cnt.steps);
         cnt.actions++;
         launch_scale(one, rhat, rr, n, s);
         launch_axpby(mone, w, one, rr, n, s);
@@ -360,6 +363,11 @@ int krylov_action(Run& run, bool psi, double t, double shift, double tol, int ma
     hipStream_t s = run.s;
     int total = 0;
     *ok = false;
+    run.W->krylovV.ensure(size_t(max_dim + 1) * n * sizeof(cpx<double>));
+    if (psi) run.W->krylovP.ensure(size_t(n) * sizeof(cpx<double>));
+    (void)small_buffers(run);
+    (void)plain_diag(run.P, shift);
+    t_reserved = true;
     for (int q = 1; q <= 64 && !*ok; q *= 2) {
         const double tau = t / q, tq = tol / q;
         bool all = true, step_ok = false;
@@ -403,6 +411,43 @@ void check_opts(const mxp_solve_opts* o) {
     if (o->use_learned && !(o->stall_ratio >= 0 && o->stall_ratio <= 1))
         fail(MXP_ERR_INVALID_ARG, "stall_ratio must be in [0, 1]");
     if (o->inner_solver < 0 || o->inner_solver > 3) fail(MXP_ERR_INVALID_ARG, "inner_solver must be 0, 1, 2 or 3");
+    if (!(o->fp64_below >= 0) || !(o->fp64_below < 1)) fail(MXP_ERR_INVALID_ARG, "fp64_below must be in [0, 1)");
+    if (o->fp64_first < 0) fail(MXP_ERR_INVALID_ARG, "fp64_first must be >= 0");
+}
+
+void reserve_precond(Run& run, const mxp_solve_opts& o) {
+    mxp_problem* P = run.P;
+    Workspace& WS = *run.W;
+    const size_t n = size_t(npts(P));
+    const Sched& sc = get_sched(P, o.t, o.shift, o.precision, o.cheb_S, o.cheb_m);
+    reserve_action(P, WS, sc, o.inner_solver >= 2, o.use_graphs != 0 && !run.batch, run.s);
+    if (o.precision == MXP_PREC_MIXED && (o.fp64_below > 0 || o.fp64_first > 0)) {
+        const Sched& s64 = get_sched(P, o.t, o.shift, MXP_PREC_FP64, o.cheb_S, o.cheb_m);
+        reserve_action(P, WS, s64, o.inner_solver >= 2, o.use_graphs != 0 && !run.batch, run.s);
+    }
+    const int m = o.inner_restart;
+    const bool gmres = o.inner_solver == 0 || o.inner_solver == 2;
+    const bool basis64 = o.precision == MXP_PREC_FP64 && gmres;
+    WS.innerV.ensure(size_t(basis64 ? m + 1 : 1) * n * sizeof(cpx<double>));
+    WS.innerRh.ensure(n * sizeof(cpx<double>));
+    WS.innerTmp.ensure(n * sizeof(cpx<double>));
+    WS.innerRr.ensure(n * sizeof(cpx<double>));
+    if (gmres && !basis64) WS.innerV32.ensure(size_t(m + 1) * n * sizeof(cpx<float>));
+    (void)small_buffers(run);
+}
+
+void reserve_solve(Run& run, const mxp_solve_opts& o) {
+    mxp_problem* P = run.P;
+    Workspace& WS = *run.W;
+    const size_t n = size_t(npts(P));
+    const int m = o.outer_restart;
+    WS.outerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
+    WS.outerZ.ensure(size_t(m) * n * sizeof(cpx<double>));
+    WS.outerR.ensure(n * sizeof(cpx<double>));
+    (void)plain_diag(P, 0.0);  // A itself, for A z_j and the true residual
+    reserve_precond(run, o);
+    if (o.use_learned && P->net)
+        cnn_reserve(P->net, ConvShape{1, int(P->g.n[2]), int(P->g.n[1]), int(P->g.n[0])}, run.s);
 }
 
 mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
@@ -413,9 +458,8 @@ mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<do
     const int64_t n = npts(P);
     hipStream_t s = run.s;
     const int m = o.outer_restart;
-    WS.outerV.ensure(size_t(m + 1) * n * sizeof(cpx<double>));
-    WS.outerZ.ensure(size_t(m) * n * sizeof(cpx<double>));
-    WS.outerR.ensure(size_t(n) * sizeof(cpx<double>));
+    reserve_solve(run, o);
+    t_reserved = true;
     cpx<double>* V = WS.outerV.as<cpx<double>>();
     cpx<double>* Z = WS.outerZ.as<cpx<double>>();
     cpx<double>* r = WS.outerR.as<cpx<double>>();
@@ -500,7 +544,14 @@ mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<do
             }
             if (!accepted) {
                 const auto a0 = now();
-                inner.push_back(precond(run, o, vj, zj, cnt));
+                // mixed form: the first fp64_first outer iterations of the solve
+                // (whose directions enter the iterate with the largest
+                // coefficients), and those starting below fp64_below, run the
+                // preconditioner's actions in double
+                const bool dbl = o.precision == MXP_PREC_MIXED &&
+                                 (its < o.fp64_first || (o.fp64_below > 0 && prev_res <= o.fp64_below * bnorm));
+                if (dbl) cnt.fp64_its++;
+                inner.push_back(precond(run, o, vj, zj, cnt, dbl ? MXP_PREC_FP64 : o.precision));
                 if (run.pairs && run.pairs->count < run.pairs->max) {
                     PairSink& ps = *run.pairs;
                     HIP_CHECK(hipMemcpyAsync(ps.r + size_t(ps.count) * n, vj, size_t(n) * sizeof(cpx<double>),
@@ -573,6 +624,7 @@ mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<do
         st->true_relres = relres;
         st->restarts = std::max(0, cycles - 1);
         st->learned_its = cnt.learned;
+        st->fp64_its = cnt.fp64_its;
         st->fallbacks = cnt.fallbacks;
         st->status = relres <= o.rtol ? MXP_OK : MXP_NOT_CONVERGED;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <optional>
 #include <random>
 #include <vector>
 
@@ -92,6 +93,7 @@ void cnn_forward(mxp_cnn* net, const ConvShape& s, const uint16_t* in, float* ou
     if (!net->packed) pack(net, st);
     // workspace first: every internal pointer is taken after it is allocated
     ensure_shape(net, s.voxels(), keep, st);
+    net->kept_voxels = keep ? s.voxels() : 0;
     if (!out) out = net->out.as<float>();
     const uint16_t* x = in;
     for (int l = 0; l < kLayers; ++l) {
@@ -104,6 +106,14 @@ void cnn_forward(mxp_cnn* net, const ConvShape& s, const uint16_t* in, float* ou
             x = y;
         }
     }
+}
+
+void cnn_reserve(mxp_cnn* net, const ConvShape& s, hipStream_t st) {
+    check_shape(s);
+    if (!net->packed) pack(net, st);
+    ensure_shape(net, s.voxels(), false, st);
+    net->io_in.ensure(size_t(s.voxels()) * 8 * 2);
+    net->io_scale.ensure(2 * sizeof(double));
 }
 
 void cnn_apply(mxp_cnn* net, const ConvShape& s, const void* v, const float* D, float Dc, double rs,
@@ -123,9 +133,11 @@ void cnn_apply(mxp_cnn* net, const ConvShape& s, const void* v, const float* D, 
 }
 
 template <class F>
-static mxp_status cnn_guard(F&& fn) {
+static mxp_status cnn_guard(const Allocator* al, F&& fn) {
     try {
         g_last_error.clear();
+        std::optional<AllocScope> scope;
+        if (al) scope.emplace(*al);
         return fn();
     } catch (const Error& e) {
         g_last_error = e.what();
@@ -152,8 +164,9 @@ int64_t mxp_cnn_num_params(void) {
 }
 
 mxp_status mxp_cnn_create(mxp_context* ctx, uint64_t seed, mxp_cnn** out) {
-    return cnn_guard([&]() {
+    return cnn_guard(nullptr, [&]() {
         if (!ctx || !out) fail(MXP_ERR_INVALID_ARG, "context or out is NULL");
+        AllocScope scope(context_alloc(ctx));
         *out = nullptr;
         int dev = 0;
         hipStream_t st = nullptr;
@@ -162,6 +175,7 @@ mxp_status mxp_cnn_create(mxp_context* ctx, uint64_t seed, mxp_cnn** out) {
         auto net = std::make_unique<mxp_cnn>();
         net->device = dev;
         net->stream = st;
+        net->alloc = context_alloc(ctx);
         int64_t off = 0;
         for (int l = 0; l < kLayers; ++l) {
             net->offW[l] = off;
@@ -201,7 +215,7 @@ void mxp_cnn_destroy(mxp_cnn* net) {
 }
 
 mxp_status mxp_cnn_get_params(const mxp_cnn* net, float* host) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !host) fail(MXP_ERR_INVALID_ARG, "network or buffer is NULL");
         HIP_CHECK(hipSetDevice(net->device));
         HIP_CHECK(hipStreamSynchronize(net->stream));
@@ -211,7 +225,7 @@ mxp_status mxp_cnn_get_params(const mxp_cnn* net, float* host) {
 }
 
 mxp_status mxp_cnn_set_params(mxp_cnn* net, const float* host) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !host) fail(MXP_ERR_INVALID_ARG, "network or buffer is NULL");
         for (int64_t k = 0; k < net->nparam; ++k)
             if (!std::isfinite(host[k])) fail(MXP_ERR_NONFINITE, "non-finite parameter");
@@ -228,7 +242,7 @@ mxp_status mxp_cnn_set_params(mxp_cnn* net, const float* host) {
 }
 
 mxp_status mxp_cnn_get_grads(const mxp_cnn* net, float* host) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !host) fail(MXP_ERR_INVALID_ARG, "network or buffer is NULL");
         HIP_CHECK(hipSetDevice(net->device));
         HIP_CHECK(hipStreamSynchronize(net->stream));
@@ -243,7 +257,7 @@ mxp_status mxp_cnn_get_grads(const mxp_cnn* net, float* host) {
 static const char kCkptTag[8] = {'M', 'X', 'P', 'C', 'N', 'N', '0', '1'};
 
 mxp_status mxp_cnn_save(const mxp_cnn* net, const char* path) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !path) fail(MXP_ERR_INVALID_ARG, "network or path is NULL");
         HIP_CHECK(hipSetDevice(net->device));
         HIP_CHECK(hipStreamSynchronize(net->stream));
@@ -266,7 +280,7 @@ mxp_status mxp_cnn_save(const mxp_cnn* net, const char* path) {
 }
 
 mxp_status mxp_cnn_load(mxp_cnn* net, const char* path) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !path) fail(MXP_ERR_INVALID_ARG, "network or path is NULL");
         std::unique_ptr<FILE, int (*)(FILE*)> f(std::fopen(path, "rb"), &std::fclose);
         if (!f) fail(MXP_ERR_INVALID_ARG, std::string("cannot open ") + path);
@@ -301,7 +315,7 @@ mxp_status mxp_cnn_load(mxp_cnn* net, const char* path) {
 
 mxp_status mxp_cnn_forward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
                            float* out) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !in || !out) fail(MXP_ERR_INVALID_ARG, "network, input or output is NULL");
         HIP_CHECK(hipSetDevice(net->device));
         const ConvShape s{nb, nz, ny, nx};
@@ -313,7 +327,7 @@ mxp_status mxp_cnn_forward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int
 
 mxp_status mxp_cnn_backward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
                             const float* gout) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !in || !gout) fail(MXP_ERR_INVALID_ARG, "network, input or gradient is NULL");
         HIP_CHECK(hipSetDevice(net->device));
         const ConvShape s{nb, nz, ny, nx};
@@ -326,9 +340,22 @@ mxp_status mxp_cnn_backward(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, in
     });
 }
 
+mxp_status mxp_cnn_get_activations(const mxp_cnn* net, int32_t layer, int64_t voxels, uint16_t* host) {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
+        if (!net || !host) fail(MXP_ERR_INVALID_ARG, "network or buffer is NULL");
+        if (layer < 1 || layer >= kLayers) fail(MXP_ERR_INVALID_ARG, "layer must be 1..5");
+        if (voxels <= 0 || voxels != net->kept_voxels)
+            fail(MXP_ERR_INVALID_ARG, "voxels must be those of the last backward or training step");
+        HIP_CHECK(hipSetDevice(net->device));
+        HIP_CHECK(hipStreamSynchronize(net->stream));
+        HIP_CHECK(hipMemcpy(host, net->act[layer].p, size_t(voxels) * 32 * 2, hipMemcpyDeviceToHost));
+        return MXP_OK;
+    });
+}
+
 mxp_status mxp_cnn_train_step(mxp_cnn* net, int32_t nb, int32_t nz, int32_t ny, int32_t nx, const void* in,
                               const float* target, float lr, double* loss) {
-    return cnn_guard([&]() {
+    return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !in || !target) fail(MXP_ERR_INVALID_ARG, "network, input or target is NULL");
         if (!(lr > 0) || !std::isfinite(lr)) fail(MXP_ERR_INVALID_ARG, "learning rate must be positive");
         HIP_CHECK(hipSetDevice(net->device));

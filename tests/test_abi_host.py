@@ -100,9 +100,20 @@ def test_context_create_without_device_fails_cleanly():
     if torch.cuda.is_available():
         pytest.skip("a device is present")
     h = ctypes.c_void_p()
-    st = mxp.lib.mxp_context_create(0, None, ctypes.byref(h))
+    st = mxp.lib.mxp_context_create(0, None, mxp.MXP_ALLOC_FN(), mxp.MXP_FREE_FN(), None, ctypes.byref(h))
     assert st == mxp.MXP_ERR_INVALID_ARG
     assert "device" in mxp.lib.mxp_last_error().decode()
+
+
+def test_context_create_rejects_a_lone_allocator_hook():
+    """mxp_context_create takes both device-memory hooks or neither; the check
+    runs before any device query."""
+    h = ctypes.c_void_p()
+    alloc = mxp.MXP_ALLOC_FN(lambda n, u: None)
+    st = mxp.lib.mxp_context_create(0, None, alloc, mxp.MXP_FREE_FN(), None, ctypes.byref(h))
+    assert st == mxp.MXP_ERR_INVALID_ARG
+    assert "together" in mxp.lib.mxp_last_error().decode()
+    assert not h.value
 
 
 def _support(A, th):
@@ -250,3 +261,23 @@ def test_complex_float_clenshaw_replay_at_the_largest_accepted_box():
             b1, b2 = (c[k] * y + np.complex64(2) * (X @ b1) - b2).astype(np.complex64), b1
         y = (c[0] * y + X @ b1 - b2).astype(np.complex64)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+def test_device_memory_is_taken_only_through_the_allocator():
+    """Every device allocation of the library goes through the context's
+    allocator (devmem.h), which calls the caller's hooks or, without them,
+    hipMalloc: no other source file allocates or frees device memory."""
+    import glob
+    import os
+    import re
+    csrc = os.path.join(os.path.dirname(mxp.__file__), "csrc")
+    pat = re.compile(r"\bhip(Malloc|MallocAsync|MallocManaged|ExtMallocWithFlags|MallocPitch|Free|FreeAsync)\s*\(")
+    offenders = []
+    for path in sorted(glob.glob(os.path.join(csrc, "*"))):
+        if os.path.basename(path) == "devmem.h":
+            continue
+        with open(path) as fh:
+            for k, line in enumerate(fh, 1):
+                if pat.search(line):
+                    offenders.append(f"{os.path.basename(path)}:{k}: {line.strip()}")
+    assert not offenders, offenders

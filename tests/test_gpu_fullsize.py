@@ -123,6 +123,43 @@ def test_exp_full_size_against_dst(ctx, n, dt, tol):
     assert rel(y, ref) <= tol
 
 
+@pytest.fixture(scope="module")
+def grf_oracle():
+    """The 2048^2 random-field workload (32-cell layer), its operator in the
+    oracle's CSR form, a seeded input and the oracle's exp and psi_1 actions at
+    t/16 (expm_multiply; about 3.4 s each on the host)."""
+    prob = wl.config2()
+    s = prob.default_shift()
+    t = prob.default_t() / 16
+    As = op.helmholtz(prob, s)
+    x = wl.random_vector(prob.npts, 31)
+    return {"prob": prob, "s": s, "t": t, "x": x,
+            "exp": matfun.exp_action(As, t, x), "psi1": matfun.phi1_action(As, t, x)}
+
+
+@pytest.mark.parametrize("fn,dt,tol", [("exp", "c128", 1e-11), ("exp", "c64", 1e-5), ("psi1", "c128", 1e-11),
+                                       ("psi1", "c64", 1e-5)])
+def test_actions_full_size_grf_against_oracle(ctx, grf_oracle, fn, dt, tol):
+    # element by element at the benchmark's 2048^2 shape, with the layer and the
+    # random-field speed, in the launch configuration the benchmark times
+    # (autotuned fused 2D passes); t/16 keeps the oracle's action to seconds
+    g = grf_oracle
+    prob = g["prob"]
+    announce("action full size vs oracle", prob.name, fn, dt)
+    P = mxp.Problem(ctx, prob)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    xd = to_dev(g["x"], tdt)
+    yd = torch.empty_like(xd)
+    (mxp.mxp_apply_exp if fn == "exp" else mxp.mxp_apply_psi1)(P, g["t"], g["s"], xd, yd)
+    torch.cuda.synchronize()
+    y = to_host(yd)
+    del xd, yd
+    P.close()
+    # (a complex-float input is the rounded x: that changes the action by about
+    # 6e-8 relative, far below the complex-float bar)
+    assert rel(y, g[fn]) <= tol
+
+
 def test_matfun_identities_full_size_grf(ctx):
     # with the layer and the random-field speed at full size:
     #   e^{itA_s} v - v = i t A_s psi_1(itA_s) v                       (Section 3.1)

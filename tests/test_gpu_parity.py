@@ -42,6 +42,30 @@ def make(name, ppw=10.0):
     return wl.small_problem(c["n"], layer=c["layer"], ppw=ppw, inhomogeneous=c["inh"], seed=7, name=name)
 
 
+def forced_precond_parity(P, As, o, r, tol, inner="gmres", form="exp"):
+    """One preconditioner apply compared element by element with the oracle's
+    at the same inner iteration count.  The count is fixed on both sides: the
+    oracle's natural count k under o.fprtol (checked against the library's to
+    +-1), then both run exactly k inner iterations (max_inner = k, fprtol
+    1e-14) and w is compared at `tol`."""
+    import copy
+    rd = to_dev(r)
+    wd = torch.empty_like(rd)
+    its = mxp.mxp_apply_precond(P, o, rd, wd)
+    natural = krylov.precond_apply(As, o.t, r, o.fprtol, inner=inner, form=form)
+    assert abs(its - natural.inner_iterations) <= 1
+    k = max(natural.inner_iterations, 1)
+    of = copy.copy(o)
+    of.fprtol = 1e-14
+    of.max_inner = k
+    its_f = mxp.mxp_apply_precond(P, of, rd, wd)
+    ref = krylov.precond_apply(As, o.t, r, 1e-14, maxit=k, inner=inner, form=form)
+    assert its_f == k == ref.inner_iterations
+    err = rel(to_host(wd), ref.w)
+    assert err <= tol, (k, err)
+    return its, natural.inner_iterations
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_apply_A(ctx, name, dt):
@@ -134,13 +158,7 @@ def test_apply_precond(ctx, name, prec):
     o = P.default_opts()
     o.precision = prec
     r = wl.random_vector(prob.npts, 4)
-    rd = to_dev(r)
-    wd = torch.empty_like(rd)
-    its = mxp.mxp_apply_precond(P, o, rd, wd)
-    ref = krylov.precond_apply(op.helmholtz(prob, o.shift), o.t, r, o.fprtol)
-    assert abs(its - ref.inner_iterations) <= 1
-    if its == ref.inner_iterations:
-        assert rel(to_host(wd), ref.w) <= (1e-10 if prec == 0 else 1e-5)
+    forced_precond_parity(P, op.helmholtz(prob, o.shift), o, r, 1e-10 if prec == 0 else 1e-5)
 
 
 @pytest.mark.parametrize("name", ["2d-homog", "2d-inh", "3d-homog", "3d-inh"])
@@ -324,13 +342,7 @@ def test_fixed_point_inner_solver(ctx, name, prec):
     o.precision = prec
     o.inner_solver = mxp.MXP_INNER_FIXED_POINT
     r = wl.random_vector(prob.npts, 4)
-    rd = to_dev(r)
-    wd = torch.empty_like(rd)
-    its = mxp.mxp_apply_precond(P, o, rd, wd)
-    ref = krylov.precond_apply(op.helmholtz(prob, o.shift), o.t, r, o.fprtol, inner="fixed_point")
-    assert abs(its - ref.inner_iterations) <= 1
-    if its == ref.inner_iterations:
-        assert rel(to_host(wd), ref.w) <= (1e-10 if prec == 0 else 1e-5)
+    forced_precond_parity(P, op.helmholtz(prob, o.shift), o, r, 1e-10 if prec == 0 else 1e-5, inner="fixed_point")
     centre = tuple(m // 2 for m in prob.n)
     f = wl.delta_source(prob, centre).ravel()
     fd = to_dev(f)
@@ -377,13 +389,8 @@ def test_psi2_form_inner_solver(ctx, name, prec, inner):
     o.precision = prec
     o.inner_solver = mxp.MXP_INNER_PSI2_GMRES if inner == "gmres" else mxp.MXP_INNER_PSI2_FIXED_POINT
     r = wl.random_vector(prob.npts, 14)
-    rd = to_dev(r)
-    wd = torch.empty_like(rd)
-    its = mxp.mxp_apply_precond(P, o, rd, wd)
-    ref = krylov.precond_apply(op.helmholtz(prob, o.shift), o.t, r, o.fprtol, inner=inner, form="psi2")
-    assert abs(its - ref.inner_iterations) <= 1
-    if its == ref.inner_iterations:
-        assert rel(to_host(wd), ref.w) <= (1e-10 if prec == 0 else 1e-5)
+    forced_precond_parity(P, op.helmholtz(prob, o.shift), o, r, 1e-10 if prec == 0 else 1e-5, inner=inner,
+                          form="psi2")
     centre = tuple(m // 2 for m in prob.n)
     f = wl.delta_source(prob, centre).ravel()
     fd = to_dev(f)
@@ -435,13 +442,7 @@ def test_cap_absorber(ctx, name):
         mxp.mxp_apply_exp(P, t, s, xd, yd)
         assert rel(to_host(yd), matfun.exp_action(As, t, to_host(xd))) <= tol
     o = P.default_opts()
-    rd = to_dev(x)
-    wd = torch.empty_like(rd)
-    its = mxp.mxp_apply_precond(P, o, rd, wd)
-    ref = krylov.precond_apply(As, o.t, x, o.fprtol)
-    assert abs(its - ref.inner_iterations) <= 1
-    if its == ref.inner_iterations:
-        assert rel(to_host(wd), ref.w) <= 1e-10
+    forced_precond_parity(P, As, o, x, 1e-10)
     centre = tuple(m // 2 for m in prob.n)
     f = wl.delta_source(prob, centre).ravel()
     fd = to_dev(f)

@@ -78,6 +78,36 @@ def test_adam_first_step_is_signed_learning_rate():
     assert np.allclose(params[0]["b"], [-0.01], rtol=0, atol=1e-15)
 
 
+def test_adam_constant_gradient_steps_the_signed_learning_rate_every_time():
+    """With a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each step
+    moves a parameter by lr sign(g): after T steps, by T lr.  A missing or
+    wrong bias correction (e.g. 1 - b instead of 1 - b^t) fails at t >= 2."""
+    params = [{"w": np.array([0.5, -1.0, 2.0])}]
+    g = np.array([3.0, -0.25, 1e-2])
+    state = {}
+    for t in range(1, 8):
+        conv.adam_step(params, [{"w": g.copy()}], state, lr=0.01, eps=0.0)
+        assert np.allclose(params[0]["w"], [0.5 - 0.01 * t, -1.0 + 0.01 * t, 2.0 - 0.01 * t], rtol=0, atol=1e-13), t
+
+
+def test_adam_second_step_closed_form():
+    """Two steps with gradients a then b.  Dividing out (1 - beta) from the
+    moment recurrences gives, at t = 2, m_hat = (b1 a + b) / (1 + b1) and
+    v_hat = (b2 a^2 + b^2) / (1 + b2).  For a = 1, b = -1 the second step is
+    -lr (1 - b1) / (1 + b1) = -lr / 19 (v_hat = 1), and for a = 2, b = -1 it is
+    lr (0.8 / 1.9) / sqrt(4.996 / 1.999)."""
+    for a, b, step2 in ((1.0, -1.0, -0.01 / 19.0),
+                        (2.0, -1.0, 0.01 * (0.8 / 1.9) / np.sqrt(4.996 / 1.999))):
+        params = [{"w": np.array([0.0])}]
+        state = {}
+        conv.adam_step(params, [{"w": np.array([a])}], state, lr=0.01, eps=0.0)
+        p1 = params[0]["w"][0]
+        assert abs(p1 - (-0.01 * np.sign(a))) <= 1e-15
+        conv.adam_step(params, [{"w": np.array([b])}], state, lr=0.01, eps=0.0)
+        assert abs((p1 - params[0]["w"][0]) - step2) <= 1e-15, (a, b)
+
+
 def test_bf16_rounding():
     assert conv.to_bf16(np.array([1.0]))[0] == 1.0
     # 1 + 2^-8 is exactly halfway between 1 and 1 + 2^-7: ties to even gives 1
