@@ -144,9 +144,20 @@ const char* mxp_version(void);
  * plane wave at normal incidence decays at the PML's rate to first order.
  * Complex-float stepping (MXP_PREC_MIXED, MXP_C64 actions) needs the potential
  * to stay below about the Laplacian's range (pi pml_C / (ppw layer) <= 1.25,
- * ppw the points per wavelength); beyond it schedules fail with UNSUPPORTED. */
+ * ppw the points per wavelength); beyond it schedules fail with UNSUPPORTED.
+ *
+ * MXP_ABSORB_ABC (2) puts no layer on the grid (every layer width must be 0):
+ * each face carries a boundary condition instead, imposed by ghost points as
+ * in the paper's Marmousi-II experiment (Section 4.3.4).  hard[d][side] != 0
+ * makes the face sound-hard (du/dn = 0); the other faces take the first-order
+ * absorbing condition du/dn = i (omega/c) u (outgoing waves e^{i k r}, n the
+ * outward normal).  The end nodes of every axis are unknowns: eliminating the
+ * ghost node by the central difference of du/dn gives the end row
+ * (2 u_inner - 2 u_end)/h^2 + (2 i omega/(c h)) u_end (the last term only on
+ * absorbing faces, with c at that node). */
 #define MXP_ABSORB_PML 0
 #define MXP_ABSORB_CAP 1
+#define MXP_ABSORB_ABC 2
 
 typedef struct {
     int32_t dim;            /* 2 or 3                                           */
@@ -159,7 +170,9 @@ typedef struct {
     const void* c;          /* wave speed per node (host or device), or NULL    */
     mxp_dtype c_dtype;      /* MXP_F32 or MXP_F64 when c != NULL                */
     double c_const;         /* wave speed everywhere when c == NULL, > 0        */
-    int32_t absorber;       /* MXP_ABSORB_PML (default) or MXP_ABSORB_CAP      */
+    int32_t absorber;       /* MXP_ABSORB_PML (default), _CAP or _ABC            */
+    int32_t hard[3][2];     /* MXP_ABSORB_ABC: nonzero = sound-hard face (low / high
+                               side of each axis); the other faces absorb      */
 } mxp_grid_desc;
 
 /* Copies the description, validates it (c finite and > 0 everywhere), builds
@@ -211,14 +224,17 @@ typedef struct {
     int32_t fp64_first;     /* MXP_PREC_MIXED only, >= 0: the first fp64_first outer iterations
                                of the solve run the preconditioner's actions in complex double.
                                Complex-float stepping noise in z_j enters the iterate with z_j's
-                               FGMRES coefficient, which is largest for the first directions.
+                               FGMRES coefficient, which is largest for the first directions;
+                               left in them it costs outer iterations once the residual nears
+                               the noise (2048^2 random-field workload: 14 outer iterations
+                               with 0, 12 = the complex-double count with 2).  Default 2;
                                0 = complex float throughout. */
 } mxp_solve_opts;
 
 /* Defaults for a problem: t = 40 h^2 (equal to 0.4/freq^2 at ten points per
  * wavelength, Section 4.1), shift = 1/freq (Section 4.1.2), fprtol = 0.08
  * (Section 4.2.1), rtol = 1e-6, restarts 30, max_outer 500, max_inner 300,
- * MXP_PREC_FP64, designed schedule. */
+ * MXP_PREC_FP64, designed schedule, fp64_first = 2 (used by MXP_PREC_MIXED). */
 mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out);
 
 typedef struct {
@@ -254,6 +270,9 @@ typedef struct {
     double half_width;            /* segment half-length                            */
     double box[4];                /* field-of-values box: re_min re_max im_min im_max */
     double trunc_bound;           /* bound on the truncation error of one action    */
+    double similarity_cond;       /* condition number of the diagonal similarity that
+                                     brings the field of values into the box (1, or
+                                     sqrt 2 per axis with ghost-point end rows)     */
     double amplification;         /* max over the box of sum_k |c_k T_k|            */
     double coef[2 * 512];         /* exp series, (re, im) pairs, m+1 used           */
     double coef_psi[2 * 512];     /* psi_1 series, (re, im) pairs, m_psi+1 used     */

@@ -10,6 +10,9 @@ Paper passages followed:
   * absorbing potential instead of the layer: omega^2 u + c^2 Lap u + i W u
     = -c^2 f, i.e. omega^2/c^2 u + Lap u + i (W/c^2) u = -f, with zero
     Dirichlet values and W >= 0 vanishing inside      (Section 2.1, eq. helmholtz-absorbing)
+  * boundary conditions instead of a layer: a sound-hard face (zero normal
+    derivative) and first-order absorbing faces, discretised with ghost
+    points                                             (Section 4.3.4, Marmousi-II)
 
 Readings where the paper is silent (also listed in the design notes):
   * multi-dimensional layer: sum over axes of (1/s_d) d_d((1/s_d) d_d u), each
@@ -23,6 +26,14 @@ Readings where the paper is silent (also listed in the design notes):
     the layer profile above, so that a normally incident plane wave decays at
     the stretch's rate to first order (k = sqrt(omega^2 + i W/c^2) ~ omega +
     i omega sigma against k = omega (1 + i sigma)).
+
+  * the first-order absorbing condition in the paper's time convention
+    (outgoing waves e^{i k r}, Section 2): du/dn = i k u on the face, k =
+    omega/c at the boundary node, n the outward normal; the ghost value comes
+    from the central difference of du/dn at the boundary node, and the grid's
+    end nodes are unknowns of the problem (no Dirichlet ghost);
+  * every face of such a problem is either sound-hard or absorbing, and a
+    corner node takes the ghost rows of each of its axes.
 
 Parity: pinned by the tests (plane-wave consistency of the interior stencil,
 second-order consistency of the 1D stretched operator against its analytic
@@ -90,6 +101,61 @@ def laplacian_pml(n, L, h, omega, C: float = 20.0, power: int = 2) -> sp.csr_mat
     return lap.tocsr()
 
 
+def ghost_axis_matrix(n: int, h: float) -> sp.csr_matrix:
+    """n x n second difference of one axis whose end nodes are unknowns with a
+    ghost node beyond each end.  Eliminating the ghost with the central
+    difference of the face's normal derivative, du/dn = q u at the end node
+    (q = 0 sound-hard, q = i k absorbing), gives u_ghost = u_inner + 2 h q u_end,
+    so the end row (u_ghost - 2 u_end + u_inner)/h^2 becomes
+    (2 u_inner - 2 u_end)/h^2 + (2 q/h) u_end.  This matrix holds the part
+    without q; the absorbing part is absorbing_boundary_diag."""
+    rows, cols, vals = [], [], []
+    w = 1.0 / (h * h)
+    for i in range(n):
+        rows.append(i); cols.append(i); vals.append(-2.0 * w)
+        if i > 0:
+            rows.append(i); cols.append(i - 1); vals.append(2.0 * w if i == n - 1 else w)
+        if i < n - 1:
+            rows.append(i); cols.append(i + 1); vals.append(2.0 * w if i == 0 else w)
+    return sp.csr_matrix((np.array(vals, dtype=np.complex128), (rows, cols)), shape=(n, n))
+
+
+def absorbing_boundary_diag(prob) -> np.ndarray:
+    """Per node, flattened: the sum over the absorbing faces the node lies on
+    of (2/h) i k with k = omega/c at the node (the q u_end term of the ghost
+    elimination, q = i k).  Sound-hard faces (prob.hard_faces, pairs (axis,
+    side)) contribute nothing."""
+    n = tuple(prob.n)
+    c = prob.c_array()
+    k = prob.omega / c  # shape n[::-1]
+    total = np.zeros(tuple(reversed(n)), dtype=np.complex128)
+    hard = set(tuple(f) for f in prob.hard_faces)
+    for ax, nd in enumerate(n):
+        for side, idx in ((0, 0), (1, nd - 1)):
+            if (ax, side) in hard:
+                continue
+            sl = [slice(None)] * len(n)
+            sl[len(n) - 1 - ax] = idx
+            total[tuple(sl)] += (2.0 / prob.h) * 1j * k[tuple(sl)]
+    return total.ravel()
+
+
+def ghost_similarity(prob) -> np.ndarray:
+    """Diagonal w of the similarity that symmetrises the ghost rows: 1/2 at an
+    axis' end nodes, 1 elsewhere, multiplied over the axes.  W^{1/2} A W^{-1/2}
+    has a real symmetric second difference (end-row weight 2/h^2 against 1/h^2
+    becomes sqrt 2/h^2 both ways) plus a diagonal with Im >= 0."""
+    n = tuple(prob.n)
+    w = np.ones(tuple(reversed(n)))
+    for ax, nd in enumerate(n):
+        wa = np.ones(nd)
+        wa[0] = wa[-1] = 0.5
+        sh = [1] * len(n)
+        sh[len(n) - 1 - ax] = nd
+        w = w * wa.reshape(sh)
+    return w.ravel()
+
+
 def cap_potential(prob) -> np.ndarray:
     """W/c^2 per node, flattened (x fastest): 2 omega^2 times the sum over axes
     of the layer profile at the node's coordinate."""
@@ -105,9 +171,20 @@ def cap_potential(prob) -> np.ndarray:
 
 def _absorber(prob) -> str:
     a = getattr(prob, "absorber", "pml")
-    if a not in ("pml", "cap"):
-        raise ValueError("absorber must be 'pml' or 'cap'")
+    if a not in ("pml", "cap", "abc"):
+        raise ValueError("absorber must be 'pml', 'cap' or 'abc'")
     return a
+
+
+def _ghost_laplacian(n, h) -> sp.csr_matrix:
+    n = tuple(n)
+    N = int(np.prod(n))
+    lap = sp.csr_matrix((N, N), dtype=np.complex128)
+    for ax, nd in enumerate(n):
+        inner = int(np.prod(n[:ax]))
+        outer = int(np.prod(n[ax + 1:]))
+        lap = lap + sp.kron(sp.identity(outer), sp.kron(ghost_axis_matrix(nd, h), sp.identity(inner)))
+    return lap.tocsr()
 
 
 def inverse_c2(prob) -> np.ndarray:
@@ -118,9 +195,13 @@ def inverse_c2(prob) -> np.ndarray:
 
 def helmholtz(prob, shift: float = 0.0) -> sp.csr_matrix:
     """A_s = omega^2 (1 + i s) D + Lap_PML; shift = 0 gives A itself.  With the
-    absorbing potential: A_s = omega^2 (1 + i s) D + Lap + i W/c^2."""
+    absorbing potential: A_s = omega^2 (1 + i s) D + Lap + i W/c^2.  With
+    boundary conditions (sound-hard and first-order absorbing faces, ghost
+    points): A_s = omega^2 (1 + i s) D + Lap_ghost + absorbing_boundary_diag."""
     D = inverse_c2(prob)
     diag = prob.omega ** 2 * (1 + 1j * shift) * D
+    if _absorber(prob) == "abc":
+        return (_ghost_laplacian(prob.n, prob.h) + sp.diags(diag + absorbing_boundary_diag(prob))).tocsr()
     if _absorber(prob) == "cap":
         lap = laplacian_pml(prob.n, 0, prob.h, prob.omega)
         diag = diag + 1j * cap_potential(prob)
@@ -142,6 +223,8 @@ def apply_rows(prob, shift: float, x: np.ndarray, points: np.ndarray) -> np.ndar
     d = len(n)
     h, om, L = prob.h, prob.omega, prob.layer
     cap = _absorber(prob) == "cap"
+    abc = _absorber(prob) == "abc"
+    hard = set(tuple(f) for f in getattr(prob, "hard_faces", ()))
     D = inverse_c2(prob)
     out = np.empty(len(points), dtype=np.complex128)
     strides = [int(np.prod(n[:ax])) for ax in range(d)]
@@ -150,6 +233,17 @@ def apply_rows(prob, shift: float, x: np.ndarray, points: np.ndarray) -> np.ndar
         acc = om * om * (1 + 1j * shift) * D[p] * x[p]
         for ax in range(d):
             i = idx[ax]
+            if abc:
+                # ghost rows at the ends; the absorbing faces add (2/h) i omega/c
+                wl = 0.0 if i == 0 else (2.0 if i == n[ax] - 1 else 1.0) / (h * h)
+                wr = 0.0 if i == n[ax] - 1 else (2.0 if i == 0 else 1.0) / (h * h)
+                um = x[p - strides[ax]] if i > 0 else 0.0
+                up = x[p + strides[ax]] if i < n[ax] - 1 else 0.0
+                acc += wl * um + wr * up - (2.0 / (h * h)) * x[p]
+                for side, end in ((0, 0), (1, n[ax] - 1)):
+                    if i == end and (ax, side) not in hard:
+                        acc += (2.0 / h) * 1j * om * np.sqrt(D[p]) * x[p]
+                continue
             xi = i * h
             sig = pml_sigma(np.array([xi - h / 2, xi, xi + h / 2]), n[ax], L, h, om, prob.pml_C, prob.pml_power)
             if cap:

@@ -30,7 +30,7 @@ MXP_ERR_UNSUPPORTED = -6
 
 MXP_C64, MXP_C128, MXP_F32, MXP_F64 = 0, 1, 2, 3
 MXP_PREC_FP64, MXP_PREC_MIXED = 0, 1
-MXP_ABSORB_PML, MXP_ABSORB_CAP = 0, 1
+MXP_ABSORB_PML, MXP_ABSORB_CAP, MXP_ABSORB_ABC = 0, 1, 2
 MXP_INNER_GMRES, MXP_INNER_FIXED_POINT, MXP_INNER_PSI2_GMRES, MXP_INNER_PSI2_FIXED_POINT = 0, 1, 2, 3
 
 
@@ -53,6 +53,7 @@ class mxp_grid_desc(ctypes.Structure):
         ("c_dtype", ctypes.c_int),
         ("c_const", ctypes.c_double),
         ("absorber", ctypes.c_int32),
+        ("hard", (ctypes.c_int32 * 2) * 3),
     ]
 
 
@@ -127,6 +128,7 @@ class mxp_schedule(ctypes.Structure):
         ("half_width", ctypes.c_double),
         ("box", ctypes.c_double * 4),
         ("trunc_bound", ctypes.c_double),
+        ("similarity_cond", ctypes.c_double),
         ("amplification", ctypes.c_double),
         ("coef", ctypes.c_double * 1024),
         ("coef_psi", ctypes.c_double * 1024),
@@ -249,7 +251,10 @@ def grid_desc(prob, c_host: Optional[np.ndarray] = None) -> mxp_grid_desc:
         d.layer[a][1] = L
     d.pml_C = prob.pml_C
     d.pml_power = prob.pml_power
-    d.absorber = {"pml": MXP_ABSORB_PML, "cap": MXP_ABSORB_CAP}[getattr(prob, "absorber", "pml")]
+    d.absorber = {"pml": MXP_ABSORB_PML, "cap": MXP_ABSORB_CAP,
+                  "abc": MXP_ABSORB_ABC}[getattr(prob, "absorber", "pml")]
+    for a, side in getattr(prob, "hard_faces", ()):
+        d.hard[a][side] = 1
     c = c_host if c_host is not None else prob.c
     if c is None:
         d.c = None

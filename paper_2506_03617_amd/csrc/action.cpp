@@ -17,8 +17,32 @@
 
 namespace mxp {
 
-static void build_diag(mxp_problem* P, double shift, cd centre, DiagTables& dt) {
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t diag_table_bytes(const GridInfo& g) {
+    const size_t total = size_t(g.n[0] + g.n[1] + g.n[2]);
+    const size_t tot2 = g.dim == 2 ? 3 * size_t(g.n[0] + g.n[1]) : 0;
+    return align256(total * sizeof(cpx<double>)) + align256(total * sizeof(cpx<float>)) +
+           align256(tot2 * sizeof(cpx<double>)) + align256(tot2 * sizeof(cpx<float>));
+}
+
+// The diagonal tables of one (shift, centre) pair.  They go to buffers the
+// tables own (ext == nullptr), or to `ext`, a device region of at least
+// diag_table_bytes(P->g) bytes that the caller owns, uploaded on stream s.
+void build_diag(mxp_problem* P, double shift, cd centre, DiagTables& dt, void* ext, hipStream_t s) {
     const GridInfo& g = P->g;
+    size_t ext_off = 0;
+    auto place = [&](DevMem& dm, const void* src, size_t bytes) -> void* {
+        if (!ext) {
+            dm.ensure(bytes);
+            HIP_CHECK(hipMemcpy(dm.p, src, bytes, hipMemcpyHostToDevice));
+            return dm.p;
+        }
+        void* p = static_cast<unsigned char*>(ext) + ext_off;
+        ext_off += align256(bytes);
+        HIP_CHECK(hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, s));
+        return p;
+    };
     const cd share = (cd(g.omega * g.omega, g.omega * g.omega * shift) * P->Dref - centre) / double(g.dim);
     size_t total = 0;
     for (int d = 0; d < 3; ++d) total += size_t(g.n[d]);
@@ -80,31 +104,29 @@ static void build_diag(mxp_problem* P, double shift, cd centre, DiagTables& dt) 
                 o += g.n[d];
             }
         }
-        dt.fmem64.ensure(tot2 * sizeof(cpx<double>));
-        dt.fmem32.ensure(tot2 * sizeof(cpx<float>));
-        HIP_CHECK(hipMemcpy(dt.fmem64.p, s64.data(), tot2 * sizeof(cpx<double>), hipMemcpyHostToDevice));
-        HIP_CHECK(hipMemcpy(dt.fmem32.p, s32.data(), tot2 * sizeof(cpx<float>), hipMemcpyHostToDevice));
+        cpx<double>* f64 = static_cast<cpx<double>*>(place(dt.fmem64, s64.data(), tot2 * sizeof(cpx<double>)));
+        cpx<float>* f32 = static_cast<cpx<float>*>(place(dt.fmem32, s32.data(), tot2 * sizeof(cpx<float>)));
         for (int d = 0; d < 2; ++d)
             for (int q = 0; q < 3; ++q) {
-                dt.f64[d][q] = dt.fmem64.as<cpx<double>>() + fo[d][q];
-                dt.f32[d][q] = dt.fmem32.as<cpx<float>>() + fo[d][q];
+                dt.f64[d][q] = f64 + fo[d][q];
+                dt.f32[d][q] = f32 + fo[d][q];
             }
     }
-    dt.mem64.ensure(total * sizeof(cpx<double>));
-    dt.mem32.ensure(total * sizeof(cpx<float>));
-    HIP_CHECK(hipMemcpy(dt.mem64.p, h64.data(), total * sizeof(cpx<double>), hipMemcpyHostToDevice));
-    HIP_CHECK(hipMemcpy(dt.mem32.p, h32.data(), total * sizeof(cpx<float>), hipMemcpyHostToDevice));
+    cpx<double>* m64 = static_cast<cpx<double>*>(place(dt.mem64, h64.data(), total * sizeof(cpx<double>)));
+    cpx<float>* m32 = static_cast<cpx<float>*>(place(dt.mem32, h32.data(), total * sizeof(cpx<float>)));
     for (int d = 0; d < 3; ++d) {
-        dt.g64[d] = dt.mem64.as<cpx<double>>() + offs[d];
-        dt.g32[d] = dt.mem32.as<cpx<float>>() + offs[d];
+        dt.g64[d] = m64 + offs[d];
+        dt.g32[d] = m32 + offs[d];
     }
+    // the host tables go out of scope: the copies must have read them
+    if (ext) HIP_CHECK(hipStreamSynchronize(s));
 }
 
 const DiagTables& plain_diag(mxp_problem* P, double shift) {
     auto it = P->plain_diag.find(shift);
     if (it != P->plain_diag.end()) return *it->second;
     auto dt = std::make_unique<DiagTables>();
-    build_diag(P, shift, cd(0.0, 0.0), *dt);
+    build_diag(P, shift, cd(0.0, 0.0), *dt, nullptr, nullptr);
     const DiagTables& ref = *dt;
     P->plain_diag.emplace(shift, std::move(dt));
     return ref;
@@ -117,7 +139,7 @@ const Sched& get_sched(mxp_problem* P, double t, double shift, mxp_precision pre
     if (it != P->scheds.end()) return *it->second;
     auto sc = std::make_unique<Sched>();
     design_schedule(P->g, t, shift, prec, &sc->s, forceS, forcem);
-    build_diag(P, shift, cd(sc->s.centre_re, sc->s.centre_im), sc->diag);
+    build_diag(P, shift, cd(sc->s.centre_re, sc->s.centre_im), sc->diag, nullptr, nullptr);
     sc->t = t;
     sc->prec = prec;
     const Sched& ref = *sc;
@@ -138,6 +160,7 @@ static StencilArgs<R> base_args(mxp_problem* P, double shift, const DiagTables& 
     for (int d = 0; d < 3; ++d) {
         a.alpha[d] = t->alpha[d];
         a.beta[d] = t->beta[d];
+        a.abc[d] = t->abc[d];
         if constexpr (sizeof(R) == 8) a.gamma[d] = diag.g64[d]; else a.gamma[d] = diag.g32[d];
     }
     if (g.homogeneous) {
@@ -298,6 +321,10 @@ static ChebPassArgs<R> pass_base(mxp_problem* P, const StencilArgs<R>& st, const
     a.D = st.D;
     a.Dconst = st.Dconst;
     a.Dref = st.Dref;
+    const DevTables<R>* t;
+    if constexpr (sizeof(R) == 8) t = &P->t64; else t = &P->t32;
+    a.abx = t->abc_h2[0];
+    a.aby = t->abc_h2[1];
     const double h2 = P->g.h * P->g.h;
     a.kD = {R(double(st.kD.re) * h2), R(double(st.kD.im) * h2)};
     a.ix0 = dt.ix0;
@@ -360,31 +387,28 @@ static void cheb_series_fused(mxp_problem* P, const Emit<R>& em, const StencilAr
 template <typename R>
 static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s);
 
-// y = exp(i t A_s) x, psi_1(i t A_s) x or psi_2(i t A_s) x (fn), precision R.
-// x and y distinct device vectors of precision R; buffers from workspace ws.
+// Device buffers of one action.
 template <typename R>
-static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched& sd, double t, double shift,
-                   int fn, const cpx<R>* x, cpx<R>* y, int64_t* steps) {
+struct ActBufs {
+    cpx<R>* w[6];
+    cpx<R>* pbuf;
+    cpx<R>* y1;
+};
+
+// y = exp(i t A_s) x, psi_1(i t A_s) x or psi_2(i t A_s) x (fn), precision R,
+// on the device buffers B (w[0..5] always, pbuf for psi_1 and psi_2, y1 for
+// psi_2), with the 2D pass tiles tc.  x and y: distinct device vectors of
+// precision R, neither of them one of B's buffers.
+template <typename R>
+static void action_on(mxp_problem* P, const ActBufs<R>& B, const TileCfg& tc, const Emit<R>& em, const Sched& sd,
+                      double t, double shift, int fn, const cpx<R>* x, cpx<R>* y, int64_t* steps) {
     if (fn < ACT_EXP || fn > ACT_PSI2) fail(MXP_ERR_INVALID_ARG, "unknown matrix function");
     const bool psi = fn == ACT_PSI1;
     const mxp_schedule& sc = sd.s;
-    const int64_t n = npts(P);
-    DevMem* W = act_buffers<R>(ws);
-    for (int q = 0; q < 7; ++q) W[q].ensure(size_t(n) * sizeof(cpx<R>));
-    cpx<R>* w[6];
-    for (int q = 0; q < 6; ++q) w[q] = W[q].as<cpx<R>>();
-    cpx<R>* pbuf = W[6].as<cpx<R>>();
+    cpx<R>* const* w = B.w;
+    cpx<R>* pbuf = B.pbuf;
     const StencilArgs<R> base = base_args<R>(P, shift, sd.diag);
     const bool fused = (P->g.dim == 2);
-    TileCfg tc;
-    if (fused) {
-        TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
-        if (slot.K == 0) {
-            if (em.rec) fail(MXP_ERR_HIP, "tiles must be tuned before a batched action");
-            tune_tiles<R>(P, ws, sd, em.s);
-        }
-        tc = slot;
-    }
     const int S = sc.S;
     // Scratch for one series: five buffers other than its input (four for the
     // passes, one for the output); the unfused path uses two of them.
@@ -403,7 +427,7 @@ static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched
         pick(xin, b, &spare);
         if (fused) {
             cheb_series_fused<R>(P, em, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
-        } else if (P->g.dim == 3 && P->tiles[sizeof(R) == 4 ? 1 : 0].K == 2) {
+        } else if (P->g.dim == 3 && P->tiles[sizeof(R) == 4 ? 1 : 0].K == 2 && !P->g.abc_per_node()) {
             cheb_series3d<R>(em, base, sc, coef, m, xin, out, b, post, add, steps);
         } else {
             cheb_series<R>(em, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
@@ -429,8 +453,7 @@ static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched
             series(sd.coef_psi2.data(), sd.m_psi2, x, y, cd(it2, 0.0), nullptr);
             return;
         }
-        W[9].ensure(size_t(n) * sizeof(cpx<R>));
-        cpx<R>* y1 = W[9].as<cpx<R>>();
+        cpx<R>* y1 = B.y1;
         series(sd.coef_psi2.data(), sd.m_psi2, x, y1, cd(1.0, 0.0), nullptr);
         series(sc.coef_psi, sc.m_psi, x, pbuf, cd(1.0, 0.0), nullptr);  // g_1 = H_1
         const cpx<R>* hk = pbuf;
@@ -469,6 +492,31 @@ static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched
         series(sc.coef, sc.m, xcur, out, post, add);
         xcur = out;
     }
+}
+
+// The same action with buffers from workspace ws (the 2D tiles are tuned at
+// the problem's first action).
+template <typename R>
+static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched& sd, double t, double shift,
+                   int fn, const cpx<R>* x, cpx<R>* y, int64_t* steps) {
+    const int64_t n = npts(P);
+    DevMem* W = act_buffers<R>(ws);
+    for (int q = 0; q < 7; ++q) W[q].ensure(size_t(n) * sizeof(cpx<R>));
+    if (fn == ACT_PSI2) W[9].ensure(size_t(n) * sizeof(cpx<R>));
+    ActBufs<R> B;
+    for (int q = 0; q < 6; ++q) B.w[q] = W[q].as<cpx<R>>();
+    B.pbuf = W[6].as<cpx<R>>();
+    B.y1 = W[9].as<cpx<R>>();
+    TileCfg tc;
+    if (P->g.dim == 2) {
+        TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
+        if (slot.K == 0) {
+            if (em.rec) fail(MXP_ERR_HIP, "tiles must be tuned before a batched action");
+            tune_tiles<R>(P, ws, sd, em.s);
+        }
+        tc = slot;
+    }
+    action_on<R>(P, B, tc, em, sd, t, shift, fn, x, y, steps);
 }
 
 // Times candidate tile configurations of the fused 2D pass on this problem's
@@ -691,6 +739,23 @@ void apply_A(mxp_problem* P, hipStream_t s, double shift, mxp_dtype dtype, const
         a.b1 = static_cast<const cpx<float>*>(x);
         a.out = static_cast<cpx<float>*>(y);
         launch_stencil(a, s);
+    } else {
+        fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
+    }
+}
+
+void apply_action_on(mxp_problem* P, void* const bufs[6], const TileCfg& tc, hipStream_t s, const Sched& sd,
+                     double t, double shift, mxp_dtype dtype, const void* x, void* y, int64_t* steps) {
+    if (dtype == MXP_C128) {
+        ActBufs<double> B{};
+        for (int q = 0; q < 6; ++q) B.w[q] = static_cast<cpx<double>*>(bufs[q]);
+        action_on<double>(P, B, tc, Emit<double>{s, nullptr}, sd, t, shift, ACT_EXP,
+                          static_cast<const cpx<double>*>(x), static_cast<cpx<double>*>(y), steps);
+    } else if (dtype == MXP_C64) {
+        ActBufs<float> B{};
+        for (int q = 0; q < 6; ++q) B.w[q] = static_cast<cpx<float>*>(bufs[q]);
+        action_on<float>(P, B, tc, Emit<float>{s, nullptr}, sd, t, shift, ACT_EXP,
+                         static_cast<const cpx<float>*>(x), static_cast<cpx<float>*>(y), steps);
     } else {
         fail(MXP_ERR_INVALID_ARG, "dtype must be MXP_C64 or MXP_C128");
     }

@@ -51,6 +51,32 @@ static void upload_tables(mxp_problem* P, DevMem& mem, DevTables<R>& t) {
         t.beta[d] = base + offs[d][1];
         t.gamma[d] = base + offs[d][2];
     }
+    if (!g.abc_per_node()) return;
+    // absorbing faces with a varying speed: 2 omega/h at the absorbing end
+    // nodes of each axis (the kernels multiply by sqrt(D_p)), and times h^2
+    DevMem& am = sizeof(R) == 8 ? P->abc64 : P->abc32;
+    const size_t na = size_t(g.n[0] + g.n[1] + g.n[2]);
+    std::vector<R> ha(2 * na, R(0));
+    size_t o = 0;
+    for (int d = 0; d < 3; ++d) {
+        if (d < g.dim) {
+            const AxisLayer ax = g.axis(d);
+            const double wgt = 2.0 * g.omega / g.h;
+            if (ax.abs_lo) ha[o] += R(wgt);
+            if (ax.abs_hi) ha[o + size_t(g.n[d]) - 1] += R(wgt);
+            if (ax.abs_lo) ha[na + o] += R(wgt * g.h * g.h);
+            if (ax.abs_hi) ha[na + o + size_t(g.n[d]) - 1] += R(wgt * g.h * g.h);
+        }
+        o += size_t(g.n[d]);
+    }
+    am.ensure(ha.size() * sizeof(R));
+    HIP_CHECK(hipMemcpy(am.p, ha.data(), ha.size() * sizeof(R), hipMemcpyHostToDevice));
+    o = 0;
+    for (int d = 0; d < 3; ++d) {
+        t.abc[d] = am.as<R>() + o;
+        t.abc_h2[d] = am.as<R>() + na + o;
+        o += size_t(g.n[d]);
+    }
 }
 
 void context_info(const mxp_context* ctx, int* device, hipStream_t* stream) {
@@ -198,7 +224,7 @@ mxp_status mxp_solve_opts_default(const mxp_grid_desc* desc, mxp_solve_opts* out
         out->use_graphs = 0;
         out->inner_solver = 0;
         out->fp64_below = 0.0;
-        out->fp64_first = 0;
+        out->fp64_first = 2;
         return MXP_OK;
     });
 }
@@ -321,6 +347,8 @@ mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, 
         if (precision != MXP_PREC_FP64 && precision != MXP_PREC_MIXED) fail(MXP_ERR_INVALID_ARG, "unknown precision");
         if (K < 0 || K > kMaxFused || (NX != 1 && NX != 2) || Ly < 1 || (K > 0 && NX * 64 - 2 * K <= 0))
             fail(MXP_ERR_INVALID_ARG, "tiles: K in 0..8, NX in {1, 2}, Ly >= 1");
+        if (K == 2 && prob->g.dim == 3 && prob->g.abc_per_node())
+            fail(MXP_ERR_UNSUPPORTED, "two-level 3D passes do not carry the absorbing-face term");
         TileCfg& t = prob->tiles[precision == MXP_PREC_MIXED ? 1 : 0];
         (void)hipStreamSynchronize(prob->ctx->stream);
         prob->ws.drop_graphs();  // captured actions bake in the tile shape

@@ -94,6 +94,10 @@ __device__ __forceinline__ cpx<R> sload(const cpx<R>* p, int idx) {
     const __attribute__((address_space(4))) R* q = (const __attribute__((address_space(4))) R*)(p);
     return {q[2 * idx], q[2 * idx + 1]};
 }
+template <typename R>
+__device__ __forceinline__ R sload_r(const R* p, int idx) {
+    return ((const __attribute__((address_space(4))) R*)(p))[idx];
+}
 
 // The fields of ChebPassArgs a pass reads, copied out of the kernel argument
 // (holding a reference to the argument would force it into scratch memory).
@@ -104,6 +108,7 @@ struct PassParams {
     const cpx<R>* by;
     const cpx<R>* gy;
     const R* D;
+    const R* aby;  // absorbing faces: h^2-scaled y weights (nullptr when absent)
     R Dconst, Dref, e3, post;
     cpx<R> kD;
     const cpx<R>* x;
@@ -123,6 +128,7 @@ struct PassParams {
         by = s.by;
         gy = s.gy;
         D = s.D;
+        aby = s.aby;
         Dconst = s.Dconst;
         Dref = s.Dref;
         e3 = s.e3;
@@ -161,6 +167,7 @@ struct Pass2D {
     bool cin[NX], cout[NX];
     uint32_t ccl[NX];                 // clamped column of each element
     cpx<R> axv[NX], bxv[NX], gxv[NX];
+    R abxv[NX];                       // absorbing faces: h^2-scaled x weights
     bool x_interior;
     cpx<R> Lw[K + 2][3][NX];          // level windows, slot = row mod 3
     cpx<R> P0[NX], P1[NX], PX[NX];    // row j+1, fetched one step ahead
@@ -296,7 +303,11 @@ struct Pass2D {
             Lw[1][sj][e] = csel(ok && !a.in1_zero, P1[e], zero);
             xs[slot_j * 64 * NX + lane * NX + e] = csel(ok, PX[e], zero);
             const R dd = (a.D_const ? a.Dconst : PD[e]) - a.Dref;
-            const cpx<R> dgv = {gxv[e].re + gyj.re + a.kD.re * dd, gxv[e].im + gyj.im + a.kD.im * dd};
+            cpx<R> dgv = {gxv[e].re + gyj.re + a.kD.re * dd, gxv[e].im + gyj.im + a.kD.im * dd};
+            if (a.aby) {  // absorbing faces: 2 i omega h sqrt(D_p) per face of the node
+                const R w = abxv[e] + sload_r(a.aby, __builtin_amdgcn_readfirstlane(rin ? j : 0));
+                if (w != R(0)) dgv.im += w * sqrt(PD[e]);
+            }
             dg[slot_j * 64 * NX + lane * NX + e] = dgv;
         }
         cpx<R> addv[NX];
@@ -408,6 +419,7 @@ __global__ __launch_bounds__(256) void k_cheb2d(ChebPassArgs<R> a) {
         ps.axv[e] = csel(ps.cin[e], a.ax[ps.ccl[e]], zero);
         ps.bxv[e] = csel(ps.cin[e], a.bx[ps.ccl[e]], zero);
         ps.gxv[e] = csel(ps.cin[e], a.gx[ps.ccl[e]], zero);
+        ps.abxv[e] = (a.abx && ps.cin[e]) ? a.abx[ps.ccl[e]] : R(0);
     }
     // interior strip: every column has unit neighbour weights
     ps.x_interior = (X0 - K >= a.ix0) && (X0 - K + 64 * NX <= a.ix1);

@@ -38,6 +38,10 @@ struct DevTables {
     cpx<R>* alpha[3] = {nullptr, nullptr, nullptr};
     cpx<R>* beta[3] = {nullptr, nullptr, nullptr};
     cpx<R>* gamma[3] = {nullptr, nullptr, nullptr};
+    // first-order absorbing faces with a varying speed: per-axis weights
+    // 2 omega/h at absorbing end nodes, and the same times h^2 (2D passes)
+    R* abc[3] = {nullptr, nullptr, nullptr};
+    R* abc_h2[3] = {nullptr, nullptr, nullptr};
 };
 
 // Per-axis diagonal tables gamma_d + (kD * Dref - centre)/dim for one
@@ -152,7 +156,7 @@ struct mxp_problem {
     mxp_context ctx_copy;  // device, stream, verbosity: the problem outlives nothing it points to
     mxp_context* ctx;      // == &ctx_copy
     mxp::GridInfo g;
-    mxp::DevMem tables64, tables32, D64, D32;
+    mxp::DevMem tables64, tables32, D64, D32, abc64, abc32;
     mxp::DevTables<double> t64;
     mxp::DevTables<float> t32;
     std::map<std::tuple<double, double, int, int, int>, std::unique_ptr<mxp::Sched>> scheds;
@@ -249,6 +253,14 @@ void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x
 // y = f(i t A_s) x (f by ActFn) on vectors of dtype, in that precision.
 void apply_action(mxp_problem* P, Workspace& ws, hipStream_t s, const Sched& sd, double t, double shift, int fn,
                   mxp_dtype dtype, const void* x, void* y, int64_t* steps);
+// exp(i t A_s) x on caller-provided buffers: six device vectors of n values of
+// dtype (none of them x or y) and the 2D pass tiles tc (K > 0).
+void apply_action_on(mxp_problem* P, void* const bufs[6], const TileCfg& tc, hipStream_t s, const Sched& sd,
+                     double t, double shift, mxp_dtype dtype, const void* x, void* y, int64_t* steps);
+// Bytes of the diagonal tables of one schedule, and building them into buffers
+// the tables own (ext == nullptr) or into the caller's device region ext.
+size_t diag_table_bytes(const GridInfo& g);
+void build_diag(mxp_problem* P, double shift, cd centre, DiagTables& dt, void* ext, hipStream_t s);
 void action64_on(mxp_problem* P, Workspace& ws, hipStream_t s, const Sched& sc, double t, double shift, int fn,
                  mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps,
                  std::vector<StepRec<double>>* rec64 = nullptr, std::vector<StepRec<float>>* rec32 = nullptr);

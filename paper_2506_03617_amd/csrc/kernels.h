@@ -47,6 +47,10 @@ struct StencilArgs {
     const cpx<R>* b3;
     cpx<R>* out;
     int zc;  // 3D sweeps: z segment length (0 = chosen from the grid)
+    // first-order absorbing faces with a varying speed: per-axis weights
+    // 2 omega/h at the absorbing end nodes (0 elsewhere); the diagonal gains
+    // i (abc_x + abc_y + abc_z) sqrt(D_p).  nullptr when absent.
+    const R* abc[3];
 };
 
 template <typename R>
@@ -104,6 +108,11 @@ struct ChebPassArgs {
     const R* D;
     R Dconst, Dref;
     cpx<R> kD;
+    // absorbing faces with a varying speed: h^2-scaled per-axis weights (2 omega h
+    // at absorbing end nodes), the diagonal gains i (abx + aby) sqrt(D_p); nullptr
+    // when absent (D must then be given)
+    const R* abx;
+    const R* aby;
     const cpx<R>* x;
     const cpx<R>* in0;
     const cpx<R>* in1;

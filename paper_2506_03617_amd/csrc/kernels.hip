@@ -53,8 +53,13 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<R> a) {
     const cpx<R> c = v[p];
     cpx<R> diag = cadd(a.gamma[0][i], a.gamma[1][j]);
     if (DIM == 3) diag = cadd(diag, a.gamma[2][k]);
-    const R Dp = (a.D ? a.D[p] : a.Dconst) - a.Dref;
-    diag = cadd(diag, cscale(Dp, a.kD));
+    const R Draw = a.D ? a.D[p] : a.Dconst;
+    diag = cadd(diag, cscale(Draw - a.Dref, a.kD));
+    if (a.abc[0]) {  // absorbing faces: 2 i omega sqrt(D_p)/h per face the node lies on
+        R w = a.abc[0][i] + a.abc[1][j];
+        if (DIM == 3) w += a.abc[2][k];
+        if (w != R(0)) diag.im += w * sqrt(Draw);
+    }
     cpx<R> s = cmul(diag, c);
     if (i > 0) s = cfma(a.alpha[0][i], v[p - 1], s);
     if (i < a.n0 - 1) s = cfma(a.beta[0][i], v[p + 1], s);
@@ -82,6 +87,10 @@ template <typename R>
 __device__ __forceinline__ cpx<R> sload(const cpx<R>* p, int64_t idx) {
     const __attribute__((address_space(4))) R* q = (const __attribute__((address_space(4))) R*)(p);
     return {q[2 * idx], q[2 * idx + 1]};
+}
+template <typename R>
+__device__ __forceinline__ R sload_r(const R* p, int64_t idx) {
+    return ((const __attribute__((address_space(4))) R*)(p))[idx];
 }
 
 // Loads and stores through the global address space.  Pointers read from
@@ -208,6 +217,9 @@ __device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGe
     const cpx<R> wxm = keep_if(col_ok && i > 0, gload(a.alpha[0], ic));
     const cpx<R> wxp = keep_if(col_ok && i < a.n0 - 1, gload(a.beta[0], ic));
     const cpx<R> gx = gload(a.gamma[0], ic);
+    // absorbing faces with a varying speed (uniform test)
+    const bool abc_on = a.abc[0] != nullptr;
+    const R abx = abc_on ? gload(a.abc[0], ic) : R(0);
     // lanes 0 and 63 read their outer x-neighbour from memory (offset 0 when it is a ghost)
     const int64_t eoff = (lane == 0 && ic > 0) ? -1 : ((lane == 63 && ic < a.n0 - 1) ? 1 : 0);
     // row offsets, clamped to the grid
@@ -246,6 +258,7 @@ __device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGe
         hp = keep_if(has_hi, hp);
         const cpx<R> az = sload(a.alpha[2], k), bz = sload(a.beta[2], k);
         const cpx<R> gxz = cadd(gx, sload(a.gamma[2], k));
+        const R abxz = abc_on ? abx + sload_r(a.abc[2], k) : R(0);
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
             next[r] = keep_if(up, next[r]);
@@ -262,6 +275,10 @@ __device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGe
             if constexpr (HD) Draw = Dv[r];
             cpx<R> diag = cadd(gxz, sload(a.gamma[1], j));
             diag = cadd(diag, cscale(Draw - a.Dref, a.kD));
+            if (abc_on) {  // 2 i omega sqrt(D_p)/h per absorbing face of the node
+                const R w = abxz + sload_r(a.abc[1], j);
+                if (w != R(0)) diag.im += w * sqrt(Draw);
+            }
             cpx<R> s = cmul(diag, cur[r]);
             s = cfma(wxm, xm, s);
             s = cfma(wxp, xp, s);

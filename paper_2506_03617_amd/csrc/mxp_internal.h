@@ -1,6 +1,7 @@
 // Internal declarations of the MatExPre library (not part of the C ABI).
 #pragma once
 
+#include <cmath>
 #include <complex>
 #include <cstdint>
 #include <stdexcept>
@@ -31,14 +32,21 @@ struct AxisLayer {
     int32_t lo, hi;
     double h, omega, C;
     int32_t power;
-    int32_t absorber;  // MXP_ABSORB_PML or MXP_ABSORB_CAP
+    int32_t absorber;  // MXP_ABSORB_PML, MXP_ABSORB_CAP or MXP_ABSORB_ABC
+    // MXP_ABSORB_ABC: the end faces that absorb (the others are sound-hard),
+    // and omega/c when c is constant (the absorbing term is then per axis), else 0
+    bool abs_lo = false, abs_hi = false;
+    double kc = 0.0;
     // the layer profile sigma(x) = C/(delta omega) (dist/delta)^power
     double sigma(double x) const;
     // imaginary part of the coordinate stretch (zero for the potential)
     double stretch(double x) const { return absorber == MXP_ABSORB_PML ? sigma(x) : 0.0; }
 };
 
-// Per-axis three-point coefficients of (1/s) d/dx((1/s) du/dx):
+// Per-axis three-point coefficients of (1/s) d/dx((1/s) du/dx), or with
+// MXP_ABSORB_ABC of the second difference with ghost-point end rows (weight
+// 2/h^2 on the inner neighbour, none outside, and with constant c the
+// absorbing term 2 i omega/(c h) of an absorbing end in gamma):
 //   (L u)_i = alpha_i u_{i-1} + beta_i u_{i+1} + gamma_i u_i,
 //   alpha_i = 1/(s_i s_{i-1/2} h^2), beta_i = 1/(s_i s_{i+1/2} h^2),
 //   gamma_i = -(alpha_i + beta_i) + i 2 omega^2 sigma(x_i) (the last term
@@ -56,13 +64,25 @@ struct GridInfo {
     int32_t pml_power;
     int32_t absorber;
     int32_t layer[3][2];
+    int32_t hard[3][2];  // MXP_ABSORB_ABC: sound-hard faces
     bool homogeneous;
     double c_const;
     double dmin, dmax;  // range of D = 1/c^2
     int64_t npts() const { return n[0] * n[1] * n[2]; }
     AxisLayer axis(int d) const {
-        return AxisLayer{n[d], layer[d][0], layer[d][1], h, omega, pml_C, pml_power, absorber};
+        AxisLayer a{n[d], layer[d][0], layer[d][1], h, omega, pml_C, pml_power, absorber};
+        if (absorber == MXP_ABSORB_ABC) {
+            a.abs_lo = hard[d][0] == 0;
+            a.abs_hi = hard[d][1] == 0;
+            a.kc = homogeneous ? omega / c_const : 0.0;
+        }
+        return a;
     }
+    // MXP_ABSORB_ABC with a varying c: the absorbing term 2 i omega sqrt(D_p)/h
+    // is per node and the kernels add it from per-axis tables
+    bool abc_per_node() const { return absorber == MXP_ABSORB_ABC && !homogeneous; }
+    // condition number of the diagonal similarity that symmetrises the ghost rows
+    double similarity_cond() const { return absorber == MXP_ABSORB_ABC ? std::pow(std::sqrt(2.0), dim) : 1.0; }
 };
 
 // Checks the description; fills everything except dmin/dmax when c is given.

@@ -48,6 +48,18 @@ AxisTables build_axis_tables(const AxisLayer& ax) {
     t.beta.resize(ax.n);
     t.gamma.resize(ax.n);
     const double h2 = ax.h * ax.h;
+    if (ax.absorber == MXP_ABSORB_ABC) {
+        // ghost-point end rows (Section 4.3.4): u_ghost = u_inner + 2 h q u_end
+        // with q = i omega/c (absorbing) or 0 (sound-hard)
+        for (int64_t i = 0; i < ax.n; ++i) {
+            t.alpha[i] = i == 0 ? 0.0 : (i == ax.n - 1 ? 2.0 : 1.0) / h2;
+            t.beta[i] = i == ax.n - 1 ? 0.0 : (i == 0 ? 2.0 : 1.0) / h2;
+            t.gamma[i] = -2.0 / h2;
+        }
+        if (ax.abs_lo) t.gamma[0] += cd(0.0, 2.0 * ax.kc / ax.h);
+        if (ax.abs_hi) t.gamma[ax.n - 1] += cd(0.0, 2.0 * ax.kc / ax.h);
+        return t;
+    }
     for (int64_t i = 0; i < ax.n; ++i) {
         const double x = i * ax.h;
         const cd s0(1.0, ax.stretch(x));
@@ -80,8 +92,8 @@ GridInfo validate_grid(const mxp_grid_desc* d) {
         fail(MXP_ERR_INVALID_ARG, "omega must be positive and finite");
     if (!(d->pml_C >= 0) || !std::isfinite(d->pml_C)) fail(MXP_ERR_INVALID_ARG, "pml_C must be >= 0");
     if (d->pml_power < 1 || d->pml_power > 8) fail(MXP_ERR_INVALID_ARG, "pml_power must be in 1..8");
-    if (d->absorber != MXP_ABSORB_PML && d->absorber != MXP_ABSORB_CAP)
-        fail(MXP_ERR_INVALID_ARG, "absorber must be MXP_ABSORB_PML or MXP_ABSORB_CAP");
+    if (d->absorber != MXP_ABSORB_PML && d->absorber != MXP_ABSORB_CAP && d->absorber != MXP_ABSORB_ABC)
+        fail(MXP_ERR_INVALID_ARG, "absorber must be MXP_ABSORB_PML, MXP_ABSORB_CAP or MXP_ABSORB_ABC");
     g.h = d->h;
     g.omega = d->omega;
     g.pml_C = d->pml_C;
@@ -92,7 +104,10 @@ GridInfo validate_grid(const mxp_grid_desc* d) {
             int32_t L = (a < g.dim) ? d->layer[a][s] : 0;
             if (L < 0 || (a < g.dim && 2 * int64_t(L) >= g.n[a]))
                 fail(MXP_ERR_INVALID_ARG, "layer widths must satisfy 0 <= layer < n/2");
+            if (g.absorber == MXP_ABSORB_ABC && L != 0)
+                fail(MXP_ERR_INVALID_ARG, "MXP_ABSORB_ABC takes no layer: every layer width must be 0");
             g.layer[a][s] = L;
+            g.hard[a][s] = (g.absorber == MXP_ABSORB_ABC && a < g.dim && d->hard[a][s] != 0) ? 1 : 0;
         }
     }
     const double npts = double(g.n[0]) * double(g.n[1]) * double(g.n[2]);
@@ -176,28 +191,50 @@ static void herm_tridiag_extremes(const std::vector<double>& a, const std::vecto
 }
 
 void fov_box(const GridInfo& g, double shift, double box[4]) {
+    // With ghost-point end rows (MXP_ABSORB_ABC) the box bounds the field of
+    // values of W^{1/2} A_s W^{-1/2}, w = 1/2 at each axis' end nodes, which
+    // makes the second difference symmetric; the schedule's error bound
+    // carries the similarity's condition number.  The absorbing term
+    // 2 i omega sqrt(D_p)/h of a varying c lies between its values at
+    // D_min and D_max.
     double re0 = 0, re1 = 0, im0 = 0, im1 = 0;
     for (int d = 0; d < g.dim; ++d) {
-        const AxisTables t = build_axis_tables(g.axis(d));
+        const AxisLayer ax = g.axis(d);
+        const AxisTables t = build_axis_tables(ax);
         const size_t n = t.gamma.size();
-        std::vector<double> ha(n), ka(n), he(n - 1), ke(n - 1);
+        const bool ghost = g.absorber == MXP_ABSORB_ABC;
+        std::vector<double> ha(n), ka(n), kb(n), he(n - 1), ke(n - 1);
         for (size_t i = 0; i < n; ++i) {
             ha[i] = t.gamma[i].real();
-            ka[i] = t.gamma[i].imag();
+            ka[i] = kb[i] = t.gamma[i].imag();
         }
+        if (g.abc_per_node()) {
+            const double a = 2.0 * g.omega / g.h;
+            if (ax.abs_lo) {
+                ka[0] += a * std::sqrt(g.dmin);
+                kb[0] += a * std::sqrt(g.dmax);
+            }
+            if (ax.abs_hi) {
+                ka[n - 1] += a * std::sqrt(g.dmin);
+                kb[n - 1] += a * std::sqrt(g.dmax);
+            }
+        }
+        auto w = [&](size_t i) { return ghost && (i == 0 || i == n - 1) ? 0.5 : 1.0; };
         for (size_t i = 0; i + 1 < n; ++i) {
             // entry (i, i+1) is beta_i, entry (i+1, i) is alpha_{i+1}
-            const cd up = t.beta[i], dn = t.alpha[i + 1];
+            const double r = std::sqrt(w(i) / w(i + 1));
+            const cd up = t.beta[i] * r, dn = t.alpha[i + 1] / r;
             he[i] = std::abs(0.5 * (up + std::conj(dn)));
             ke[i] = std::abs((up - std::conj(dn)) / cd(0.0, 2.0));
         }
-        double a0, a1, b0, b1;
+        double a0, a1, b0, b1, c0, c1;
         herm_tridiag_extremes(ha, he, &a0, &a1);
         herm_tridiag_extremes(ka, ke, &b0, &b1);
+        herm_tridiag_extremes(kb, ke, &c0, &c1);
         re0 += a0;
         re1 += a1;
-        im0 += b0;
-        im1 += b1;
+        im0 += std::min(b0, c0);
+        im1 += std::max(b1, c1);
     }
     const double w2 = g.omega * g.omega;
     box[0] = re0 + w2 * g.dmin;
@@ -411,7 +448,8 @@ void design_schedule(const GridInfo& g, double t, double shift, mxp_precision pr
              "times its width, e.g. a strong absorbing potential in a thin layer); use MXP_PREC_FP64");
     const double tol = fp64 ? 1e-12 : 1e-6;     // truncation bound of one action
     const double amp_max = fp64 ? 1e3 : 8.0;    // rounding amplification cap
-    const double crouzeix = 1.0 + std::sqrt(2.0);
+    // Crouzeix-Palencia, times the similarity's condition number with ghost rows
+    const double crouzeix = (1.0 + std::sqrt(2.0)) * g.similarity_cond();
     const int m_cap = 500;
     const Boundary bd = box_boundary(box);
     const double width = std::max(box[1] - box[0], 1e-300);
@@ -500,6 +538,7 @@ void design_schedule(const GridInfo& g, double t, double shift, mxp_precision pr
     out->half_width = hw;
     for (int i = 0; i < 4; ++i) out->box[i] = box[i];
     out->trunc_bound = crouzeix * bS * berr;
+    out->similarity_cond = g.similarity_cond();
     out->amplification = bamp;
 }
 
@@ -609,7 +648,7 @@ void design_psi2_series(const mxp_schedule& sc, double t, mxp_precision prec, st
     const bool fp64 = (prec == MXP_PREC_FP64);
     const double tol = fp64 ? 1e-12 : 1e-6;
     const double amp_max = fp64 ? 1e3 : 8.0;
-    const double crouzeix = 1.0 + std::sqrt(2.0);
+    const double crouzeix = (1.0 + std::sqrt(2.0)) * (sc.similarity_cond > 1.0 ? sc.similarity_cond : 1.0);
     const double tau = t / sc.S;
     const cd c0(sc.centre_re, sc.centre_im);
     const double hw = sc.half_width;

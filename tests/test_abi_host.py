@@ -281,3 +281,31 @@ def test_device_memory_is_taken_only_through_the_allocator():
                 if pat.search(line):
                     offenders.append(f"{os.path.basename(path)}:{k}: {line.strip()}")
     assert not offenders, offenders
+
+
+def test_absorbing_face_problems_validate_and_design():
+    """MXP_ABSORB_ABC: no layer allowed; the schedule's error bound carries the
+    condition number sqrt(2)^dim of the symmetrising similarity, and its box
+    contains the oracle operator's field of values after that similarity."""
+    import dataclasses
+    from oracle import operator as op
+    base = wl.small_problem((21, 17), layer=0, ppw=8.0, inhomogeneous=True, seed=2, name="abc-host")
+    prob = dataclasses.replace(base, absorber="abc", hard_faces=((1, 0),))
+    d = mxp.grid_desc(prob)
+    s = prob.default_shift()
+    sch = mxp.mxp_design_schedule(d, prob.default_t(), s, mxp.MXP_PREC_FP64)
+    assert abs(sch.similarity_cond - 2.0) <= 1e-15
+    A = op.helmholtz(prob, s).toarray()
+    w = np.sqrt(op.ghost_similarity(prob))
+    S = w[:, None] * A / w[None, :]
+    H = (S + S.conj().T) / 2
+    K = (S - S.conj().T) / 2j
+    re = np.linalg.eigvalsh(H)
+    im = np.linalg.eigvalsh(K)
+    span = sch.box[1] - sch.box[0]
+    assert sch.box[0] <= re[0] + 1e-9 * span and re[-1] <= sch.box[1] + 1e-9 * span
+    assert sch.box[2] <= im[0] + 1e-9 * span and im[-1] <= sch.box[3] + 1e-9 * span
+    bad = mxp.grid_desc(dataclasses.replace(prob, layer=3))
+    with pytest.raises(mxp.MxpError) as ei:
+        mxp.mxp_design_schedule(bad, prob.default_t(), s, mxp.MXP_PREC_FP64)
+    assert ei.value.status == mxp.MXP_ERR_INVALID_ARG

@@ -532,3 +532,101 @@ def test_krylov_matrix_function_invariant_space(ctx):
     zd = torch.zeros_like(xd)
     st, dim = mxp.mxp_apply_fn_krylov(P, True, t, s, 1e-12, 50, zd, yd)
     assert st == mxp.MXP_OK and dim == 0 and not to_host(yd).any()
+
+
+# Boundary conditions in place of a layer (Section 4.3.4): first-order
+# absorbing faces and a sound-hard face by ghost points.
+ABC_CASES = {
+    "2d-inh": dict(n=(67, 45), hard=((1, 0),), inh=True),
+    "2d-homog": dict(n=(67, 45), hard=((1, 0),), inh=False),
+    "3d-ragged": dict(n=(70, 17, 37), hard=((2, 0),), inh=True),
+}
+
+
+def make_abc(name):
+    import dataclasses
+    c = ABC_CASES[name]
+    base = wl.small_problem(c["n"], layer=0, ppw=10.0, inhomogeneous=c["inh"], seed=17, name="abc-" + name)
+    return dataclasses.replace(base, absorber="abc", hard_faces=c["hard"])
+
+
+@pytest.mark.parametrize("name", list(ABC_CASES))
+def test_abc_operator_actions_and_precond(ctx, name):
+    prob = make_abc(name)
+    announce("abc", name, prob.n)
+    P = mxp.Problem(ctx, prob)
+    s = prob.default_shift()
+    As = op.helmholtz(prob, s)
+    x = wl.random_vector(prob.npts, 23)
+    for tdt, eps in ((torch.complex128, 2.0**-53), (torch.complex64, 2.0**-24)):
+        xd = to_dev(x, tdt)
+        yd = torch.empty_like(xd)
+        mxp.mxp_apply_A(P, s, xd, yd)
+        xr = to_host(xd)
+        bound = np.linalg.norm(abs(As) @ np.abs(xr))
+        assert np.linalg.norm(to_host(yd) - As @ xr) <= 16 * eps * bound, tdt
+    t = prob.default_t()
+    for tdt, tol in ((torch.complex128, 1e-11), (torch.complex64, 1e-5)):
+        xd = to_dev(x, tdt)
+        yd = torch.empty_like(xd)
+        mxp.mxp_apply_exp(P, t, s, xd, yd)
+        assert rel(to_host(yd), matfun.exp_action(As, t, to_host(xd))) <= tol, tdt
+        mxp.mxp_apply_psi1(P, t, s, xd, yd)
+        assert rel(to_host(yd), matfun.phi1_action(As, t, to_host(xd))) <= tol, tdt
+    for prec in (0, 1):
+        o = P.default_opts()
+        o.precision = prec
+        forced_precond_parity(P, As, o, x, 1e-10 if prec == 0 else 1e-5)
+    P.close()
+
+
+@pytest.mark.parametrize("name", ["2d-inh", "3d-ragged"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_abc_solve(ctx, name, prec):
+    prob = make_abc(name)
+    announce("abc solve", name, prec)
+    P = mxp.Problem(ctx, prob)
+    # a source next to the sound-hard face, centred on the other axes
+    node = [m // 2 for m in prob.n]
+    node[ABC_CASES[name]["hard"][0][0]] = 2
+    f = wl.delta_source(prob, tuple(node)).ravel()
+    fd = to_dev(f)
+    ud = torch.zeros_like(fd)
+    o = P.default_opts()
+    o.precision = prec
+    st = mxp.mxp_solve(P, o, fd, ud)
+    ref = krylov.matexpre_solve(prob, f, o.t, o.shift, o.fprtol, o.rtol)
+    assert st["status"] == mxp.MXP_OK and st["true_relres"] <= o.rtol
+    assert abs(st["outer_its"] - ref.outer_iterations) <= 1
+    assert abs(st["inner_mean"] - ref.inner_mean) <= 1.0
+    o.rtol = 1e-12
+    ud.zero_()
+    st = mxp.mxp_solve(P, o, fd, ud)
+    assert st["true_relres"] <= 1e-12
+    assert rel(to_host(ud), krylov.direct_solve(prob, f)) <= (1e-10 if prec == 0 else 1e-5)
+    P.close()
+
+
+def test_abc_batch_equals_separate_solves(ctx):
+    """A batched solve over an absorbing-face problem (3D, varying speed) and a
+    layer problem equals the separate solves bit for bit."""
+    probs = [make_abc("3d-ragged"), make("3d-inh")]
+    announce("abc batch", [p.n for p in probs])
+    Ps = [mxp.Problem(ctx, p) for p in probs]
+    fs, us, opts, refs = [], [], [], []
+    for p, P in zip(probs, Ps):
+        f = to_dev(wl.random_vector(p.npts, 31))
+        o = P.default_opts()
+        o.precision = mxp.MXP_PREC_MIXED
+        u = torch.zeros_like(f)
+        mxp.mxp_solve(P, o, f, u)
+        refs.append(u.clone())
+        fs.append(f)
+        us.append(torch.zeros_like(f))
+        opts.append(o)
+    status, stats = mxp.mxp_solve_batch(ctx, Ps, opts, fs, us)
+    assert status == mxp.MXP_OK
+    for u, r in zip(us, refs):
+        assert torch.equal(u, r)
+    for P in Ps:
+        P.close()

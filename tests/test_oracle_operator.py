@@ -7,7 +7,8 @@ import pytest
 
 import workloads as wl
 from oracle import operator as op
-from oracle import matfun
+from oracle import krylov, matfun
+from scipy.sparse.linalg import splu
 
 
 def test_dirichlet_eigs_match_dense_second_difference():
@@ -231,3 +232,109 @@ def test_greens_function_2d_outgoing_with_cap():
     assert np.linalg.norm(sol[ann] - green) / np.linalg.norm(green) < 0.05
     wrong = 0.25j * np.conj(hankel1(0, prob.omega * r[ann]))
     assert np.linalg.norm(sol[ann] - wrong) / np.linalg.norm(wrong) > 0.5
+
+
+# ---------------------------------------------------------------------------
+# Boundary conditions in place of a layer (Section 4.3.4): a sound-hard face
+# and first-order absorbing faces by ghost points.
+
+
+def _abc_1d(N, h, omega, c, hard_left=True):
+    return wl.Problem("abc1d", (N,), h, omega, 0, None, c, absorber="abc",
+                      hard_faces=((0, 0),) if hard_left else ())
+
+
+@pytest.mark.parametrize("ppw", [6.0, 10.0, 20.0])
+def test_abc_1d_reflection_closed_form(ppw):
+    """A plane wave driven from the left meets the absorbing right end.  The
+    interior rows hold exactly for u_j = a z^j + b z^-j with z = e^{i xi h},
+    2 - 2 cos(xi h) = (k h)^2; the ghost row u_N = u_{N-2} + 2 i h k u_{N-1}
+    then gives |b/a| = |sin(xi h) - k h| / (sin(xi h) + k h) = tan^2(xi h / 4).
+    c = 2 so that k = omega / c is tested (a k from 1/c^2 or a flipped sign,
+    which reflects more than it sends, fails)."""
+    N, h, c = 60, 1.0 / 59, 2.0
+    k = 2 * np.pi / (ppw * h)
+    omega = k * c
+    prob = _abc_1d(N, h, omega, c)
+    A = op.helmholtz(prob, 0.0).tolil()
+    A[0, :] = 0
+    A[0, 0] = 1.0  # drive u_0 = 1
+    rhs = np.zeros(N, dtype=complex)
+    rhs[0] = 1.0
+    u = splu(A.tocsc()).solve(rhs)
+    xi_h = np.arccos(1 - (k * h) ** 2 / 2)
+    z = np.exp(1j * xi_h)
+    M = np.array([[z ** 1, z ** -1], [z ** 2, z ** -2]])
+    a, b = np.linalg.solve(M, u[1:3])
+    # the two-mode form holds on every node the interior rows cover
+    j = np.arange(N)
+    assert np.allclose(a * z ** j + b * z ** -j, u, rtol=0, atol=1e-10 * abs(a))
+    assert abs(abs(b / a) - np.tan(xi_h / 4) ** 2) <= 1e-9
+    assert abs(b / a) < 0.1
+
+
+def test_abc_sound_hard_face_is_a_mirror():
+    """A sound-hard face is a mirror: the problem on a half domain with the
+    hard face at y = 0 equals, on its nodes, the problem on the domain
+    reflected across that face (speed and source mirrored, all faces
+    absorbing), because the ghost value u_{-1} = u_1 is what the symmetric
+    solution has there."""
+    rng = np.random.default_rng(5)
+    nx, ny = 15, 9
+    h = 1.0 / 14
+    omega = wl.omega_for(8, h)
+    c_half = rng.uniform(1.0, 2.0, (ny, nx))
+    f_half = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    half = wl.Problem("half", (nx, ny), h, omega, 0, c_half, absorber="abc", hard_faces=((1, 0),))
+    full_rows = np.concatenate([np.arange(ny - 1, 0, -1), np.arange(ny)])  # mirrored row index |j|
+    full = wl.Problem("full", (nx, 2 * ny - 1), h, omega, 0, c_half[full_rows], absorber="abc")
+    s = 0.05
+    u_half = krylov.direct_solve(half, f_half.ravel(), shift=s).reshape(ny, nx)
+    u_full = krylov.direct_solve(full, f_half[full_rows].ravel(), shift=s).reshape(2 * ny - 1, nx)
+    assert np.linalg.norm(u_full[ny - 1:] - u_half) <= 1e-11 * np.linalg.norm(u_half)
+    # with the face absorbing instead, the two differ at O(1)
+    half_abs = wl.Problem("half-abs", (nx, ny), h, omega, 0, c_half, absorber="abc")
+    u_abs = krylov.direct_solve(half_abs, f_half.ravel(), shift=s).reshape(ny, nx)
+    assert np.linalg.norm(u_full[ny - 1:] - u_abs) > 1e-2 * np.linalg.norm(u_half)
+
+
+def test_abc_spectrum_and_symmetrised_field_of_values():
+    """The paper states that every eigenvalue of the matrix from these
+    conditions has a non-negative imaginary part.  The diagonal similarity
+    W^{1/2} A W^{-1/2} (w = 1/2 at each axis' end nodes) is complex symmetric
+    with a real second difference, and its skew-Hermitian part is a diagonal
+    >= 0, so its field of values lies in the upper half-plane: the bound the
+    library's schedule design takes, times the condition number of the
+    similarity."""
+    rng = np.random.default_rng(8)
+    n = (9, 8)
+    h = 1.0 / 8
+    c = rng.uniform(1.0, 3.0, (n[1], n[0]))
+    prob = wl.Problem("abc-small", n, h, wl.omega_for(6, h), 0, c, absorber="abc", hard_faces=((1, 0),))
+    A = op.helmholtz(prob, 0.0).toarray()
+    ev = np.linalg.eigvals(A)
+    scale = np.abs(ev).max()
+    assert ev.imag.min() >= -1e-12 * scale
+    ev_s = np.linalg.eigvals(op.helmholtz(prob, 0.1).toarray())
+    assert ev_s.imag.min() > 0
+    w = op.ghost_similarity(prob)
+    S = np.sqrt(w)[:, None] * A / np.sqrt(w)[None, :]
+    assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+    K = (S - S.conj().T) / 2j
+    assert np.linalg.eigvalsh(K).min() >= -1e-12 * scale
+    # the absorbing faces are what makes it non-Hermitian: with every face hard
+    # the matrix is similar to a real symmetric one (real spectrum)
+    hard_all = wl.Problem("hard", n, h, prob.omega, 0, c, absorber="abc",
+                          hard_faces=((0, 0), (0, 1), (1, 0), (1, 1)))
+    assert np.abs(np.linalg.eigvals(op.helmholtz(hard_all, 0.0).toarray()).imag).max() <= 1e-9 * scale
+
+
+def test_abc_rows_against_the_assembled_matrix():
+    rng = np.random.default_rng(9)
+    n = (7, 6, 5)
+    prob = wl.Problem("abc3", n, 1.0 / 6, 20.0, 0, rng.uniform(1, 2, n[::-1]), absorber="abc",
+                      hard_faces=((2, 0),))
+    x = rng.standard_normal(prob.npts) + 1j * rng.standard_normal(prob.npts)
+    A = op.helmholtz(prob, 0.2)
+    pts = np.arange(prob.npts)
+    assert np.abs(op.apply_rows(prob, 0.2, x, pts) - A @ x).max() <= 1e-12 * np.abs(A @ x).max()

@@ -40,7 +40,9 @@ class Problem:
     c_const: float = 1.0          # used when c is None
     pml_C: float = 20.0           # absorbing strength constant
     pml_power: int = 2            # quadratic profile
-    absorber: str = "pml"         # "pml" (coordinate stretch) or "cap" (absorbing potential)
+    absorber: str = "pml"         # "pml" (coordinate stretch), "cap" (absorbing potential) or
+                                  # "abc" (boundary conditions on the grid's faces, no layer)
+    hard_faces: Tuple[Tuple[int, int], ...] = ()  # "abc": sound-hard faces (axis, side); the rest absorb
 
     @property
     def dim(self) -> int:
