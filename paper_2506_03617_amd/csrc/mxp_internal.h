@@ -115,4 +115,12 @@ void expm_dense(int n, std::vector<cd>& A);
 void design_psi2_series(const mxp_schedule& sc, double t, mxp_precision prec, std::vector<double>* coef,
                         int* m);
 
+// The learned stage's checkpoint file (host only): write the parameters and
+// both Adam moments (buf: 3 * nparam floats) with the architecture header, or
+// read them back after checking the architecture, length and finiteness.
+void write_checkpoint(const char* path, int32_t layers, const int32_t* channels, int64_t nparam, int64_t adam_t,
+                      const std::vector<float>& buf);
+void read_checkpoint(const char* path, int32_t layers, const int32_t* channels, int64_t nparam, int64_t* adam_t,
+                     std::vector<float>* buf);
+
 }  // namespace mxp

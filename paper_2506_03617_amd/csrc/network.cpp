@@ -251,11 +251,6 @@ mxp_status mxp_cnn_get_grads(const mxp_cnn* net, float* host) {
     });
 }
 
-// Checkpoint file: the 8-byte tag below, int32 layer count, int32 channel
-// counts (layers + 1), int64 parameter count, int64 Adam step, then the
-// parameters and the two Adam moments as float, all little-endian.
-static const char kCkptTag[8] = {'M', 'X', 'P', 'C', 'N', 'N', '0', '1'};
-
 mxp_status mxp_cnn_save(const mxp_cnn* net, const char* path) {
     return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !path) fail(MXP_ERR_INVALID_ARG, "network or path is NULL");
@@ -266,15 +261,7 @@ mxp_status mxp_cnn_save(const mxp_cnn* net, const char* path) {
         HIP_CHECK(hipMemcpy(buf.data(), net->params.p, n * 4, hipMemcpyDeviceToHost));
         HIP_CHECK(hipMemcpy(buf.data() + n, net->adam_m.p, n * 4, hipMemcpyDeviceToHost));
         HIP_CHECK(hipMemcpy(buf.data() + 2 * n, net->adam_v.p, n * 4, hipMemcpyDeviceToHost));
-        std::unique_ptr<FILE, int (*)(FILE*)> f(std::fopen(path, "wb"), &std::fclose);
-        if (!f) fail(MXP_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
-        const int32_t layers = kLayers;
-        bool ok = std::fwrite(kCkptTag, 1, 8, f.get()) == 8 && std::fwrite(&layers, 4, 1, f.get()) == 1 &&
-                  std::fwrite(kChannels, 4, kLayers + 1, f.get()) == size_t(kLayers + 1) &&
-                  std::fwrite(&net->nparam, 8, 1, f.get()) == 1 && std::fwrite(&net->adam_t, 8, 1, f.get()) == 1 &&
-                  std::fwrite(buf.data(), 4, buf.size(), f.get()) == buf.size();
-        ok = (std::fclose(f.release()) == 0) && ok;
-        if (!ok) fail(MXP_ERR_INVALID_ARG, std::string("write to ") + path + " failed");
+        write_checkpoint(path, kLayers, kChannels, net->nparam, net->adam_t, buf);
         return MXP_OK;
     });
 }
@@ -282,26 +269,10 @@ mxp_status mxp_cnn_save(const mxp_cnn* net, const char* path) {
 mxp_status mxp_cnn_load(mxp_cnn* net, const char* path) {
     return cnn_guard(net ? &net->alloc : nullptr, [&]() {
         if (!net || !path) fail(MXP_ERR_INVALID_ARG, "network or path is NULL");
-        std::unique_ptr<FILE, int (*)(FILE*)> f(std::fopen(path, "rb"), &std::fclose);
-        if (!f) fail(MXP_ERR_INVALID_ARG, std::string("cannot open ") + path);
-        char tag[8];
-        int32_t layers = 0, ch[kLayers + 1];
-        int64_t np = 0, t = 0;
-        if (std::fread(tag, 1, 8, f.get()) != 8 || std::memcmp(tag, kCkptTag, 8) != 0)
-            fail(MXP_ERR_INVALID_ARG, "not a network checkpoint");
-        if (std::fread(&layers, 4, 1, f.get()) != 1 || layers != kLayers ||
-            std::fread(ch, 4, kLayers + 1, f.get()) != size_t(kLayers + 1) ||
-            std::memcmp(ch, kChannels, sizeof(ch)) != 0)
-            fail(MXP_ERR_INVALID_ARG, "checkpoint holds another architecture");
-        if (std::fread(&np, 8, 1, f.get()) != 1 || np != net->nparam || std::fread(&t, 8, 1, f.get()) != 1 || t < 0)
-            fail(MXP_ERR_INVALID_ARG, "checkpoint header is inconsistent");
-        const size_t n = size_t(np);
-        std::vector<float> buf(3 * n);
-        if (std::fread(buf.data(), 4, buf.size(), f.get()) != buf.size() || std::fgetc(f.get()) != EOF)
-            fail(MXP_ERR_INVALID_ARG, "checkpoint has the wrong length");
-        for (size_t k = 0; k < buf.size(); ++k)
-            if (!std::isfinite(buf[k]) || (k >= 2 * n && buf[k] < 0.0f))
-                fail(MXP_ERR_NONFINITE, "checkpoint holds a non-finite parameter or moment");
+        std::vector<float> buf;
+        int64_t t = 0;
+        read_checkpoint(path, kLayers, kChannels, net->nparam, &t, &buf);
+        const size_t n = size_t(net->nparam);
         HIP_CHECK(hipSetDevice(net->device));
         HIP_CHECK(hipStreamSynchronize(net->stream));
         HIP_CHECK(hipMemcpy(net->params.p, buf.data(), n * 4, hipMemcpyHostToDevice));
