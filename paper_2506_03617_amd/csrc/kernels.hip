@@ -185,16 +185,27 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t tiles, int64_t pa
 
 // 3D sweep marching along z.  A workgroup's four wavefronts lie side by side
 // along x: work-item c owns column c of a tile of kSweepW columns and TY rows
-// and keeps those TY values of v for planes k-1, k and k+1 in registers.  So
-// per plane v is loaded once for the tile's rows plus one halo row on either
+// and keeps those TY values of v for planes k-1 .. k+2 in registers.  So per
+// plane v is loaded once for the tile's rows plus one halo row on either
 // side; y-neighbours inside the tile come from the work-item's own registers
 // and x-neighbours from the adjacent lanes by DPP wavefront shifts (lanes 0
 // and 63 load theirs: it lies in the neighbouring wavefront, or tile).  The
-// plane loop is unrolled by three so that the three plane slots rotate by
-// renaming.  The x weights are loop-invariant per lane, the y and z tables
-// are uniform (scalar cache); ghost neighbours get weight zero and clamped
+// loop is software-pipelined: the step for plane k first issues the loads of
+// plane k+2 of v and of plane k+1's other operands, then computes plane k
+// from registers loaded one step earlier, so a wavefront's loads are in
+// flight while it computes.  It is unrolled by four so that the four plane
+// slots and the two operand sets rotate by renaming.  The x weights are
+// loop-invariant per lane, the y and z tables are uniform (scalar cache);
+// ghost neighbours get weight zero and planes outside the grid clamped
 // addresses (no branch around a load).  OPS marks the operands present (1: x,
 // 2: b2, 4: b3, 8: D), so absent ones cost no load.
+template <typename R, int OPS, int TY>
+struct PipeOps {
+    cpx<R> xe[TY], xv[TY], b2v[TY], b3v[TY];
+    R Dv[TY];
+    cpx<R> hm, hp;
+};
+
 template <typename R, int OPS, int TY>
 __device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGeom& m, int64_t tile) {
     constexpr bool HX = OPS & 1, H2 = OPS & 2, H3 = OPS & 4, HD = OPS & 8;
@@ -212,67 +223,60 @@ __device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGe
     const int64_t sy = a.n0;
     const int64_t sz = a.n0 * a.n1;
     const cpx<R>* __restrict__ v = a.b1;
-    const cpx<R> zero{R(0), R(0)};
     // x weights (zero for ghosts and for columns beyond the grid)
     const cpx<R> wxm = keep_if(col_ok && i > 0, gload(a.alpha[0], ic));
     const cpx<R> wxp = keep_if(col_ok && i < a.n0 - 1, gload(a.beta[0], ic));
     const cpx<R> gx = gload(a.gamma[0], ic);
-    // absorbing faces with a varying speed (uniform test)
     const bool abc_on = a.abc[0] != nullptr;
     const R abx = abc_on ? gload(a.abc[0], ic) : R(0);
-    // lanes 0 and 63 read their outer x-neighbour from memory (offset 0 when it is a ghost)
     const int64_t eoff = (lane == 0 && ic > 0) ? -1 : ((lane == 63 && ic < a.n0 - 1) ? 1 : 0);
-    // row offsets, clamped to the grid
     int64_t roff[TY];
 #pragma unroll
     for (int r = 0; r < TY; ++r) roff[r] = sy * (j0 + r < a.n1 ? j0 + r : a.n1 - 1);
     const int64_t hlo = sy * (j0 > 0 ? j0 - 1 : 0);
     const int64_t hhi = sy * (j0 + TY < a.n1 ? j0 + TY : a.n1 - 1);
     const bool has_lo = j0 > 0, has_hi = j0 + TY < a.n1;
-    cpx<R> P0[TY], P1[TY], P2[TY];
-    // planes z0 - 1 and z0
+    // plane k clamped into the grid
+    auto zcl = [&](int64_t k) { return k < 0 ? int64_t(0) : (k >= a.n2 ? a.n2 - 1 : k); };
+    auto load_v = [&](int64_t k, cpx<R>(&dst)[TY]) {
+        const int64_t pk = ic + sz * zcl(k);
 #pragma unroll
-    for (int r = 0; r < TY; ++r) {
-        P0[r] = keep_if(z0 > 0, gload(v, ic + roff[r] + sz * (z0 > 0 ? z0 - 1 : z0)));
-        P1[r] = gload(v, ic + roff[r] + sz * z0);
-    }
-    // one plane: prev = k-1, cur = k, next receives k+1
-    auto plane = [&](int64_t k, const cpx<R>(&prev)[TY], const cpx<R>(&cur)[TY], cpx<R>(&next)[TY]) {
-        const bool up = k + 1 < a.n2;
-        const int64_t pk = ic + sz * k;
-        const int64_t pn = ic + sz * (up ? k + 1 : k);
-        cpx<R> hm = gload(v, pk + hlo);
-        cpx<R> xe[TY], xv[TY], b2v[TY], b3v[TY];
-        R Dv[TY];
+        for (int r = 0; r < TY; ++r) dst[r] = gload(v, pk + roff[r]);
+    };
+    auto load_ops = [&](int64_t k, PipeOps<R, OPS, TY>& o) {
+        const int64_t pk = ic + sz * zcl(k);
+        o.hm = gload(v, pk + hlo);
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
-            next[r] = gload(v, pn + roff[r]);
-            xe[r] = gload(v, pk + roff[r] + eoff);
-            if constexpr (HX) xv[r] = gload(a.x, pk + roff[r]);
-            if constexpr (H2) b2v[r] = gload(a.b2, pk + roff[r]);
-            if constexpr (H3) b3v[r] = gload(a.b3, pk + roff[r]);
-            if constexpr (HD) Dv[r] = gload(a.D, pk + roff[r]);
+            o.xe[r] = gload(v, pk + roff[r] + eoff);
+            if constexpr (HX) o.xv[r] = gload(a.x, pk + roff[r]);
+            if constexpr (H2) o.b2v[r] = gload(a.b2, pk + roff[r]);
+            if constexpr (H3) o.b3v[r] = gload(a.b3, pk + roff[r]);
+            if constexpr (HD) o.Dv[r] = gload(a.D, pk + roff[r]);
         }
-        cpx<R> hp = gload(v, pk + hhi);
-        hm = keep_if(has_lo, hm);
-        hp = keep_if(has_hi, hp);
+        o.hp = gload(v, pk + hhi);
+    };
+    auto compute = [&](int64_t k, const cpx<R>(&prev)[TY], const cpx<R>(&cur)[TY], const cpx<R>(&next)[TY],
+                       const PipeOps<R, OPS, TY>& o) {
+        const int64_t pk = ic + sz * k;
+        const bool dn = k > 0, up = k + 1 < a.n2;
+        const cpx<R> hm = keep_if(has_lo, o.hm), hp = keep_if(has_hi, o.hp);
         const cpx<R> az = sload(a.alpha[2], k), bz = sload(a.beta[2], k);
         const cpx<R> gxz = cadd(gx, sload(a.gamma[2], k));
         const R abxz = abc_on ? abx + sload_r(a.abc[2], k) : R(0);
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
-            next[r] = keep_if(up, next[r]);
             const int64_t j = j0 + r;
             if (j >= a.n1) break;  // uniform: rows beyond the grid
             cpx<R> xm = from_below(cur[r]), xp = from_above(cur[r]);
-            xm = csel(lane == 0, xe[r], xm);
-            xp = csel(lane == 63, xe[r], xp);
+            xm = csel(lane == 0, o.xe[r], xm);
+            xp = csel(lane == 63, o.xe[r], xp);
             const cpx<R> ym = r > 0 ? cur[r - 1] : hm;
             const cpx<R> yp = r < TY - 1 ? cur[r + 1] : hp;
             const cpx<R> wym = keep_if(j > 0, sload(a.alpha[1], j));
             const cpx<R> wyp = keep_if(j < a.n1 - 1, sload(a.beta[1], j));
             R Draw = a.Dconst;
-            if constexpr (HD) Draw = Dv[r];
+            if constexpr (HD) Draw = o.Dv[r];
             cpx<R> diag = cadd(gxz, sload(a.gamma[1], j));
             diag = cadd(diag, cscale(Draw - a.Dref, a.kD));
             if (abc_on) {  // 2 i omega sqrt(D_p)/h per absorbing face of the node
@@ -284,27 +288,43 @@ __device__ __forceinline__ void sweep3d(const StencilArgs<R>& a, const Sweep3DGe
             s = cfma(wxp, xp, s);
             s = cfma(wym, ym, s);
             s = cfma(wyp, yp, s);
-            s = cfma(az, prev[r], s);
-            s = cfma(bz, next[r], s);
-            cpx<R> o = cmul(a.g, s);
-            if constexpr (HX) o = cfma(a.cx, xv[r], o);
-            if constexpr (H2) o = cfma(a.e2, b2v[r], o);
-            if constexpr (H3) o = cfma(a.e3, b3v[r], o);
-            if (col_ok) gstore(a.out, pk + roff[r], o);
+            s = cfma(az, keep_if(dn, prev[r]), s);
+            s = cfma(bz, keep_if(up, next[r]), s);
+            cpx<R> o2 = cmul(a.g, s);
+            if constexpr (HX) o2 = cfma(a.cx, o.xv[r], o2);
+            if constexpr (H2) o2 = cfma(a.e2, o.b2v[r], o2);
+            if constexpr (H3) o2 = cfma(a.e3, o.b3v[r], o2);
+            if (col_ok) gstore(a.out, pk + roff[r], o2);
         }
     };
-    for (int64_t k = z0; k < z1; k += 3) {
-        plane(k, P0, P1, P2);
-        if (k + 1 >= z1) break;
-        plane(k + 1, P1, P2, P0);
-        if (k + 2 >= z1) break;
-        plane(k + 2, P2, P0, P1);
+    cpx<R> V0[TY], V1[TY], V2[TY], V3[TY];
+    PipeOps<R, OPS, TY> O0, O1;
+    load_v(z0 - 1, V0);
+    load_v(z0, V1);
+    load_v(z0 + 1, V2);
+    load_ops(z0, O0);
+    // step for plane k: slots (k-1, k, k+1, k+2) and operands (k, k+1)
+#define MXP_PIPE_STEP(A, B, C, Dn, OC, ON)        \
+    {                                             \
+        load_v(k + 2, Dn);                        \
+        if (k + 1 < z1) load_ops(k + 1, ON);      \
+        compute(k, A, B, C, OC);                  \
+        if (++k >= z1) break;                     \
     }
+    int64_t k = z0;
+    while (true) {
+        MXP_PIPE_STEP(V0, V1, V2, V3, O0, O1)
+        MXP_PIPE_STEP(V1, V2, V3, V0, O1, O0)
+        MXP_PIPE_STEP(V2, V3, V0, V1, O0, O1)
+        MXP_PIPE_STEP(V3, V0, V1, V2, O1, O0)
+    }
+#undef MXP_PIPE_STEP
 }
 
-// rows per work-item: complex float 8, complex double 4 (register budget)
+// rows per work-item: complex float 4, complex double 2 (the pipelined loop
+// holds two planes of operands in registers)
 template <typename R>
-constexpr int sweep_rows() { return sizeof(R) == 4 ? 8 : 4; }
+constexpr int sweep_rows() { return sizeof(R) == 4 ? 4 : 2; }
 
 template <typename R, int OPS>
 __global__ __launch_bounds__(256) void k_stencil3d(StencilArgs<R> a, Sweep3DGeom m) {
