@@ -339,11 +339,12 @@ def bench_learned(args, torch, mxp, wl):
     t_train = time.perf_counter() - t1
     del X_all, T_all, crops_in, crops_t
     # --- conv throughput at the evaluation size (inference forward)
-    test = layered_model(wl, (256, 256, 256), 20, 9999)
+    ne = args.eval_grid
+    test = layered_model(wl, (ne, ne, ne), 20 if ne >= 256 else 16, 9999)
     V = test.npts
     xin = torch.zeros(V * 8, dtype=torch.int16, device="cuda:0")
     out = torch.empty(V * 2, dtype=torch.float32, device="cuda:0")
-    vshape = (1, 256, 256, 256)
+    vshape = (1, ne, ne, ne)
     net.forward(vshape, xin, out)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -357,18 +358,19 @@ def bench_learned(args, torch, mxp, wl):
     del xin, out
     # --- evaluation: plain mixed vs learned on the unseen model
     P = mxp.Problem(ctx, test)
-    f = torch.from_numpy(wl.delta_source(test, (128, 128, 22)).ravel()).to("cuda:0")
+    f = torch.from_numpy(wl.delta_source(test, (ne // 2, ne // 2, test.layer + 2)).ravel()).to("cuda:0")
     u = torch.zeros_like(f)
     o = P.default_opts()
     o.precision = mxp.MXP_PREC_MIXED
     o.outer_restart = args.eval_restart
     res = {}
-    print(f"[bench] network forward at 256^3: {t_fwd * 1e3:.2f} ms", file=sys.stderr, flush=True)
-    for mode in ("plain", "learned"):
-        o.use_learned = 1 if mode == "learned" else 0
-        o.stall_ratio = 0.0   # cost-aware acceptance
-        if mode == "learned":
-            mxp.mxp_problem_set_learned(P, net, kappa)
+    print(f"[bench] network forward at {ne}^3: {t_fwd * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    mxp.mxp_problem_set_learned(P, net, kappa)
+    for mode in ("plain", "learned", "warm"):
+        # learned: the network's direction tried first at every outer iteration;
+        # warm: its output starts the inner GMRES of every preconditioner apply
+        o.use_learned = {"plain": 0, "learned": 1, "warm": 2}[mode]
+        o.stall_ratio = 0.0   # cost-aware acceptance (counted work)
         u.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -386,10 +388,14 @@ def bench_learned(args, torch, mxp, wl):
         "data": "synthetic (seeded layered models, point sources); pairs generated by the solver",
         "config": {"workload": "3d-learned", "train_grid": [128, 128, 128], "train_models": args.train_models,
                    "pairs": n_pairs, "crops": 2 * n_pairs, "crop": list(crop), "train_steps": args.train_steps,
-                   "batch": B, "eval_grid": [256, 256, 256], "precision": "mixed", "outer_restart": args.eval_restart,
+                   "batch": B, "eval_grid": [ne, ne, ne], "precision": "mixed", "outer_restart": args.eval_restart,
                    "stall_ratio": "adaptive (0)"},
         "learned": {k: res["learned"][k] for k in ("wall", "outer_its", "learned_its", "fallbacks", "inner_mean",
                                                      "stencil_steps", "true_relres")},
+        "warm_start": {k: res["warm"][k] for k in ("wall", "outer_its", "learned_its", "fallbacks", "inner_mean",
+                                                   "stencil_steps", "true_relres")},
+        "gain_vs_plain": {m: {"stencil_steps": round(res["plain"]["stencil_steps"] / res[m]["stencil_steps"], 4),
+                              "wall": round(res["plain"]["wall"] / res[m]["wall"], 4)} for m in ("learned", "warm")},
         "plain_mixed": {k: res["plain"][k] for k in ("wall", "outer_its", "inner_mean", "stencil_steps",
                                                      "true_relres")},
         "training": {"data_seconds": round(t_data, 1), "train_seconds": round(t_train, 1),
@@ -644,6 +650,7 @@ def main():
     ap.add_argument("--train-models", type=int, default=6, help="3d-learned: 128^3 training models")
     ap.add_argument("--train-steps", type=int, default=1500, help="3d-learned: Adam steps")
     ap.add_argument("--eval-restart", type=int, default=60, help="3d-learned: FGMRES restart of the evaluation")
+    ap.add_argument("--eval-grid", type=int, default=256, help="3d-learned: nodes per axis of the evaluation model")
     ap.add_argument("--conv-only", action="store_true",
                     help="3d-learned: time the network alone (forward at 256^3, training steps on 4 x 64^3)")
     ap.add_argument("--rhs", type=int, default=2,

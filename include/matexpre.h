@@ -200,7 +200,9 @@ typedef struct {
     mxp_precision precision;
     int32_t cheb_S;         /* > 0 forces the number of Chebyshev substeps (0 = designed) */
     int32_t cheb_m;         /* > 0 forces the series degree per substep    (0 = designed) */
-    int32_t use_learned;    /* 1: learned network tried first at outer iterations (see below) */
+    int32_t use_learned;    /* 1: learned network tried first at outer iterations; 2: its output
+                               warm-starts the inner GMRES of every preconditioner apply (the
+                               exp form); see mxp_problem_set_learned.  0: off */
     double stall_ratio;     /* in [0, 1]: > 0 keeps a learned z_j if the residual estimate drops
                                below this factor times the previous one; 0 (default) sets the
                                factor from MatExPre's own iterations (see below) */
@@ -248,8 +250,8 @@ typedef struct {
     double seconds;           /* wall time of the call                            */
     int32_t restarts;         /* outer restart cycles after the first             */
     int32_t status;           /* this solve's outcome (mxp_status)                */
-    int32_t learned_its;      /* outer iterations preconditioned by the network   */
-    int32_t fallbacks;        /* network tries rejected (MatExPre used instead)   */
+    int32_t learned_its;      /* network directions kept (use_learned 1) or warm starts kept (2) */
+    int32_t fallbacks;        /* network outputs rejected (MatExPre alone used instead) */
     int32_t fp64_its;         /* mixed form: outer iterations with actions in double */
 } mxp_solve_stats;
 
@@ -471,18 +473,29 @@ mxp_status mxp_collect_pairs(mxp_problem* prob, const mxp_solve_opts* opts, cons
                              int32_t max_pairs, void* r_out, void* z_out, double* rnorm, double* znorm,
                              int32_t* npairs, mxp_solve_stats* stats);
 /* Attaches a network (not owned; NULL detaches) to a problem for solves with
- * opts.use_learned = 1.  The network sees v_j scaled to unit root-mean-square
- * value and its output, scaled back, is multiplied by out_scale (the typical
- * ||M(v)|| / ||v|| of the training pairs).  At an outer iteration z_j =
- * network(v_j) is kept if the Arnoldi residual estimate falls below a
- * threshold times the previous one: stall_ratio if > 0, else
- * min(exp(g), exp(rate * T)) with g the mean log reduction per MatExPre
- * iteration so far, rate the same per second and T the time of the network
- * try (a kept direction takes a slot of the restart cycle, so it must reduce
- * the residual as much as the MatExPre iteration it displaces, and at least
- * as cost-effectively).  Otherwise z_j = M(v_j) from MatExPre (a
+ * opts.use_learned = 1 or 2.  The network sees its input scaled to unit
+ * root-mean-square value, and its output, scaled back, is multiplied by
+ * out_scale (the typical ||M(v)|| / ||v|| of the training pairs).
+ *
+ * use_learned = 2: each preconditioner apply M(r) starts its inner GMRES from
+ * w_0 = network(r) (the network is trained on pairs (r, M(r))) when the
+ * residual of w_0 on (I - exp(i t A_s)) w = r_hat, which costs one action, is
+ * below ||r_hat||, else from zero.  Stats count kept starts in learned_its and
+ * rejected ones in fallbacks.
+ *
+ * use_learned = 1: at an outer iteration z_j = network(v_j) is kept if the
+ * Arnoldi residual estimate falls below a threshold times the previous one:
+ * stall_ratio if > 0, else min(exp(g), exp(r * 48)) with g the mean log
+ * reduction per MatExPre iteration so far and r the same per stencil step
+ * those iterations took (a network try counts as 48 stencil steps: the
+ * inference takes about as long as 40 sweeps, plus A z and a Gram-Schmidt
+ * pass).  A kept direction takes a slot of the restart cycle, so it must
+ * reduce the residual as much as the MatExPre iteration it displaces, and at
+ * least as cost-effectively; the rule counts work, not time, so repeated
+ * solves make the same choices.  Otherwise z_j = M(v_j) from MatExPre (a
  * fallback); after two fallbacks in a row MatExPre alone is used until the
  * next restart cycle.  The first outer iteration always uses MatExPre.
+ *
  * Convergence is judged by the complex-double true residual as always.
  * Single solves only (mxp_solve_batch rejects use_learned). */
 mxp_status mxp_problem_set_learned(mxp_problem* prob, mxp_cnn* net, double out_scale);

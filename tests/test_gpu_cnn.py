@@ -306,6 +306,39 @@ def test_learned_solve_converges_to_the_solution(ctx):
     st = mxp.mxp_solve(P, o, f2d, u2)
     assert st["status"] == mxp.MXP_OK and st["true_relres"] <= o.rtol
     assert st["learned_its"] + st["fallbacks"] >= 1
+    # the adaptive acceptance counts work, not time: repeated solves make the
+    # same choices and give the same iterate
+    o.stall_ratio = 0.0
+    runs = []
+    for _ in range(2):
+        u2.zero_()
+        sa = mxp.mxp_solve(P, o, f2d, u2)
+        runs.append(({k: sa[k] for k in ("outer_its", "learned_its", "fallbacks", "stencil_steps")}, u2.clone()))
+    assert runs[0][0] == runs[1][0] and torch.equal(runs[0][1], runs[1][1])
+    assert sa["status"] == mxp.MXP_OK
+    # warm start of the inner GMRES (use_learned = 2): an apply solved tightly
+    # from the network's start equals the one solved from zero (same system),
+    # and solves converge, deterministically
+    ow = P.default_opts()
+    ow.fprtol = 1e-11
+    ow.inner_restart = 60
+    ow.max_inner = 200
+    rd = to_dev(wl.random_vector(n, 41))
+    w_cold, w_warm = torch.empty_like(rd), torch.empty_like(rd)
+    mxp.mxp_apply_precond(P, ow, rd, w_cold)
+    ow.use_learned = 2
+    mxp.mxp_apply_precond(P, ow, rd, w_warm)
+    assert rel(to_host(w_warm), to_host(w_cold)) <= 1e-8
+    o.use_learned = 2
+    warm = []
+    for _ in range(2):
+        u2.zero_()
+        sw = mxp.mxp_solve(P, o, f2d, u2)
+        assert sw["status"] == mxp.MXP_OK and sw["true_relres"] <= o.rtol
+        warm.append(({k: sw[k] for k in ("outer_its", "learned_its", "fallbacks", "stencil_steps")}, u2.clone()))
+    assert warm[0][0] == warm[1][0] and torch.equal(warm[0][1], warm[1][1])
+    assert warm[0][0]["learned_its"] + warm[0][0]["fallbacks"] == warm[0][0]["outer_its"]
+    o.use_learned = 1
     # the learned form still reaches the complex-double solution
     o.rtol = 1e-12
     o.precision = mxp.MXP_PREC_FP64

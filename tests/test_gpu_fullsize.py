@@ -227,18 +227,27 @@ def test_config1_counts_against_stored_oracle_run(ctx, prec):
 
 
 def test_full_solve_2048_true_residual(ctx):
-    # the benchmarked mixed solve; its residual recomputed with the oracle's matrix
+    # the mixed solve at 2048^2: outer count within +-1 of the complex-double
+    # solve's, its solution close to that one, and its residual recomputed with
+    # the oracle's matrix
     prob = wl.config2()
     announce("full solve", prob.name)
     P = mxp.Problem(ctx, prob)
     f = wl.delta_source(prob, (1024, 1024)).ravel()
+    fd = to_dev(f)
+    u64 = torch.zeros_like(fd)
+    st64 = mxp.mxp_solve(P, P.default_opts(), fd, u64)
     o = P.default_opts()
     o.precision = mxp.MXP_PREC_MIXED
-    fd = to_dev(f)
     ud = torch.zeros_like(fd)
     st = mxp.mxp_solve(P, o, fd, ud)
+    assert st64["status"] == mxp.MXP_OK
+    assert abs(st["outer_its"] - st64["outer_its"]) <= 1, (st["outer_its"], st64["outer_its"])
+    # both meet 1e-6 in the residual; the solutions differ by about the same
+    # relative amount (measured 1.8e-6)
+    assert ((ud - u64).norm() / u64.norm()).item() <= 1e-5
     u = to_host(ud)
-    del fd, ud
+    del fd, ud, u64
     P.close()
     assert st["status"] == mxp.MXP_OK
     A = op.helmholtz(prob, 0.0)
