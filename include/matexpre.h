@@ -298,6 +298,21 @@ mxp_status mxp_apply_A(mxp_problem* prob, double shift, mxp_dtype dtype, const v
 mxp_status mxp_apply_exp(mxp_problem* prob, double t, double shift, mxp_dtype dtype,
                          const void* x, void* y);
 
+/* y = exp(i t A_s) x as mxp_apply_exp, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the call allocates nothing.  Its Clenshaw buffers and
+ * the schedule's diagonal tables live in a fixed 64 MiB device array that
+ * every GPU the library runs on holds until the process ends; the schedule is
+ * designed on the host at every call and 2D problems use the tiles
+ * mxp_apply_exp tuned, else six Clenshaw levels per pass.  Calls on one GPU
+ * share the array (each call finds it as the last one left it and overwrites
+ * it): calls that overlap on one GPU, from several host threads, race.
+ * Errors: as mxp_apply_exp; INVALID_ARG also when six vectors of the problem
+ * plus its tables exceed 64 MiB (about 690k nodes in complex double, 1.39M in
+ * complex float). */
+mxp_status mxp_apply_exp_noalloc(mxp_problem* prob, double t, double shift, mxp_dtype dtype, const void* x,
+                                 void* y);
+
 /* y = psi_1(i t A_s) x  (Section 3.1, Def. psi; t psi_1(i t A) equals the time
  * integral of exp(i tau A) over [0, t]). */
 mxp_status mxp_apply_psi1(mxp_problem* prob, double t, double shift, mxp_dtype dtype,

@@ -148,7 +148,7 @@ ABI_SYMBOLS = (
     "mxp_context_create", "mxp_context_destroy", "mxp_context_alloc_stats", "mxp_last_error", "mxp_version",
     "mxp_problem_create", "mxp_problem_destroy", "mxp_problem_size",
     "mxp_solve_opts_default", "mxp_design_schedule",
-    "mxp_apply_A", "mxp_apply_exp", "mxp_apply_psi1", "mxp_apply_psi2", "mxp_apply_fn_krylov", "mxp_apply_precond", "mxp_solve",
+    "mxp_apply_A", "mxp_apply_exp", "mxp_apply_exp_noalloc", "mxp_apply_psi1", "mxp_apply_psi2", "mxp_apply_fn_krylov", "mxp_apply_precond", "mxp_solve",
     "mxp_set_tiles", "mxp_get_tiles", "mxp_solve_batch",
     "mxp_cnn_num_params", "mxp_cnn_create", "mxp_cnn_destroy", "mxp_cnn_get_params", "mxp_cnn_set_params",
     "mxp_cnn_get_grads", "mxp_cnn_get_activations", "mxp_cnn_forward", "mxp_cnn_backward", "mxp_cnn_train_step", "mxp_cnn_make_sample",
@@ -180,6 +180,7 @@ def _load():
                                      ctypes.c_int, ctypes.POINTER(mxp_schedule)]),
         "mxp_apply_A": (st, [P, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_exp": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
+        "mxp_apply_exp_noalloc": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_psi1": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_psi2": (st, [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]),
         "mxp_apply_fn_krylov": (st, [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -422,6 +423,11 @@ def mxp_apply_A(prob: Problem, shift: float, x, y) -> None:
 
 def mxp_apply_exp(prob: Problem, t: float, shift: float, x, y) -> None:
     _check(lib.mxp_apply_exp(prob.handle, t, shift, _dtype_of(x), _ptr(x), _ptr(y)))
+
+
+def mxp_apply_exp_noalloc(prob: Problem, t: float, shift: float, x, y) -> None:
+    """mxp_apply_exp that allocates no device memory (fixed 64 MiB scratch)."""
+    _check(lib.mxp_apply_exp_noalloc(prob.handle, t, shift, _dtype_of(x), _ptr(x), _ptr(y)))
 
 
 def mxp_apply_psi1(prob: Problem, t: float, shift: float, x, y) -> None:

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmatexpre.so")
 
 SOURCES = ["kernels.hip", "cheb2d.hip", "cheb3d.hip", "cnn.hip", "schedule.cpp", "action.cpp", "krylov.cpp",
-           "batch.cpp", "api.cpp", "network.cpp", "checkpoint.cpp"]
+           "batch.cpp", "api.cpp", "network.cpp", "checkpoint.cpp",
+           "noalloc.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
