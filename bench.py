@@ -663,7 +663,8 @@ def main():
     ap.add_argument("--roofline-reps", type=int, default=3)
     ap.add_argument("--graphs", action="store_true", help="replay matrix-function actions from HIP graphs")
     ap.add_argument("--tiles", default=None,
-                    help="K,NX,Ly of the fused 2D passes for both precisions (default: autotuned)")
+                    help="K,NX,Ly of the fused 2D passes for both precisions, or K,NX,Ly/K,NX,Ly for "
+                         "complex double / complex float (default: autotuned)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="skip the solves: run only the exp-action timing loop and a plain "
                          "1 GiB device copy (counter calibration); for profiler runs")
@@ -715,8 +716,11 @@ def main():
     if args.fp64_below is not None:
         o_mixed.fp64_below = args.fp64_below
     if args.tiles:
-        K_, NX_, Ly_ = (int(v) for v in args.tiles.split(","))
-        for prec in (mxp.MXP_PREC_FP64, mxp.MXP_PREC_MIXED):
+        parts = args.tiles.split("/")
+        if len(parts) == 1:
+            parts = parts * 2
+        for prec, part in zip((mxp.MXP_PREC_FP64, mxp.MXP_PREC_MIXED), parts):
+            K_, NX_, Ly_ = (int(v) for v in part.split(","))
             mxp.mxp_set_tiles(P, prec, K_, NX_, Ly_)
     print(f"[bench] {prob.name}: n={prob.n} omega={prob.omega:.2f} t={o64.t:.3e} "
           f"s={o64.shift:.4f}", file=sys.stderr, flush=True)
