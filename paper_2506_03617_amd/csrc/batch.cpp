@@ -21,9 +21,11 @@ namespace mxp {
 // and HIP stream.  Each matrix-function action a thread needs becomes a
 // request; when every active thread has one pending, the requests run as one
 // lockstep action: step k of every request is launched before step k + 1 of
-// any, and the 3D sweeps of one step that share an operand set go out as a
-// single launch over all their grids (uneven sizes included).  The 2D
-// temporally blocked passes are launched per request within the same step.
+// any.  The 3D sweeps of one step that share an operand set go out as a
+// single launch over all their grids (uneven sizes included), and so do the
+// 2D temporally blocked passes of one step that share K and NX; both batched
+// kernels are persistent (resident workgroups striding over every grid's
+// tiles).
 
 struct ActionReq {
     Run* run;
@@ -106,10 +108,10 @@ class Batcher {
         }
     }
 
-    struct Group {  // one batched 3D launch
+    struct Group {  // one batched launch
         int prec;   // 0 double, 1 float
-        int kind;   // 0 sweeps, 2 two-level passes
-        int ops;    // operand set / variant
+        int kind;   // 0 3D sweeps, 1 2D passes, 2 3D two-level passes
+        int ops;    // operand set / variant; 2D passes: K * 4 + NX
         size_t jobs_off, lut_off;
         int64_t blocks;
     };
@@ -151,6 +153,16 @@ class Batcher {
     }
 
     template <typename R>
+    static void add_passes2d(std::vector<unsigned char>& buf, Group& g, const std::vector<const StepRec<R>*>& ps) {
+        std::vector<Cheb2DJob<R>> jobs(ps.size());
+        for (size_t q = 0; q < ps.size(); ++q) {
+            jobs[q].a = prepare_cheb2d(ps[q]->cp, ps[q]->K, ps[q]->NX);
+            jobs[q].blocks = cheb2d_blocks(jobs[q].a);
+        }
+        add_table(buf, g, jobs);
+    }
+
+    template <typename R>
     static void add_jobs(std::vector<unsigned char>& buf, Group& g, const std::vector<const StencilArgs<R>*>& sw) {
         std::vector<Sweep3DJob<R>> jobs(sw.size());
         for (size_t q = 0; q < sw.size(); ++q) {
@@ -186,7 +198,13 @@ class Batcher {
             std::map<int, std::vector<const StencilArgs<float>*>> g32;
             std::map<int, std::vector<const ChebPass3DArgs<double>*>> p64;
             std::map<int, std::vector<const ChebPass3DArgs<float>*>> p32;
+            std::map<int, std::vector<const StepRec<double>*>> f64;
+            std::map<int, std::vector<const StepRec<float>*>> f32;
             for (size_t i = 0; i < nq; ++i) {
+                if (k < r64[i].size() && r64[i][k].kind == 1)
+                    f64[r64[i][k].K * 4 + r64[i][k].NX].push_back(&r64[i][k]);
+                if (k < r32[i].size() && r32[i][k].kind == 1)
+                    f32[r32[i][k].K * 4 + r32[i][k].NX].push_back(&r32[i][k]);
                 if (k < r64[i].size() && r64[i][k].kind == 0 && r64[i][k].st.dim == 3)
                     g64[sweep_ops(r64[i][k].st)].push_back(&r64[i][k].st);
                 if (k < r32[i].size() && r32[i][k].kind == 0 && r32[i][k].st.dim == 3)
@@ -204,6 +222,16 @@ class Batcher {
             for (auto& kv : g32) {
                 Group g{1, 0, kv.first, 0, 0, 0};
                 add_jobs<float>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+            for (auto& kv : f64) {
+                Group g{0, 1, kv.first, 0, 0, 0};
+                add_passes2d<double>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+            for (auto& kv : f32) {
+                Group g{1, 1, kv.first, 0, 0, 0};
+                add_passes2d<float>(buf, g, kv.second);
                 plan[k].push_back(g);
             }
             for (auto& kv : p64) {
@@ -232,23 +260,23 @@ class Batcher {
         }
         const unsigned char* dev = table_.as<unsigned char>();
         for (size_t k = 0; k < L; ++k) {
-            // launches that are not batched: 2D passes and 2D sweeps (3D
-            // sweeps and 3D passes go out in the grouped launches below)
+            // launches that are not batched: 2D sweeps (the unfused path;
+            // every other step goes out in the grouped launches below)
             for (size_t i = 0; i < nq; ++i) {
-                if (k < r64[i].size()) {
-                    const StepRec<double>& r = r64[i][k];
-                    if (r.kind == 1) launch_cheb2d<double>(r.cp, r.K, r.NX, s_);
-                    else if (r.kind == 0 && r.st.dim != 3) launch_stencil(r.st, s_);
-                }
-                if (k < r32[i].size()) {
-                    const StepRec<float>& r = r32[i][k];
-                    if (r.kind == 1) launch_cheb2d<float>(r.cp, r.K, r.NX, s_);
-                    else if (r.kind == 0 && r.st.dim != 3) launch_stencil(r.st, s_);
-                }
+                if (k < r64[i].size() && r64[i][k].kind == 0 && r64[i][k].st.dim != 3)
+                    launch_stencil(r64[i][k].st, s_);
+                if (k < r32[i].size() && r32[i][k].kind == 0 && r32[i][k].st.dim != 3)
+                    launch_stencil(r32[i][k].st, s_);
             }
             for (const Group& g : plan[k]) {
                 const uint32_t* lut = reinterpret_cast<const uint32_t*>(dev + g.lut_off);
-                if (g.kind == 2 && g.prec == 0)
+                if (g.kind == 1 && g.prec == 0)
+                    launch_cheb2d_batch<double>(reinterpret_cast<const Cheb2DJob<double>*>(dev + g.jobs_off), lut,
+                                                g.blocks, g.ops / 4, g.ops % 4, s_);
+                else if (g.kind == 1)
+                    launch_cheb2d_batch<float>(reinterpret_cast<const Cheb2DJob<float>*>(dev + g.jobs_off), lut,
+                                               g.blocks, g.ops / 4, g.ops % 4, s_);
+                else if (g.kind == 2 && g.prec == 0)
                     launch_cheb3d_batch<double>(reinterpret_cast<const Cheb3DJob<double>*>(dev + g.jobs_off), lut,
                                                 g.blocks, g.ops, s_);
                 else if (g.kind == 2)
@@ -369,15 +397,27 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
             for (int r = 0; r < nrhs[q]; ++r)
                 items.push_back({P, &o, static_cast<const cpx<double>*>(f[q]) + size_t(r) * n,
                                  static_cast<cpx<double>*>(u[q]) + size_t(r) * n, bytes});
+            // steps of one action: the longest schedule the solve may use
+            auto action_steps = [](const Sched& x) {
+                const int mmax = std::max(std::max(x.s.m, x.s.m_psi), std::max(x.m_psi2, 0));
+                return size_t(x.s.S + 2) * size_t(mmax + 1);
+            };
+            size_t steps = action_steps(sd);
+            if (switches) steps = std::max(steps, action_steps(get_sched(P, o.t, o.shift, MXP_PREC_FP64, o.cheb_S, o.cheb_m)));
             if (P->g.dim == 3) {
                 // job-table bytes per right-hand side and step: the job, two
                 // alignments and one lookup entry per 64 workgroups (tiles no
                 // smaller than 62 x 4 nodes, z segments of at least 8 planes)
-                const int mmax = std::max(std::max(sd.s.m, sd.s.m_psi), std::max(sd.m_psi2, 0));
-                const size_t steps = size_t(sd.s.S + 2) * size_t(mmax + 1);
                 const int64_t blocks = ((P->g.n[0] + 61) / 62) * ((P->g.n[1] + 3) / 4) * ((P->g.n[2] + 7) / 8);
                 const size_t per = sizeof(Cheb3DJob<double>) + sizeof(Sweep3DJob<double>) + 1024 +
                                    4 * size_t(blocks / 64 + 1);
+                table_steps = std::max(table_steps, steps);
+                table_per_rhs = std::max(table_per_rhs, per);
+            } else {
+                // 2D: one pass job per right-hand side and step (strips at
+                // least 48 columns wide, segments of at least one row)
+                const int64_t blocks = ((P->g.n[0] + 47) / 48) * P->g.n[1] / 4 + 1;
+                const size_t per = sizeof(Cheb2DJob<double>) + 1024 + 4 * size_t(blocks / 64 + 1);
                 table_steps = std::max(table_steps, steps);
                 table_per_rhs = std::max(table_per_rhs, per);
             }

@@ -31,6 +31,7 @@
 
 #include <utility>
 
+#include "devmem.h"
 #include "kernels.h"
 #include "mxp_internal.h"
 
@@ -97,6 +98,16 @@ __device__ __forceinline__ cpx<R> sload(const cpx<R>* p, int idx) {
 template <typename R>
 __device__ __forceinline__ R sload_r(const R* p, int idx) {
     return ((const __attribute__((address_space(4))) R*)(p))[idx];
+}
+// A whole uniform struct through the scalar cache, one dword at a time.
+template <class T>
+__device__ __forceinline__ T sload_words(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized struct expected");
+    const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)(p);
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = q[i];
+    return __builtin_bit_cast(T, w);
 }
 
 // The fields of ChebPassArgs a pass reads, copied out of the kernel argument
@@ -388,14 +399,11 @@ struct Pass2D {
     }
 };
 
+// One wavefront's share of a pass: strip and row segment number wv of the
+// grid (strips vary fastest), with its LDS ring rows xs and dg.
 template <typename R, int K, int NX>
-__global__ __launch_bounds__(256) void k_cheb2d(ChebPassArgs<R> a) {
-    constexpr int M = ring_rows<K>();
-    __shared__ cpx<R> xs_all[4][M * 64 * NX];
-    __shared__ cpx<R> dg_all[4][M * 64 * NX];
+__device__ __forceinline__ void pass2d(const ChebPassArgs<R>& a, int wv, cpx<R>* xs, cpx<R>* dg) {
     const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const int wv = int(blockIdx.x) * 4 + wid;
     const int strip = wv % a.strips;
     const int seg = wv / a.strips;
     PassParams<R, K> pp;
@@ -407,8 +415,6 @@ __global__ __launch_bounds__(256) void k_cheb2d(ChebPassArgs<R> a) {
     const int X0 = strip * a.W;
     ps.cbase = X0 - K + lane * NX;
     ps.lane = lane;
-    cpx<R>* xs = xs_all[wid];
-    cpx<R>* dg = dg_all[wid];
     const cpx<R> zero{R(0), R(0)};
 #pragma unroll
     for (int e = 0; e < NX; ++e) {
@@ -436,6 +442,50 @@ __global__ __launch_bounds__(256) void k_cheb2d(ChebPassArgs<R> a) {
 }
 
 template <typename R, int K, int NX>
+__global__ __launch_bounds__(256) void k_cheb2d(ChebPassArgs<R> a) {
+    constexpr int M = ring_rows<K>();
+    __shared__ cpx<R> xs_all[4][M * 64 * NX];
+    __shared__ cpx<R> dg_all[4][M * 64 * NX];
+    const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    pass2d<R, K, NX>(a, int(blockIdx.x) * 4 + wid, xs_all[wid], dg_all[wid]);
+}
+
+// Batched form over the passes of many grids (one K, NX): a persistent grid
+// of resident workgroups strides over the concatenated workgroup ranges of
+// the jobs.  The job of range index w comes from a lookup table with one
+// entry per 64 indices, and its description is read through the scalar
+// cache (uniform across the workgroup).  The wavefronts of a workgroup share
+// no data, so each leaves a job's range on its own.
+template <typename R, int K, int NX>
+__device__ __forceinline__ void cheb2d_batch_body(const Cheb2DJob<R>* jobs, const uint32_t* lut, int total) {
+    constexpr int M = ring_rows<K>();
+    __shared__ cpx<R> xs_all[4][M * 64 * NX];
+    __shared__ cpx<R> dg_all[4][M * 64 * NX];
+    const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const __attribute__((address_space(4))) uint32_t* lq = (const __attribute__((address_space(4))) uint32_t*)(lut);
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const uint32_t q = lq[w >> 6];
+        const Cheb2DJob<R> job = sload_words(jobs + q);
+        const int local = w - int(job.block0);
+        if (local >= int(job.blocks)) continue;
+        pass2d<R, K, NX>(job.a, local * 4 + wid, xs_all[wid], dg_all[wid]);
+    }
+}
+
+template <typename R, int K, int NX>
+__global__ __launch_bounds__(256) void k_cheb2d_batch(const Cheb2DJob<R>* jobs, const uint32_t* lut, int total) {
+    cheb2d_batch_body<R, K, NX>(jobs, lut, total);
+}
+// The same, held to two wavefronts per SIMD: for the shapes whose
+// single-grid pass fits two and whose loop state would otherwise tip the
+// register count past 256 (complex double, K = 6, NX = 1).
+template <typename R, int K, int NX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_cheb2d_batch_w2(
+    const Cheb2DJob<R>* jobs, const uint32_t* lut, int total) {
+    cheb2d_batch_body<R, K, NX>(jobs, lut, total);
+}
+
+template <typename R, int K, int NX>
 void launch_k(const ChebPassArgs<R>& a, hipStream_t s) {
     if constexpr (sizeof(R) == 8 && NX == 2 && K > 3) {
         // register- and LDS-limited shape: not built
@@ -446,6 +496,60 @@ void launch_k(const ChebPassArgs<R>& a, hipStream_t s) {
         const int waves = a.strips * a.segs;
         const int blocks = (waves + 3) / 4;
         hipLaunchKernelGGL((k_cheb2d<R, K, NX>), dim3(blocks), dim3(256), 0, s, a);
+    }
+}
+
+// Resident workgroups of a batched kernel: its occupancy per compute unit
+// (asked once per instantiation) times the device's compute units, at most
+// `total`.
+template <typename Kern>
+int64_t persistent_grid(Kern kern, int64_t total) {
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int n = 0;
+        HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kern), 256, 0));
+        per_cu = n > 0 ? n : 1;
+    }
+    int dev = 0, cus = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t slots = int64_t(per_cu) * (cus > 0 ? cus : 1);
+    return total < slots ? total : slots;
+}
+
+template <typename R, int K, int NX>
+void launch_k_batch(const Cheb2DJob<R>* jobs, const uint32_t* lut, int64_t total, hipStream_t s) {
+    if constexpr (sizeof(R) == 8 && NX == 2 && K > 3) {
+        (void)jobs;
+        (void)lut;
+        (void)total;
+        (void)s;
+        fail(MXP_ERR_UNSUPPORTED, "complex-double passes with NX = 2 support K <= 3");
+    } else {
+        if constexpr (sizeof(R) == 8 && K == 6 && NX == 1) {
+            const int64_t g = persistent_grid(k_cheb2d_batch_w2<R, K, NX>, total);
+            hipLaunchKernelGGL((k_cheb2d_batch_w2<R, K, NX>), dim3(unsigned(g)), dim3(256), 0, s, jobs, lut,
+                               int(total));
+        } else {
+            const int64_t g = persistent_grid(k_cheb2d_batch<R, K, NX>, total);
+            hipLaunchKernelGGL((k_cheb2d_batch<R, K, NX>), dim3(unsigned(g)), dim3(256), 0, s, jobs, lut,
+                               int(total));
+        }
+    }
+}
+
+template <typename R, int NX>
+void launch_nx_batch(const Cheb2DJob<R>* jobs, const uint32_t* lut, int64_t total, int K, hipStream_t s) {
+    switch (K) {
+        case 1: launch_k_batch<R, 1, NX>(jobs, lut, total, s); break;
+        case 2: launch_k_batch<R, 2, NX>(jobs, lut, total, s); break;
+        case 3: launch_k_batch<R, 3, NX>(jobs, lut, total, s); break;
+        case 4: launch_k_batch<R, 4, NX>(jobs, lut, total, s); break;
+        case 5: launch_k_batch<R, 5, NX>(jobs, lut, total, s); break;
+        case 6: launch_k_batch<R, 6, NX>(jobs, lut, total, s); break;
+        case 7: launch_k_batch<R, 7, NX>(jobs, lut, total, s); break;
+        case 8: launch_k_batch<R, 8, NX>(jobs, lut, total, s); break;
+        default: fail(MXP_ERR_INVALID_ARG, "fused level count must be 1..8");
     }
 }
 
@@ -477,8 +581,9 @@ template void cheb2d_geometry<float>(ChebPassArgs<float>&, int, int, int);
 template void cheb2d_geometry<double>(ChebPassArgs<double>&, int, int, int);
 
 template <typename R>
-void launch_cheb2d(const ChebPassArgs<R>& in, int K, int NX, hipStream_t s) {
+ChebPassArgs<R> prepare_cheb2d(const ChebPassArgs<R>& in, int K, int NX) {
     if (K < 1 || K > kMaxFused) fail(MXP_ERR_INVALID_ARG, "fused level count out of range");
+    if (NX != 1 && NX != 2) fail(MXP_ERR_INVALID_ARG, "NX must be 1 or 2");
     if (uint64_t(in.n0) * uint64_t(in.n1) * sizeof(cpx<R>) >= (uint64_t(1) << 32))
         fail(MXP_ERR_UNSUPPORTED, "fused 2D passes need vectors below 4 GiB");
     if (in.W != NX * 64 - 2 * K || in.W <= 0) fail(MXP_ERR_INVALID_ARG, "pass geometry does not match K, NX");
@@ -495,15 +600,45 @@ void launch_cheb2d(const ChebPassArgs<R>& in, int K, int NX, hipStream_t s) {
         a.e3 = R(0);
     }
     if (!a.final_pass && !a.outA) fail(MXP_ERR_INVALID_ARG, "a non-final pass writes two levels");
+    return a;
+}
+
+template <typename R>
+int64_t cheb2d_blocks(const ChebPassArgs<R>& a) {
+    return (int64_t(a.strips) * a.segs + 3) / 4;
+}
+
+template <typename R>
+void launch_cheb2d(const ChebPassArgs<R>& in, int K, int NX, hipStream_t s) {
+    const ChebPassArgs<R> a = prepare_cheb2d(in, K, NX);
     if (NX == 1)
         launch_nx<R, 1>(a, K, s);
-    else if (NX == 2)
-        launch_nx<R, 2>(a, K, s);
     else
-        fail(MXP_ERR_INVALID_ARG, "NX must be 1 or 2");
+        launch_nx<R, 2>(a, K, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) fail(MXP_ERR_HIP, std::string("cheb2d launch failed: ") + hipGetErrorString(e));
 }
+
+template <typename R>
+void launch_cheb2d_batch(const Cheb2DJob<R>* jobs, const uint32_t* lut, int64_t total_blocks, int K, int NX,
+                         hipStream_t s) {
+    if (total_blocks <= 0) return;
+    if (total_blocks > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "batched 2D pass too large");
+    if (NX == 1)
+        launch_nx_batch<R, 1>(jobs, lut, total_blocks, K, s);
+    else if (NX == 2)
+        launch_nx_batch<R, 2>(jobs, lut, total_blocks, K, s);
+    else
+        fail(MXP_ERR_INVALID_ARG, "NX must be 1 or 2");
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(MXP_ERR_HIP, std::string("batched cheb2d launch failed: ") + hipGetErrorString(e));
+}
+template ChebPassArgs<float> prepare_cheb2d<float>(const ChebPassArgs<float>&, int, int);
+template ChebPassArgs<double> prepare_cheb2d<double>(const ChebPassArgs<double>&, int, int);
+template int64_t cheb2d_blocks<float>(const ChebPassArgs<float>&);
+template int64_t cheb2d_blocks<double>(const ChebPassArgs<double>&);
+template void launch_cheb2d_batch<float>(const Cheb2DJob<float>*, const uint32_t*, int64_t, int, int, hipStream_t);
+template void launch_cheb2d_batch<double>(const Cheb2DJob<double>*, const uint32_t*, int64_t, int, int, hipStream_t);
 template void launch_cheb2d<float>(const ChebPassArgs<float>&, int, int, hipStream_t);
 template void launch_cheb2d<double>(const ChebPassArgs<double>&, int, int, hipStream_t);
 

@@ -135,6 +135,26 @@ template <typename R>
 void cheb2d_geometry(ChebPassArgs<R>& a, int K, int NX, int Ly);
 template <typename R>
 void launch_cheb2d(const ChebPassArgs<R>& a, int K, int NX, hipStream_t s);
+// Checks a pass against K, NX and points absent operands at x with their
+// flags set, as launch_cheb2d does before a launch.
+template <typename R>
+ChebPassArgs<R> prepare_cheb2d(const ChebPassArgs<R>& a, int K, int NX);
+// Workgroups of one pass (four wavefronts each, one strip segment per wavefront).
+template <typename R>
+int64_t cheb2d_blocks(const ChebPassArgs<R>& a);
+// Batched form over the passes of grids of different sizes with one K, NX:
+// each job holds prepared arguments and its range [block0, block0 + blocks)
+// of workgroup indices (block0 a multiple of 64); lut maps each 64 indices
+// to their job.  A persistent grid of resident workgroups covers
+// total_blocks indices.
+template <typename R>
+struct Cheb2DJob {
+    ChebPassArgs<R> a;
+    int64_t block0, blocks;
+};
+template <typename R>
+void launch_cheb2d_batch(const Cheb2DJob<R>* jobs, const uint32_t* lut, int64_t total_blocks, int K, int NX,
+                         hipStream_t s);
 
 // Complex-double BLAS-1 and deterministic reductions.  Vectors have length n;
 // a "block" V holds nv vectors of length n back to back (stride ld >= n).

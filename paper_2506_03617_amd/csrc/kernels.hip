@@ -9,6 +9,7 @@
 
 #include <utility>
 
+#include "devmem.h"
 #include "kernels.h"
 #include "mxp_internal.h"
 
@@ -333,20 +334,24 @@ __global__ __launch_bounds__(256) void k_stencil3d(StencilArgs<R> a, Sweep3DGeom
     sweep3d<R, OPS, sweep_rows<R>()>(a, m, t);
 }
 
-// Batched form: the job of a workgroup comes from a lookup table with one
-// entry per 64 workgroups, and its description is read through the scalar
-// cache (uniform across the workgroup).
+// Batched form over grids of different sizes: a persistent grid of resident
+// workgroups (a multiple of eight, so that index w keeps the XCD of w mod 8)
+// strides over the concatenated workgroup ranges of the jobs.  The job of
+// range index w comes from a lookup table with one entry per 64 indices, and
+// its description is read through the scalar cache (uniform across the
+// workgroup).  The wavefronts of a workgroup share no data.
 template <typename R, int OPS>
-__global__ __launch_bounds__(256) void k_stencil3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut) {
-    const int b = blockIdx.x;
+__global__ __launch_bounds__(256) void k_stencil3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut, int total) {
     const __attribute__((address_space(4))) uint32_t* lq = (const __attribute__((address_space(4))) uint32_t*)(lut);
-    const int q = lq[b >> 6];
-    const Sweep3DJob<R> job = sload_words(jobs + q);
-    const int64_t local = int64_t(b) - job.block0;
-    if (local >= job.geom.blocks) return;
-    const int64_t t = xcd_tile(local, job.geom.tiles, job.geom.blocks);
-    if (t < 0) return;
-    sweep3d<R, OPS, sweep_rows<R>()>(job.a, job.geom, t);
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const uint32_t q = lq[w >> 6];
+        const Sweep3DJob<R> job = sload_words(jobs + q);
+        const int local = w - int(job.block0);
+        if (local >= int(job.geom.blocks)) continue;
+        const int64_t t = xcd_tile(local, job.geom.tiles, job.geom.blocks);
+        if (t < 0) continue;
+        sweep3d<R, OPS, sweep_rows<R>()>(job.a, job.geom, t);
+    }
 }
 
 template <typename R, int OPS>
@@ -361,14 +366,30 @@ void launch_3d(const StencilArgs<R>& a, const Sweep3DGeom& m, unsigned nb, int o
 }
 
 template <typename R, int OPS>
-void launch_3d_batch_ops(const Sweep3DJob<R>* jobs, const uint32_t* lut, unsigned nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_stencil3d_batch<R, OPS>), dim3(nb), dim3(kSweepW, 1, 1), 0, s, jobs, lut);
+void launch_3d_batch_ops(const Sweep3DJob<R>* jobs, const uint32_t* lut, int64_t total, hipStream_t s) {
+    // resident workgroups: occupancy (asked once per instantiation) times the
+    // compute units, rounded down to a multiple of eight, at most the total
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int n = 0;
+        HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(k_stencil3d_batch<R, OPS>), kSweepW, 0));
+        per_cu = n > 0 ? n : 1;
+    }
+    int dev = 0, cus = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t g = int64_t(per_cu) * (cus > 0 ? cus : 1);
+    g = g >= 8 ? g / 8 * 8 : g;
+    if (g > total) g = total;
+    hipLaunchKernelGGL((k_stencil3d_batch<R, OPS>), dim3(unsigned(g)), dim3(kSweepW, 1, 1), 0, s, jobs, lut,
+                       int(total));
 }
 
 template <typename R, int... OPS>
-void launch_3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut, unsigned nb, int ops, hipStream_t s,
+void launch_3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut, int64_t total, int ops, hipStream_t s,
                      std::integer_sequence<int, OPS...>) {
-    ((ops == OPS ? launch_3d_batch_ops<R, OPS>(jobs, lut, nb, s) : void()), ...);
+    ((ops == OPS ? launch_3d_batch_ops<R, OPS>(jobs, lut, total, s) : void()), ...);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -584,7 +605,7 @@ void launch_stencil3d_batch(const Sweep3DJob<R>* jobs, const uint32_t* lut, int6
                             hipStream_t s) {
     if (total_blocks <= 0) return;
     if (total_blocks > 0x7fffffff) fail(MXP_ERR_UNSUPPORTED, "batched 3D sweep too large");
-    launch_3d_batch<R>(jobs, lut, unsigned(total_blocks), ops, s, std::make_integer_sequence<int, 16>{});
+    launch_3d_batch<R>(jobs, lut, total_blocks, ops, s, std::make_integer_sequence<int, 16>{});
     check_launch("batched 3D sweep");
 }
 template void launch_stencil3d_batch<double>(const Sweep3DJob<double>*, const uint32_t*, int64_t, int, hipStream_t);

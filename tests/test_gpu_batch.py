@@ -2,9 +2,9 @@
 
 Every right-hand side of a batch runs the same arithmetic as a separate
 mxp_solve on the same problem (the lockstep batching only reorders launches
-across right-hand sides, and the batched 3D sweep computes each grid point as
-the single-grid sweep does), so solutions and statistics must agree bit for
-bit.  The separate solves are themselves pinned to the oracle by the parity
+across right-hand sides, and the batched 3D sweep and 2D pass compute each
+grid point as the single-grid kernels do), so solutions and statistics must
+agree bit for bit.  The separate solves are themselves pinned to the oracle by the parity
 tests; here a few batched right-hand sides are also checked against the oracle
 directly, and the full-size layered batch against its true residuals."""
 import numpy as np
@@ -73,6 +73,46 @@ def test_batch_equals_separate_solves_bit_for_bit(ctx, prec, two_level):
         o = h.default_opts()
         o.precision = prec
         o.outer_restart = 20
+        opts.append(o)
+    status, stats, us = run_batch(ctx, handles, opts, rhs)
+    assert status == mxp.MXP_OK
+    k = 0
+    for q, h in enumerate(handles):
+        for r in range(rhs[q].shape[0]):
+            fd = to_dev(rhs[q][r])
+            ud = torch.zeros_like(fd)
+            st = mxp.mxp_solve(h, opts[q], fd, ud)
+            assert st["status"] == mxp.MXP_OK and stats[k]["status"] == mxp.MXP_OK
+            for key in ("outer_its", "inner_its_total", "stencil_steps", "fn_actions", "true_relres"):
+                assert stats[k][key] == st[key], (q, r, key)
+            assert np.array_equal(us[q][r], to_host(ud)), (q, r)
+            k += 1
+    for h in handles:
+        h.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_2d_passes_equal_separate_solves(ctx, prec):
+    """Uneven 2D grids in one batch: each step's fused passes go out as one
+    persistent launch per (K, NX) over every grid (two tile shapes here, so
+    two groups), and every right-hand side keeps the separate solve's bits."""
+    probs = [wl.small_problem((97, 61), layer=8, ppw=10, inhomogeneous=True, seed=31, name="e"),
+             wl.small_problem((130, 45), layer=8, ppw=10, inhomogeneous=True, seed=32, name="f"),
+             wl.small_problem((70, 83), layer=8, ppw=10, inhomogeneous=False, seed=33, name="g")]
+    tiles = [(4, 1, 8), (6, 1, 12), (4, 1, 8)]
+    rhs = []
+    for q, p in enumerate(probs):
+        rng = np.random.default_rng(200 + q)
+        fs = [wl.delta_source(p, tuple(int(rng.integers(p.layer + 1, m - p.layer - 1)) for m in p.n)).ravel()
+              for _ in range(2)]
+        rhs.append(np.stack(fs))
+    announce("batched 2D passes", prec, [p.n for p in probs])
+    handles = [mxp.Problem(ctx, p) for p in probs]
+    opts = []
+    for h, (K, NX, Ly) in zip(handles, tiles):
+        mxp.mxp_set_tiles(h, prec, K, NX, Ly)
+        o = h.default_opts()
+        o.precision = prec
         opts.append(o)
     status, stats, us = run_batch(ctx, handles, opts, rhs)
     assert status == mxp.MXP_OK
