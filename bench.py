@@ -366,6 +366,10 @@ def bench_learned(args, torch, mxp, wl):
     res = {}
     print(f"[bench] network forward at {ne}^3: {t_fwd * 1e3:.2f} ms", file=sys.stderr, flush=True)
     mxp.mxp_problem_set_learned(P, net, kappa)
+    # untimed warm-up: schedules, tiles and workspaces of the evaluation grid
+    # (both precisions of the mixed form) are set up before any timed solve
+    o.use_learned = 0
+    mxp.mxp_solve(P, o, f, u)
     for mode in ("plain", "learned", "warm"):
         # learned: the network's direction tried first at every outer iteration;
         # warm: its output starts the inner GMRES of every preconditioner apply
@@ -382,7 +386,7 @@ def bench_learned(args, torch, mxp, wl):
               f"fallbacks {st['fallbacks']}, relres {st['true_relres']:.2e}", file=sys.stderr, flush=True)
     line = {
         "metric": "s to 1e-6 rel. residual (plain vs FP32/learned); stencil HBM GB/s vs peak",
-        "value": round(res["learned"]["wall"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "value": round(res["learned"]["wall"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": round(res["learned"]["wall"] * 1e3, 1), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16 network + c64 stepping and inner basis + c128 Krylov sums and outer solve",
         "data": "synthetic (seeded layered models, point sources); pairs generated by the solver",
