@@ -426,24 +426,53 @@ constexpr int kMaxBlocks = 1024;
 __device__ __forceinline__ cpx<double> widen(cpx<double> v) { return v; }
 __device__ __forceinline__ cpx<double> widen(cpx<float> v) { return {double(v.re), double(v.im)}; }
 
-// TV: the basis' element type (complex double, or complex float for the
-// inner GMRES of the mixed form); w and all arithmetic are complex double.
+// Partial sums of conj(V_q) . w for a group of up to kDotGroup basis
+// vectors q = blockIdx.y * kDotGroup + i: each work-item loads w[p] once for
+// the whole group and accumulates one sum per vector, so w is read once per
+// group instead of once per vector.  Every sum is accumulated in the same
+// order as a one-vector kernel would (grid-stride p, then the wavefront
+// butterfly, then the four wavefronts in order), so the result does not
+// depend on the grouping.  TV: the basis' element type (complex double, or
+// complex float for the inner GMRES of the mixed form); w and all arithmetic
+// are complex double.
+constexpr int kDotGroup = 8;
+
 template <typename TV>
-__global__ __launch_bounds__(256) void k_mdot_partial(const TV* __restrict__ V, int64_t ld,
+__global__ __launch_bounds__(256) void k_mdot_partial(const TV* __restrict__ V, int64_t ld, int nv,
                                                       const cpx<double>* __restrict__ w, int64_t n,
                                                       cpx<double>* __restrict__ partial) {
-    const int vi = blockIdx.y;
-    const TV* __restrict__ Vi = V + int64_t(vi) * ld;
-    cpx<double> acc{0.0, 0.0};
+    __shared__ cpx<double> red[4][kDotGroup];
+    const int q0 = int(blockIdx.y) * kDotGroup;
+    const int g = nv - q0 < kDotGroup ? nv - q0 : kDotGroup;  // uniform
+    cpx<double> acc[kDotGroup];
+#pragma unroll
+    for (int i = 0; i < kDotGroup; ++i) acc[i] = {0.0, 0.0};
     const int64_t stride = int64_t(gridDim.x) * kRedThreads;
     for (int64_t p = int64_t(blockIdx.x) * kRedThreads + threadIdx.x; p < n; p += stride) {
-        const cpx<double> a = widen(Vi[p]), b = w[p];
-        // conj(a) * b
-        acc.re = fma(a.re, b.re, fma(a.im, b.im, acc.re));
-        acc.im = fma(a.re, b.im, fma(-a.im, b.re, acc.im));
+        const cpx<double> b = w[p];
+#pragma unroll
+        for (int i = 0; i < kDotGroup; ++i) {
+            if (i < g) {
+                const cpx<double> a = widen(V[int64_t(q0 + i) * ld + p]);
+                // conj(a) * b
+                acc[i].re = fma(a.re, b.re, fma(a.im, b.im, acc[i].re));
+                acc[i].im = fma(a.re, b.im, fma(-a.im, b.re, acc[i].im));
+            }
+        }
     }
-    const cpx<double> s = block_sum(acc);
-    if (threadIdx.x == 0) partial[int64_t(vi) * gridDim.x + blockIdx.x] = s;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < kDotGroup; ++i) {
+        const cpx<double> v = wave_sum(acc[i]);
+        if (lane == 0) red[wid][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < g) {
+        const int i = threadIdx.x;
+        cpx<double> r = red[0][i];
+        for (int k = 1; k < 4; ++k) r = cadd(r, red[k][i]);
+        partial[int64_t(q0 + i) * gridDim.x + blockIdx.x] = r;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_nrm2_partial(const cpx<double>* __restrict__ w, int64_t n,
@@ -621,7 +650,8 @@ template <typename TV>
 void launch_mdot(const TV* V, int64_t ld, int nv, const cpx<double>* w, int64_t n,
                  cpx<double>* partial, cpx<double>* out, hipStream_t s) {
     const int nb = reduce_blocks(n);
-    hipLaunchKernelGGL(k_mdot_partial<TV>, dim3(nb, nv), dim3(kRedThreads), 0, s, V, ld, w, n, partial);
+    const int groups = (nv + kDotGroup - 1) / kDotGroup;
+    hipLaunchKernelGGL(k_mdot_partial<TV>, dim3(nb, groups), dim3(kRedThreads), 0, s, V, ld, nv, w, n, partial);
     hipLaunchKernelGGL(k_partial_sum, dim3(nv), dim3(kRedThreads), 0, s, partial, nb, out);
     check_launch("mdot");
 }
