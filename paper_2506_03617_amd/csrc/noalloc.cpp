@@ -21,8 +21,9 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
 
-// Device address of `scratch` on `device` (current), looked up once per device:
-// each GPU holds its own copy of the array at its own address.
+// Device address of `scratch` on `device`, which must be the current device,
+// looked up once per device: each GPU holds its own copy of the array at its
+// own address.
 void* scratch_on(int device) {
     if (device < 0 || device >= kMaxDevices) fail(MXP_ERR_UNSUPPORTED, "device index beyond the scratch table");
     std::lock_guard<std::mutex> lk(g_scratch_mu);
@@ -55,6 +56,7 @@ extern "C" mxp_status mxp_apply_exp_noalloc(mxp_problem* prob, double t, double 
         if (need > kScratchBytes)
             fail(MXP_ERR_INVALID_ARG, "the action needs " + std::to_string(need) + " bytes of scratch, more than the " +
                                           std::to_string(kScratchBytes) + " bytes of the no-allocation path");
+        // check_problem made the problem's device current: the address is that device's copy
         unsigned char* base = static_cast<unsigned char*>(scratch_on(prob->ctx->device));
         hipStream_t s = prob->ctx->stream;
         const mxp_precision prec = dtype == MXP_C128 ? MXP_PREC_FP64 : MXP_PREC_MIXED;

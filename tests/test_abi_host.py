@@ -309,3 +309,21 @@ def test_absorbing_face_problems_validate_and_design():
     with pytest.raises(mxp.MxpError) as ei:
         mxp.mxp_design_schedule(bad, prob.default_t(), s, mxp.MXP_PREC_FP64)
     assert ei.value.status == mxp.MXP_ERR_INVALID_ARG
+
+
+def test_noalloc_action_checks_its_arguments_before_device_work():
+    """mxp_apply_exp_noalloc refuses a missing problem or vectors with
+    INVALID_ARG before it touches a device, and its source allocates nothing
+    and reaches its scratch only through the address looked up per device."""
+    import os
+    import re
+    st = mxp.lib.mxp_apply_exp_noalloc(None, ctypes.c_double(1e-3), ctypes.c_double(0.0), mxp.MXP_C128, None, None)
+    assert st == mxp.MXP_ERR_INVALID_ARG
+    src = open(os.path.join(os.path.dirname(mxp.__file__), "csrc", "noalloc.cpp")).read()
+    code = "\n".join(re.sub(r'"[^"]*"', '""', l.split("//")[0]) for l in src.splitlines())
+    assert not re.search(r"\bhip(Malloc|Free|MallocAsync|FreeAsync|HostMalloc)\s*\(", code)
+    assert not re.search(r"\b(ensure|reserve_\w+|alloc)\s*\(", code)
+    assert "hipGetSymbolAddress" in code and "static __device__ __align__(256)" in code
+    # the array's name appears only in its definition and the address lookup
+    uses = [l for l in code.splitlines() if re.search(r"\bscratch\b", l)]
+    assert len(uses) == 2, uses

@@ -95,16 +95,20 @@ def test_batch_equals_separate_solves_bit_for_bit(ctx, prec, two_level):
 def test_batched_2d_passes_equal_separate_solves(ctx, prec):
     """Uneven 2D grids in one batch: each step's fused passes go out as one
     persistent launch per (K, NX) over every grid (two tile shapes here, so
-    two groups), and every right-hand side keeps the separate solve's bits."""
+    two groups), and every right-hand side keeps the separate solve's bits.
+    The last grid's two-row segments give 1,350 workgroup indices per pass,
+    more than the device holds at once, so the persistent loop strides."""
     probs = [wl.small_problem((97, 61), layer=8, ppw=10, inhomogeneous=True, seed=31, name="e"),
              wl.small_problem((130, 45), layer=8, ppw=10, inhomogeneous=True, seed=32, name="f"),
-             wl.small_problem((70, 83), layer=8, ppw=10, inhomogeneous=False, seed=33, name="g")]
-    tiles = [(4, 1, 8), (6, 1, 12), (4, 1, 8)]
+             wl.small_problem((70, 83), layer=8, ppw=10, inhomogeneous=False, seed=33, name="g"),
+             wl.small_problem((1000, 600), layer=12, ppw=10, inhomogeneous=True, seed=34, name="h")]
+    tiles = [(4, 1, 8), (6, 1, 12), (4, 1, 8), (4, 1, 2)]
+    nrhs = [2, 2, 2, 1]
     rhs = []
     for q, p in enumerate(probs):
         rng = np.random.default_rng(200 + q)
         fs = [wl.delta_source(p, tuple(int(rng.integers(p.layer + 1, m - p.layer - 1)) for m in p.n)).ravel()
-              for _ in range(2)]
+              for _ in range(nrhs[q])]
         rhs.append(np.stack(fs))
     announce("batched 2D passes", prec, [p.n for p in probs])
     handles = [mxp.Problem(ctx, p) for p in probs]
