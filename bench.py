@@ -124,6 +124,18 @@ def measure_roofline(mxp, torch, P, prob, o, reps, prec):
         kernel = f"k_cheb2d<{R},{K},{tiles['NX']}> (fused Clenshaw pass, Ly={tiles['Ly']})"
         key = f"cheb2d_{tag}_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}"
         extra = {"levels_per_launch": K}
+    elif mxp.mxp_get_tiles(P, prec)["K"] == 2:
+        # two-level pass k_cheb3d<R, VAR> (the 3D tuner's choice): levels in
+        # pairs, then an odd level and the final level as single sweeps.  Per
+        # point: the first pass reads x and writes two levels; every later pass
+        # reads in0, in1, x and writes two; an odd sweep and the final sweep
+        # read two levels and x and write one; each launch reads D.
+        pairs = m // 2
+        per_series = (3 * z + rd_D) + (pairs - 1) * (5 * z + rd_D) + (m % 2) * (4 * z + rd_D) + (4 * z + rd_D)
+        launches_per_series = pairs + (m % 2) + 1
+        kernel = f"k_cheb3d<{R},VAR> (two Clenshaw levels per pass; with the series' last one or two single-level sweeps)"
+        key = f"cheb3d_{tag}"
+        extra = {"levels_per_launch": 2}
     else:
         # single-level z-marching sweep k_stencil3d<R, OPS>: one level per
         # launch.  Per point: the first sweep reads x and writes b_{m-1}; the

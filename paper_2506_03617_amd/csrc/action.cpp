@@ -386,6 +386,8 @@ static void cheb_series_fused(mxp_problem* P, const Emit<R>& em, const StencilAr
 
 template <typename R>
 static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s);
+template <typename R>
+static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s);
 
 // Device buffers of one action.
 template <typename R>
@@ -427,7 +429,7 @@ static void action_on(mxp_problem* P, const ActBufs<R>& B, const TileCfg& tc, co
         pick(xin, b, &spare);
         if (fused) {
             cheb_series_fused<R>(P, em, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
-        } else if (P->g.dim == 3 && P->tiles[sizeof(R) == 4 ? 1 : 0].K == 2 && !P->g.abc_per_node()) {
+        } else if (P->g.dim == 3 && tc.K == 2 && !P->g.abc_per_node()) {
             cheb_series3d<R>(em, base, sc, coef, m, xin, out, b, post, add, steps);
         } else {
             cheb_series<R>(em, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
@@ -507,15 +509,15 @@ static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched
     for (int q = 0; q < 6; ++q) B.w[q] = W[q].as<cpx<R>>();
     B.pbuf = W[6].as<cpx<R>>();
     B.y1 = W[9].as<cpx<R>>();
-    TileCfg tc;
-    if (P->g.dim == 2) {
-        TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
-        if (slot.K == 0) {
-            if (em.rec) fail(MXP_ERR_HIP, "tiles must be tuned before a batched action");
+    TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
+    if (slot.K == 0) {
+        if (em.rec) fail(MXP_ERR_HIP, "tiles must be tuned before a batched action");
+        if (P->g.dim == 2)
             tune_tiles<R>(P, ws, sd, em.s);
-        }
-        tc = slot;
+        else
+            tune_3d<R>(P, ws, sd, em.s);
     }
+    const TileCfg tc = slot;
     action_on<R>(P, B, tc, em, sd, t, shift, fn, x, y, steps);
 }
 
@@ -705,6 +707,97 @@ void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x
 // f(i t A_s) x with f = exp or psi_1 from one Arnoldi basis, the route the
 // paper takes for its matrix functions (a Krylov method, Section 4
 
+// Chooses the 3D Clenshaw kernel of this problem and precision: times a
+// single-level sweep (a middle step: x, b_{k+1}, b_{k+2}) against a two-level
+// pass (x, in0, in1) on the problem's own buffers (HIP events on the context
+// stream) and keeps the faster per Clenshaw level: K = 2 for two-level
+// passes, K = 1 with Ly = 0 (automatic z-chunk) for sweeps.  Grids whose
+// absorbing faces carry a per-node term take sweeps (the two-level pass does
+// not carry that term).
+template <typename R>
+static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s) {
+    TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
+    TileCfg sweep;
+    sweep.K = 1;
+    sweep.NX = 1;
+    sweep.Ly = 0;
+    if (P->g.abc_per_node()) {
+        slot = sweep;
+        return;
+    }
+    const int64_t n = npts(P);
+    DevMem* W = act_buffers<R>(ws);
+    for (int q = 0; q < 5; ++q) {
+        W[q].ensure(size_t(n) * sizeof(cpx<R>));
+        launch_zero<R>(W[q].as<cpx<R>>(), n, s);
+    }
+    StencilArgs<R> st = base_args<R>(P, 0.0, sd.diag);
+    st.x = W[0].as<cpx<R>>();
+    st.b1 = W[1].as<cpx<R>>();
+    st.b2 = W[2].as<cpx<R>>();
+    st.b3 = nullptr;
+    st.g = {R(0.1), R(0)};
+    st.cx = {R(0.1), R(0)};
+    st.e2 = {R(-1), R(0)};
+    st.e3 = {R(0), R(0)};
+    st.out = W[3].as<cpx<R>>();
+    ChebPass3DArgs<R> a{};
+    a.n0 = st.n0;
+    a.n1 = st.n1;
+    a.n2 = st.n2;
+    for (int d = 0; d < 3; ++d) {
+        a.alpha[d] = st.alpha[d];
+        a.beta[d] = st.beta[d];
+        a.gamma[d] = st.gamma[d];
+    }
+    a.D = st.D;
+    a.Dconst = st.Dconst;
+    a.Dref = st.Dref;
+    a.kD = st.kD;
+    a.x = W[0].as<cpx<R>>();
+    a.in0 = W[1].as<cpx<R>>();
+    a.in1 = W[2].as<cpx<R>>();
+    a.outA = W[3].as<cpx<R>>();
+    a.outB = W[4].as<cpx<R>>();
+    for (int l = 0; l < 2; ++l) {
+        a.cx[l] = {R(0.1), R(0)};
+        a.g[l] = R(0.1);
+    }
+    cheb3d_geometry<R>(a);
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    auto time_us = [&](auto&& launch, int levels) {
+        launch();  // warm
+        const int reps = 3;
+        HIP_CHECK(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch();
+        HIP_CHECK(hipEventRecord(e1, s));
+        HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        return 1e3 * ms / (reps * levels);
+    };
+    const double us_sweep = time_us([&] { launch_stencil(st, s); }, 1);
+    const double us_pass = time_us([&] { launch_cheb3d<R>(a, s); }, 2);
+    HIP_CHECK(hipEventDestroy(e0));
+    HIP_CHECK(hipEventDestroy(e1));
+    if (P->ctx->verbose)
+        std::fprintf(stderr, "[mxp] tune 3D %s: sweep %.3f us/level, two-level pass %.3f us/level\n",
+                     sizeof(R) == 4 ? "c64" : "c128", us_sweep, us_pass);
+    if (us_pass < us_sweep) {
+        TileCfg two;
+        two.K = 2;
+        two.NX = 1;
+        two.Ly = 0;
+        two.us_per_level = us_pass;
+        slot = two;
+    } else {
+        sweep.us_per_level = us_sweep;
+        slot = sweep;
+    }
+}
+
 void reserve_action(mxp_problem* P, Workspace& ws, const Sched& sd, bool psi2, bool graphs, hipStream_t s) {
     const size_t n = size_t(npts(P));
     if (sd.prec == MXP_PREC_FP64) {
@@ -726,9 +819,13 @@ void reserve_action(mxp_problem* P, Workspace& ws, const Sched& sd, bool psi2, b
 }
 
 void ensure_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s) {
-    if (P->g.dim != 2) return;
-    if (sd.prec == MXP_PREC_FP64 && P->tiles[0].K == 0) tune_tiles<double>(P, ws, sd, s);
-    if (sd.prec == MXP_PREC_MIXED && P->tiles[1].K == 0) tune_tiles<float>(P, ws, sd, s);
+    const bool dbl = sd.prec == MXP_PREC_FP64;
+    if (P->tiles[dbl ? 0 : 1].K != 0) return;
+    if (P->g.dim == 2) {
+        if (dbl) tune_tiles<double>(P, ws, sd, s); else tune_tiles<float>(P, ws, sd, s);
+    } else {
+        if (dbl) tune_3d<double>(P, ws, sd, s); else tune_3d<float>(P, ws, sd, s);
+    }
 }
 
 void apply_A(mxp_problem* P, hipStream_t s, double shift, mxp_dtype dtype, const void* x, void* y) {

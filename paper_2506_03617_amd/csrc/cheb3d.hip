@@ -23,6 +23,7 @@
 #include <utility>
 
 #include "cheb3d.h"
+#include "devmem.h"
 #include "kernels.h"
 #include "mxp_internal.h"
 
@@ -267,16 +268,24 @@ __global__ __launch_bounds__(NW * 64) void k_cheb3d(ChebPass3DArgs<R> a) {
     cheb3d_body<R, VAR>(a, blockIdx.x, ring);
 }
 
+// Batched form over grids of different sizes: a persistent grid of resident
+// workgroups strides over the concatenated tile ranges of the jobs (job of
+// index w from the lookup table, one entry per 64 indices, read through the
+// scalar cache).  Every wavefront of a workgroup works on the same tile, so
+// the per-plane barriers stay uniform; one more barrier after each tile keeps
+// the next tile's first ring writes behind the last reads of this one.
 template <typename R, int VAR>
-__global__ __launch_bounds__(NW * 64) void k_cheb3d_batch(const Cheb3DJob<R>* jobs, const uint32_t* lut) {
+__global__ __launch_bounds__(NW * 64) void k_cheb3d_batch(const Cheb3DJob<R>* jobs, const uint32_t* lut, int total) {
     __shared__ cpx<R> ring[3][NW][64];
-    const int b = blockIdx.x;
     const __attribute__((address_space(4))) uint32_t* lq = (const __attribute__((address_space(4))) uint32_t*)(lut);
-    const int q = lq[b >> 6];
-    const Cheb3DJob<R> job = sload_words(jobs + q);
-    const int64_t local = int64_t(b) - job.block0;
-    if (local >= job.blocks) return;  // the whole workgroup leaves together
-    cheb3d_body<R, VAR>(job.a, int(local), ring);
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const uint32_t q = lq[b >> 6];
+        const Cheb3DJob<R> job = sload_words(jobs + q);
+        const int local = b - int(job.block0);
+        if (local >= int(job.blocks)) continue;  // uniform: the whole workgroup skips
+        cheb3d_body<R, VAR>(job.a, local, ring);
+        __syncthreads();
+    }
 }
 
 template <typename R, int V>
@@ -285,7 +294,21 @@ void launch_one(const ChebPass3DArgs<R>& a, unsigned nb, hipStream_t s) {
 }
 template <typename R, int V>
 void launch_one_batch(const Cheb3DJob<R>* jobs, const uint32_t* lut, unsigned nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_cheb3d_batch<R, V>), dim3(nb), dim3(NW * 64), 0, s, jobs, lut);
+    // resident workgroups: occupancy (asked once per instantiation) times the
+    // compute units, at most the total
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int n = 0;
+        HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(k_cheb3d_batch<R, V>), NW * 64, 0));
+        per_cu = n > 0 ? n : 1;
+    }
+    int dev = 0, cus = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t g = int64_t(per_cu) * (cus > 0 ? cus : 1);
+    if (g > int64_t(nb)) g = nb;
+    hipLaunchKernelGGL((k_cheb3d_batch<R, V>), dim3(unsigned(g)), dim3(NW * 64), 0, s, jobs, lut, int(nb));
 }
 template <typename R, int... V>
 void launch_var(const ChebPass3DArgs<R>& a, unsigned nb, int var, hipStream_t s, std::integer_sequence<int, V...>) {

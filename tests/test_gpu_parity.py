@@ -297,6 +297,36 @@ def test_two_level_3d_passes(ctx, name, prec):
     assert rel(to_host(yd), matfun.phi1_action(As, t, to_host(xd))) <= tol
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_3d_kernel_choice_is_tuned_and_matches_the_oracle(ctx, prec):
+    # the first action on a 3D problem times a sweep against a two-level pass
+    # and keeps the faster per level (K = 1 with an automatic z-chunk, or
+    # K = 2); the chosen kernel's action matches the oracle, and a grid with
+    # per-node absorbing faces always takes sweeps
+    prob = make("3d-inh")
+    announce("3d kernel choice", prec)
+    P = mxp.Problem(ctx, prob)
+    assert mxp.mxp_get_tiles(P, prec)["K"] == 0
+    tdt = torch.complex128 if prec == 0 else torch.complex64
+    xd = to_dev(wl.random_vector(prob.npts, 5), tdt)
+    yd = torch.empty_like(xd)
+    t, s = prob.default_t(), prob.default_shift()
+    mxp.mxp_apply_exp(P, t, s, xd, yd)
+    tiles = mxp.mxp_get_tiles(P, prec)
+    assert tiles["K"] in (1, 2) and tiles["us_per_level"] > 0
+    assert tiles["K"] == 2 or tiles["Ly"] == 0
+    tol = 1e-11 if prec == 0 else 1e-5
+    assert rel(to_host(yd), matfun.exp_action(op.helmholtz(prob, s), t, to_host(xd))) <= tol
+    P.close()
+    pa = make_abc("3d-ragged")
+    Pa = mxp.Problem(ctx, pa)
+    xa = to_dev(wl.random_vector(pa.npts, 6), tdt)
+    ya = torch.empty_like(xa)
+    mxp.mxp_apply_exp(Pa, pa.default_t(), pa.default_shift(), xa, ya)
+    assert mxp.mxp_get_tiles(Pa, prec)["K"] == 1
+    Pa.close()
+
+
 @pytest.mark.parametrize("name", ["2d-inh", "3d-inh"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_graph_replayed_actions_match_direct_launches(ctx, name, prec):
