@@ -236,7 +236,7 @@ static void cheb_series(const Emit<R>& em, const StencilArgs<R>& base, const mxp
 template <typename R>
 static void cheb_series3d(const Emit<R>& em, const StencilArgs<R>& base, const mxp_schedule& sc, const double* coef,
                           int m, const cpx<R>* x, cpx<R>* out, cpx<R>* const bufs[4], cd post, const cpx<R>* add,
-                          int64_t* steps) {
+                          int64_t* steps, int zc) {
     const double hw = sc.half_width;
     ChebPass3DArgs<R> a{};
     a.n0 = base.n0;
@@ -252,7 +252,7 @@ static void cheb_series3d(const Emit<R>& em, const StencilArgs<R>& base, const m
     a.Dref = base.Dref;
     a.kD = base.kD;
     a.x = x;
-    cheb3d_geometry<R>(a);
+    cheb3d_geometry<R>(a, zc);
     const cpx<R>* prevA = nullptr;  // L_{q-2}
     const cpx<R>* prevB = nullptr;  // L_{q-1}
     int q = 0, pair = 0;
@@ -430,7 +430,7 @@ static void action_on(mxp_problem* P, const ActBufs<R>& B, const TileCfg& tc, co
         if (fused) {
             cheb_series_fused<R>(P, em, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
         } else if (P->g.dim == 3 && tc.K == 2 && !P->g.abc_per_node()) {
-            cheb_series3d<R>(em, base, sc, coef, m, xin, out, b, post, add, steps);
+            cheb_series3d<R>(em, base, sc, coef, m, xin, out, b, post, add, steps, tc.Ly);
         } else {
             cheb_series<R>(em, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
         }
@@ -711,7 +711,8 @@ void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x
 // single-level sweep (a middle step: x, b_{k+1}, b_{k+2}) against a two-level
 // pass (x, in0, in1) on the problem's own buffers (HIP events on the context
 // stream) and keeps the faster per Clenshaw level: K = 2 for two-level
-// passes, K = 1 with Ly = 0 (automatic z-chunk) for sweeps.  Grids whose
+// passes (Ly: the best of 16-, 32- and 64-plane z-chunks), K = 1 with Ly = 0
+// (automatic z-chunk) for sweeps.  Grids whose
 // absorbing faces carry a per-node term take sweeps (the two-level pass does
 // not carry that term).
 template <typename R>
@@ -763,7 +764,6 @@ static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t 
         a.cx[l] = {R(0.1), R(0)};
         a.g[l] = R(0.1);
     }
-    cheb3d_geometry<R>(a);
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -779,7 +779,21 @@ static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t 
         return 1e3 * ms / (reps * levels);
     };
     const double us_sweep = time_us([&] { launch_stencil(st, s); }, 1);
-    const double us_pass = time_us([&] { launch_cheb3d<R>(a, s); }, 2);
+    // the two-level pass with z-chunks of 16, 32 and 64 planes (no longer than the grid)
+    double us_pass = 1e300;
+    int best_zc = 0;
+    for (int zc : {16, 32, 64}) {
+        if (zc > 16 && zc / 2 >= P->g.n[2]) continue;
+        cheb3d_geometry<R>(a, zc);
+        const double us = time_us([&] { launch_cheb3d<R>(a, s); }, 2);
+        if (P->ctx->verbose)
+            std::fprintf(stderr, "[mxp] tune 3D %s: two-level pass, %d-plane chunks: %.3f us/level\n",
+                         sizeof(R) == 4 ? "c64" : "c128", zc, us);
+        if (us < us_pass) {
+            us_pass = us;
+            best_zc = zc;
+        }
+    }
     HIP_CHECK(hipEventDestroy(e0));
     HIP_CHECK(hipEventDestroy(e1));
     if (P->ctx->verbose)
@@ -789,7 +803,7 @@ static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t 
         TileCfg two;
         two.K = 2;
         two.NX = 1;
-        two.Ly = 0;
+        two.Ly = best_zc;
         two.us_per_level = us_pass;
         slot = two;
     } else {

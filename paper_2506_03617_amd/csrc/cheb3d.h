@@ -32,7 +32,7 @@ struct ChebPass3DArgs {
     int tiles_x, tiles_y, zchunks, zc;
 };
 template <typename R>
-void cheb3d_geometry(ChebPass3DArgs<R>& a);
+void cheb3d_geometry(ChebPass3DArgs<R>& a, int zc);  // zc: planes per z-chunk, 0 for 32
 template <typename R>
 int cheb3d_variant(const ChebPass3DArgs<R>& a);  // 1: D present, 2: in0, 4: in1
 template <typename R>

@@ -34,7 +34,7 @@ namespace {
 constexpr int TY = 8;           // output rows per workgroup
 constexpr int NW = TY + 2;      // wavefronts: one per row, plus a halo row each side
 constexpr int TXO = 62;         // output columns per 64-lane wavefront
-constexpr int kZChunk = 16;
+constexpr int kZChunk = 32;  // default z-chunk (planes)
 
 template <typename R>
 __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
@@ -328,10 +328,10 @@ inline void check_launch(const char* what) {
 }  // namespace
 
 template <typename R>
-void cheb3d_geometry(ChebPass3DArgs<R>& a) {
+void cheb3d_geometry(ChebPass3DArgs<R>& a, int zc) {
     a.tiles_x = int((a.n0 + TXO - 1) / TXO);
     a.tiles_y = int((a.n1 + TY - 1) / TY);
-    a.zc = kZChunk;
+    a.zc = zc > 0 ? zc : kZChunk;
     a.zchunks = int((a.n2 + a.zc - 1) / a.zc);
 }
 
@@ -359,8 +359,8 @@ void launch_cheb3d_batch(const Cheb3DJob<R>* jobs, const uint32_t* lut, int64_t 
     check_launch("batched 3D Clenshaw pass");
 }
 
-template void cheb3d_geometry<float>(ChebPass3DArgs<float>&);
-template void cheb3d_geometry<double>(ChebPass3DArgs<double>&);
+template void cheb3d_geometry<float>(ChebPass3DArgs<float>&, int);
+template void cheb3d_geometry<double>(ChebPass3DArgs<double>&, int);
 template int cheb3d_variant<float>(const ChebPass3DArgs<float>&);
 template int cheb3d_variant<double>(const ChebPass3DArgs<double>&);
 template void launch_cheb3d<float>(const ChebPass3DArgs<float>&, hipStream_t);
