@@ -373,8 +373,9 @@ mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, mxp_
  * (Ly = 0: chosen from the grid, as the autotuner reports it); NX is unused
  * there.  By default the first action times one sweep
  * against two-level passes (16-, 32- and 64-plane chunks) on the problem's
- * buffers and keeps the fastest per level (at 256^3 the two-level pass in
- * complex double, the sweep in complex float); grids with per-node absorbing-face terms always take
+ * buffers and keeps the fastest per level, the two-level pass only when it
+ * wins by more than 3% (at 256^3 the two-level pass in complex double, the
+ * sweep in complex float); grids with per-node absorbing-face terms always take
  * sweeps.  Errors: INVALID_ARG; UNSUPPORTED for K = 2 on such grids. */
 mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, int32_t NX, int32_t Ly);
 mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32_t* K, int32_t* NX,

@@ -10,8 +10,8 @@ namespace mxp {
 // S the stencil of StencilArgs (unscaled tables, the centre folded into
 // gamma, kD (D - Dref) per node); in0 / in1 = nullptr read as zero.  Writes
 // L_0 to outA and L_1 to outB; outputs must not alias any input.  Geometry
-// (cheb3d_geometry): tiles of 62 x 8 output columns x rows, chunks of zc
-// planes; a workgroup of ten wavefronts also recomputes L_0 on a one-node
+// (cheb3d_geometry): tiles of 62 x 14 output columns x rows, chunks of zc
+// planes; a workgroup of sixteen wavefronts also recomputes L_0 on a one-node
 // halo in x and y and one plane in z on each side.
 template <typename R>
 struct ChebPass3DArgs {

@@ -2,16 +2,16 @@
 //
 //   L_0 = cx0 x + g0 S(in1) - in0,   L_1 = cx1 x + g1 S(L_0) - in1
 //
-// A workgroup of ten wavefronts owns a tile of 62 x 8 output nodes (x, y)
+// A workgroup of sixteen wavefronts owns a tile of 62 x 14 output nodes (x, y)
 // and marches along z over a chunk of planes.  Wavefront w holds grid row
-// y0 - 1 + w (rows 0 and 9 are halo rows) and its 64 lanes hold columns
+// y0 - 1 + w (rows 0 and 15 are halo rows) and its 64 lanes hold columns
 // x0 - 1 .. x0 + 62 (lanes 0 and 63 are halo columns).  At step k:
 //  * every wavefront computes L_0 on plane k for its row (in1's z-window of
 //    three planes is carried in registers; x-neighbours come from the
 //    adjacent lanes through DPP, the two edge lanes load theirs);
 //  * L_0 is written to a three-plane LDS ring and the workgroup synchronises
 //    once;
-//  * wavefronts 1..8 compute L_1 on plane k - 1: x-neighbours by DPP,
+//  * wavefronts 1..14 compute L_1 on plane k - 1: x-neighbours by DPP,
 //    y-neighbours from the ring, z-neighbours from the L_0 planes the
 //    wavefront carries; lanes 1..62 store both levels.
 // Ghost nodes (outside the grid) hold zero, as in the single-level sweep.
@@ -31,7 +31,7 @@ namespace mxp {
 
 namespace {
 
-constexpr int TY = 8;           // output rows per workgroup
+constexpr int TY = 14;          // output rows per workgroup (16 wavefronts: 4 per SIMD at one workgroup per CU)
 constexpr int NW = TY + 2;      // wavefronts: one per row, plus a halo row each side
 constexpr int TXO = 62;         // output columns per 64-lane wavefront
 constexpr int kZChunk = 32;  // default z-chunk (planes)
@@ -227,7 +227,7 @@ __device__ __forceinline__ void cheb3d_body(const ChebPass3DArgs<R>& a, int tile
         // plane stay in flight across it
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt and expcnt left free
         __builtin_amdgcn_s_barrier();
-        // ---- L_1 on plane k - 1 (rows 1..8 of the workgroup)
+        // ---- L_1 on plane k - 1 (rows 1..TY of the workgroup)
         const int64_t kb = k - 1;
         if (kb >= z0 && kb < z1 && w >= 1 && w <= TY) {
             const int sb = int(((kb % 3) + 3) % 3);

@@ -278,7 +278,7 @@ def test_autotuned_tiles_are_recorded(ctx):
 @pytest.mark.parametrize("name", ["3d-homog", "3d-inh", "3d-ragged"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_two_level_3d_passes(ctx, name, prec):
-    # the two-level 3D pass (tiles K = 2): chunks of 16 planes, 62 x 8 tiles
+    # the two-level 3D pass (tiles K = 2): one-plane chunks, 62 x 14 tiles
     # with ragged edges, odd and even series degrees through exp and psi_1
     prob = make(name)
     announce("3d two-level passes", name, prec)
