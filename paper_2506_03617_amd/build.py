@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmatexpre.so")
 
 SOURCES = ["kernels.hip", "cheb2d.hip", "cheb3d.hip", "cnn.hip", "schedule.cpp", "action.cpp", "krylov.cpp",
-           "batch.cpp", "api.cpp", "network.cpp", "checkpoint.cpp",
+           "batch.cpp", "api.cpp", "network.cpp", "checkpoint.cpp", "tunecache.cpp",
            "noalloc.cpp"]
 
 HIP_FLAGS = [
@@ -58,7 +58,10 @@ def build(verbose: bool = False) -> str:
         for fut in [pool.submit(subprocess.run, cmd, check=True) for cmd in cmds]:
             fut.result()
     tmp = LIB + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    # roctx ranges around the solver's phases (rocprofv3 --marker-trace)
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-L", os.path.join(rocm, "lib"),
+           "-lrocprofiler-sdk-roctx", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "engine.h"
@@ -384,6 +385,62 @@ static void cheb_series_fused(mxp_problem* P, const Emit<R>& em, const StencilAr
     *steps += m;
 }
 
+// The on-disk tile cache named by MXP_AUTOTUNE_CACHE (empty: none), and the
+// key of this problem's choice in it: library version, device architecture,
+// grid shape, precision, medium (per-node D or constant) and absorber.
+static const char* tile_cache_path() {
+    const char* p = std::getenv("MXP_AUTOTUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+static std::string tile_cache_key(const mxp_problem* P, bool dbl) {
+    hipDeviceProp_t prop;
+    HIP_CHECK(hipGetDeviceProperties(&prop, P->ctx->device));
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s|%s|%dd %lldx%lldx%lld|%s|%s|absorber %d%s", mxp_version(), prop.gcnArchName,
+                  P->g.dim, (long long)P->g.n[0], (long long)P->g.n[1], (long long)P->g.n[2], dbl ? "c128" : "c64",
+                  P->D64.p ? "D" : "c", int(P->g.absorber), P->g.abc_per_node() ? " per-node" : "");
+    std::string k(buf);
+    for (char& c : k)
+        if (c == '"' || c == '\\') c = '_';
+    return k;
+}
+// A cached choice this build can run on this problem.
+static bool tiles_valid(const mxp_problem* P, bool dbl, const int v[3]) {
+    const int K = v[0], NX = v[1], Ly = v[2];
+    if (P->g.dim == 2)
+        return K >= 1 && K <= kMaxFused && (NX == 1 || NX == 2) && Ly >= 1 && NX * 64 - 2 * K > 0 &&
+               !(dbl && NX == 2 && K > 3);
+    return Ly >= 0 && NX == 1 && (K == 1 || (K == 2 && !P->g.abc_per_node()));
+}
+template <typename R>
+static bool tiles_from_cache(mxp_problem* P) {
+    const char* path = tile_cache_path();
+    if (!path) return false;
+    int v[3];
+    double us = 0.0;
+    const bool dbl = sizeof(R) == 8;
+    if (!tune_cache_get(path, tile_cache_key(P, dbl), v, &us) || !tiles_valid(P, dbl, v)) return false;
+    TileCfg t;
+    t.K = v[0];
+    t.NX = v[1];
+    t.Ly = v[2];
+    t.us_per_level = us;
+    P->tiles[dbl ? 0 : 1] = t;
+    if (P->ctx->verbose)
+        std::fprintf(stderr, "[mxp] tiles from %s: K=%d NX=%d Ly=%d (%.3f us/level)\n", path, t.K, t.NX, t.Ly, us);
+    return true;
+}
+template <typename R>
+static void tiles_to_cache(const mxp_problem* P) {
+    const char* path = tile_cache_path();
+    if (!path) return;
+    const bool dbl = sizeof(R) == 8;
+    const TileCfg& t = P->tiles[dbl ? 0 : 1];
+    const int v[3] = {t.K, t.NX, t.Ly};
+    if (!tune_cache_put(path, tile_cache_key(P, dbl), v, t.us_per_level) && P->ctx->verbose)
+        std::fprintf(stderr, "[mxp] tile cache %s not updated (unreadable or not a tile cache)\n", path);
+}
+
 template <typename R>
 static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s);
 template <typename R>
@@ -526,6 +583,8 @@ static void action(mxp_problem* P, Workspace& ws, const Emit<R>& em, const Sched
 // Clenshaw level.
 template <typename R>
 static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s) {
+    Range range("tile tuning 2D");
+    if (tiles_from_cache<R>(P)) return;
     const int64_t n = npts(P);
     DevMem* W = act_buffers<R>(ws);
     for (int q = 0; q < 7; ++q) {
@@ -607,6 +666,7 @@ static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream
     (void)hipEventDestroy(e1);
     if (best.K == 0) fail(MXP_ERR_HIP, "tile autotuning measured no candidate");
     P->tiles[sizeof(R) == 4 ? 1 : 0] = best;
+    tiles_to_cache<R>(P);
 }
 
 // y = exp, psi_1 or psi_2 action (fn) on complex-double vectors, in the requested
@@ -616,6 +676,7 @@ static void tune_tiles(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream
 void action64_on(mxp_problem* P, Workspace& ws, hipStream_t s, const Sched& sc, double t, double shift,
                         int fn, mxp_precision prec, const cpx<double>* x, cpx<double>* y, int64_t* steps,
                         std::vector<StepRec<double>>* rec64, std::vector<StepRec<float>>* rec32) {
+    Range range(fn == ACT_EXP ? "exp action" : (fn == ACT_PSI1 ? "psi1 action" : "psi2 action"));
     if (prec == MXP_PREC_FP64) {
         action<double>(P, ws, Emit<double>{s, rec64}, sc, t, shift, fn, x, y, steps);
         return;
@@ -717,6 +778,8 @@ void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x
 // not carry that term).
 template <typename R>
 static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t s) {
+    Range range("tile tuning 3D");
+    if (tiles_from_cache<R>(P)) return;
     TileCfg& slot = P->tiles[sizeof(R) == 4 ? 1 : 0];
     TileCfg sweep;
     sweep.K = 1;
@@ -812,6 +875,7 @@ static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t 
         sweep.us_per_level = us_sweep;
         slot = sweep;
     }
+    tiles_to_cache<R>(P);
 }
 
 void reserve_action(mxp_problem* P, Workspace& ws, const Sched& sd, bool psi2, bool graphs, hipStream_t s) {

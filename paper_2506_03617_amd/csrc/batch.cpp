@@ -174,6 +174,7 @@ class Batcher {
     }
 
     void execute(std::vector<ActionReq*>& reqs) {
+        Range range("batched lockstep action");
         HIP_CHECK(hipSetDevice(device_));
         const size_t nq = reqs.size();
         // inputs are ready once each solve's stream reaches this point
@@ -348,6 +349,7 @@ mxp_status mxp_solve_batch(mxp_context* ctx, int32_t nprob, mxp_problem* const* 
                            const void* const* f, void* const* u, const mxp_solve_opts* opts, int32_t max_resident,
                            mxp_solve_stats* stats) {
     return guard([&]() -> mxp_status {
+        Range range("mxp solve batch");
         if (!ctx || nprob < 1 || !problems || !nrhs || !f || !u || !opts)
             fail(MXP_ERR_INVALID_ARG, "batch: context, problem, rhs and option arrays must be given");
         if (max_resident < 0) fail(MXP_ERR_INVALID_ARG, "max_resident must be >= 0");

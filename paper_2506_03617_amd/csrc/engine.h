@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <complex>
 #include <map>
@@ -307,6 +308,15 @@ inline mxp_status guard(F&& fn) {
         return MXP_ERR_HIP;
     }
 }
+
+// A roctx range for the lifetime of a scope (shown by rocprofv3 --marker-trace;
+// per host thread, so the ranges of a batched solve's threads nest on their own).
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 inline void use_device(const mxp_context* ctx) { HIP_CHECK(hipSetDevice(ctx->device)); }
 

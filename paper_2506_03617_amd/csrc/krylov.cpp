@@ -148,6 +148,7 @@ constexpr double kNetTrySteps = 48.0;
 
 // z = learned network applied to v (unit norm), complex double.
 static void learned_apply(Run& run, const cpx<double>* v, double vnorm, cpx<double>* z) {
+    Range range("network inference");
     mxp_problem* P = run.P;
     const int64_t n = npts(P);
     const ConvShape sh{1, int(P->g.n[2]), int(P->g.n[1]), int(P->g.n[0])};
@@ -160,6 +161,7 @@ static void learned_apply(Run& run, const cpx<double>* v, double vnorm, cpx<doub
 // Algorithm 1.  r, w: complex double device vectors.
 int precond(Run& run, const mxp_solve_opts& o, const cpx<double>* r, cpx<double>* w, Counters& cnt,
             mxp_precision ap) {
+    Range range("preconditioner apply");
     mxp_problem* P = run.P;
     run.graphs = o.use_graphs != 0 && !run.batch;
     Workspace& WS = *run.W;
@@ -391,6 +393,7 @@ static int arnoldi_action(Run& run, bool psi, double t, double shift, double tol
 // built over all attempts; *ok is false if q = 64 did not suffice.
 int krylov_action(Run& run, bool psi, double t, double shift, double tol, int max_dim,
                          const cpx<double>* x, cpx<double>* y, bool* ok) {
+    Range range("arnoldi action");
     const int64_t n = npts(run.P);
     hipStream_t s = run.s;
     int total = 0;
@@ -485,6 +488,7 @@ void reserve_solve(Run& run, const mxp_solve_opts& o) {
 
 mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<double>* u,
                         mxp_solve_stats* st) {
+    Range range("mxp solve");
     const auto t0 = std::chrono::steady_clock::now();
     mxp_problem* P = run.P;
     Workspace& WS = *run.W;

@@ -123,4 +123,14 @@ void write_checkpoint(const char* path, int32_t layers, const int32_t* channels,
 void read_checkpoint(const char* path, int32_t layers, const int32_t* channels, int64_t nparam, int64_t* adam_t,
                      std::vector<float>* buf);
 
+// On-disk cache of autotuned tiles (host only): the JSON file at `path` maps
+// a configuration key to (K, NX, Ly) and the measured microseconds per level.
+// get: false if the path is empty, the file is missing or does not parse, or
+// the key is absent.  put: adds or replaces the key and rewrites the file
+// through a temporary and a rename; false (file untouched) if the path is
+// empty, the file exists but does not parse, or writing fails.  Calls within
+// a process are serialised.
+bool tune_cache_get(const char* path, const std::string& key, int v[3], double* us);
+bool tune_cache_put(const char* path, const std::string& key, const int v[3], double us);
+
 }  // namespace mxp

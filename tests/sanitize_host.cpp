@@ -1,8 +1,9 @@
 // Host code of the library run under AddressSanitizer and UndefinedBehaviour
 // Sanitizer (built by tests/test_host_sanitizers.py with g++, no GPU): the grid
 // checks, the field-of-values box and schedule design for every absorber in
-// both precisions, the psi_2 series, the dense exponential, and the checkpoint
-// reader on valid, truncated, corrupted and non-finite files.
+// both precisions, the psi_2 series, the dense exponential, the checkpoint
+// reader on valid, truncated, corrupted and non-finite files, and the
+// autotuner cache on round trips and on malformed files.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -185,6 +186,62 @@ int main(int argc, char** argv) {
         bad[9] = std::nanf("");
         write_checkpoint((dir + "/nan.bin").c_str(), layers, ch, np, 7, bad);
         expect_error(dir + "/nan.bin", layers, ch, np, MXP_ERR_NONFINITE, "NaN parameter");
+    }
+    // the autotuner's on-disk cache
+    {
+        const std::string path = dir + "/tiles.json";
+        std::remove(path.c_str());
+        int v[3] = {0, 0, 0};
+        double us = 0.0;
+        CHECK(!tune_cache_get(path.c_str(), "a", v, &us), "missing cache file reads as empty");
+        CHECK(!tune_cache_get(nullptr, "a", v, &us) && !tune_cache_get("", "a", v, &us), "no cache path");
+        const int a[3] = {4, 1, 25}, b[3] = {2, 1, 32}, c[3] = {6, 2, 8};
+        CHECK(tune_cache_put(path.c_str(), "v|gfx950|2d 2048x2048x1|c64|D|absorber 0", a, 11.7), "first put");
+        CHECK(tune_cache_put(path.c_str(), "v|gfx950|3d 256x256x256|c128|c|absorber 0", b, 171.8), "second put");
+        CHECK(tune_cache_put(path.c_str(), "v|gfx950|2d 2048x2048x1|c64|D|absorber 0", c, 9.5), "replace");
+        CHECK(!tune_cache_put(path.c_str(), "bad\"key", a, 1.0), "key with a quote refused");
+        CHECK(tune_cache_get(path.c_str(), "v|gfx950|3d 256x256x256|c128|c|absorber 0", v, &us) && v[0] == 2 &&
+                  v[1] == 1 && v[2] == 32 && std::fabs(us - 171.8) < 1e-9,
+              "round trip");
+        CHECK(tune_cache_get(path.c_str(), "v|gfx950|2d 2048x2048x1|c64|D|absorber 0", v, &us) && v[0] == 6 &&
+                  v[1] == 2 && v[2] == 8,
+              "replaced entry");
+        CHECK(!tune_cache_get(path.c_str(), "absent", v, &us), "absent key");
+        // malformed or foreign files: read as empty and never overwritten
+        const char* bad[] = {"", "{", "[1, 2]", "{\"k\": [1, 2, 3]}", "{\"k\": [1, 2, 3, 4, 5]}",
+                             "{\"k\": [1.5, 2, 3, 4]}", "{\"k\": [1, 2, 3, -4]}", "{\"k\": [1, 2, 3, 4]} x",
+                             "{\"k\" [1, 2, 3, 4]}", "{\"k\": [1, 2, 3, 4],}", "{\"k\": [1, 2, 3, nan]}",
+                             "{\"k\": [1e300, 2, 3, 4]}", "{\"k\\\": [1, 2, 3, 4]}"};
+        for (const char* text : bad) {
+            const std::string bp = dir + "/bad.json";
+            FILE* f = std::fopen(bp.c_str(), "wb");
+            if (f) {
+                if (*text) std::fwrite(text, 1, std::strlen(text), f);
+                std::fclose(f);
+            }
+            CHECK(!tune_cache_get(bp.c_str(), "k", v, &us), "malformed cache reads as empty");
+            CHECK(!tune_cache_put(bp.c_str(), "k", a, 1.0), "malformed cache not overwritten");
+            FILE* g = std::fopen(bp.c_str(), "rb");
+            std::string back;
+            if (g) {
+                char chunk[256];
+                size_t k;
+                while ((k = std::fread(chunk, 1, sizeof(chunk), g)) > 0) back.append(chunk, k);
+                std::fclose(g);
+            }
+            CHECK(back == text, "malformed cache left as it was");
+        }
+        {
+            const std::string ep = dir + "/empty_obj.json";
+            FILE* f = std::fopen(ep.c_str(), "wb");
+            if (f) {
+                std::fputs(" { } \n", f);
+                std::fclose(f);
+            }
+            CHECK(!tune_cache_get(ep.c_str(), "k", v, &us), "empty object has no key");
+            CHECK(tune_cache_put(ep.c_str(), "k", a, 2.5) && tune_cache_get(ep.c_str(), "k", v, &us) && v[2] == 25,
+                  "empty object takes a first entry");
+        }
     }
     if (failures == 0) std::printf("all host checks passed\n");
     return failures == 0 ? 0 : 1;

@@ -327,3 +327,19 @@ def test_noalloc_action_checks_its_arguments_before_device_work():
     # the array's name appears only in its definition and the address lookup
     uses = [l for l in code.splitlines() if re.search(r"\bscratch\b", l)]
     assert len(uses) == 2, uses
+
+
+def test_library_marks_its_phases_with_roctx_ranges():
+    """The solver's phases are roctx ranges (rocprofv3 --marker-trace): the
+    library imports the range calls, and every source that opens one pairs
+    it with a scope (the Range type pops on scope exit)."""
+    import os
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--undefined-only", mxp.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+    csrc = os.path.join(os.path.dirname(mxp.__file__), "csrc")
+    for name in os.listdir(csrc):
+        if name.endswith((".cpp", ".hip")):
+            src = open(os.path.join(csrc, name)).read()
+            assert "roctxRangePushA(" not in src and "roctxRangePop(" not in src, name

@@ -1,5 +1,5 @@
 """The library's host code (schedule designer, grid checks, dense exponential,
-checkpoint reader) built with g++ under AddressSanitizer and UndefinedBehaviour
+checkpoint reader, autotuner cache) built with g++ under AddressSanitizer and UndefinedBehaviour
 Sanitizer and run on valid and invalid inputs (no GPU)."""
 import os
 import shutil
@@ -18,7 +18,8 @@ def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-I", os.path.join(ROOT, "include"),
            os.path.join(ROOT, "tests", "sanitize_host.cpp"),
-           os.path.join(CSRC, "schedule.cpp"), os.path.join(CSRC, "checkpoint.cpp"), "-o", exe]
+           os.path.join(CSRC, "schedule.cpp"), os.path.join(CSRC, "checkpoint.cpp"),
+           os.path.join(CSRC, "tunecache.cpp"), "-o", exe]
     subprocess.run(cmd, check=True, timeout=300)
     # a library preloaded into every process may come before the sanitizer runtime
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
