@@ -435,3 +435,40 @@ def test_learned_gain_on_a_held_out_source(ctx):
     mxp.mxp_problem_set_learned(P, None, 1.0)
     net.close()
     P.close()
+
+
+def test_failure_paths_are_reported_and_recovered(ctx):
+    """Forced failures: a network with zero weights proposes z = 0, every try
+    is rejected and the solve is MatExPre's (the FP64 true residual judges);
+    fprtol = 1 makes Algorithm 1 return w = 0 before its first iteration, and
+    FGMRES reports the singular direction as MXP_ERR_BREAKDOWN instead of
+    returning a wrong iterate."""
+    prob = wl.small_problem((28, 26, 24), layer=4, ppw=10, inhomogeneous=True, seed=11, name="fail")
+    announce("failure paths")
+    P = mxp.Problem(ctx, prob)
+    f = to_dev(wl.delta_source(prob, (17, 13, 14)).ravel())
+    o = P.default_opts()
+    o.precision = mxp.MXP_PREC_MIXED
+    u = torch.zeros_like(f)
+    plain = mxp.mxp_solve(P, o, f, u)
+    u_plain = u.clone()
+    net = mxp.Network(ctx, 5)
+    net.set_params(np.zeros(mxp.Network.num_params(), dtype=np.float32))
+    mxp.mxp_problem_set_learned(P, net, 1.0)
+    o.use_learned = 1
+    o.stall_ratio = 0.0
+    u.zero_()
+    st = mxp.mxp_solve(P, o, f, u)
+    assert st["status"] == mxp.MXP_OK and st["true_relres"] <= o.rtol
+    assert st["learned_its"] == 0 and st["fallbacks"] >= 1
+    assert st["outer_its"] == plain["outer_its"] and torch.equal(u, u_plain)
+    mxp.mxp_problem_set_learned(P, None, 1.0)
+    net.close()
+    ob = P.default_opts()
+    ob.fprtol = 1.0
+    u.zero_()
+    with pytest.raises(mxp.MxpError) as ei:
+        mxp.mxp_solve(P, ob, f, u)
+    assert ei.value.status == mxp.MXP_ERR_BREAKDOWN
+    assert torch.isfinite(u).all()
+    P.close()
