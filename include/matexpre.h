@@ -512,7 +512,9 @@ mxp_status mxp_collect_pairs(mxp_problem* prob, const mxp_solve_opts* opts, cons
  * pass).  A kept direction takes a slot of the restart cycle, so it must
  * reduce the residual as much as the MatExPre iteration it displaces, and at
  * least as cost-effectively; the rule counts work, not time, so repeated
- * solves make the same choices.  Otherwise z_j = M(v_j) from MatExPre (a
+ * solves make the same choices.  A proposal whose new Hessenberg column is
+ * zero or dependent on the earlier ones (rotated diagonal below 1e-8 of the
+ * column's norm) is rejected whatever its residual estimate.  Otherwise z_j = M(v_j) from MatExPre (a
  * fallback); after two fallbacks in a row MatExPre alone is used until the
  * next restart cycle.  The first outer iteration always uses MatExPre.
  *

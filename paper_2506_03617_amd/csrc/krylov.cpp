@@ -559,13 +559,19 @@ mxp_status solve(Run& run, const mxp_solve_opts& o, const cpx<double>* f, cpx<do
                 hn = cgs2(run, V, n, j + 1, vn, h);
                 Givens trial = gv;
                 res = trial.add_column(j, h, hn);
+                // a proposal whose column is zero or (nearly) dependent on the
+                // earlier ones leaves a singular factor, and its residual
+                // estimate (zero after a degenerate rotation) means nothing
+                double col = hn * hn;
+                for (int i = 0; i <= j; ++i) col += std::norm(h[i]);
+                const bool singular = !(std::abs(trial.at(j, j)) > 1e-8 * std::sqrt(col));
                 double thr = o.stall_ratio;
                 if (thr <= 0) {
                     const double per_it = m_log / m_count;                            // log reduction per iteration
                     const double per_step = m_log / std::max(double(m_steps), 1.0);  // ... per stencil step
                     thr = std::min(1.0, std::min(std::exp(per_it), std::exp(per_step * kNetTrySteps)));
                 }
-                if (std::isfinite(res) && res <= thr * prev_res) {
+                if (!singular && std::isfinite(res) && res <= thr * prev_res) {
                     gv = trial;
                     accepted = true;
                     cnt.learned++;
