@@ -35,6 +35,7 @@ KERNEL_SOURCES = {
     "cheb2d": ("cheb2d.hip", "kernels.h"),
     "stencil3d": ("kernels.hip", "kernels.h"),
     "cheb3d": ("cheb3d.hip", "cheb3d.h", "kernels.h"),
+    "cheb3d3": ("cheb3d.hip", "cheb3d.h", "kernels.h"),
 }
 
 
@@ -124,6 +125,21 @@ def measure_roofline(mxp, torch, P, prob, o, reps, prec):
         kernel = f"k_cheb2d<{R},{K},{tiles['NX']}> (fused Clenshaw pass, Ly={tiles['Ly']})"
         key = f"cheb2d_{tag}_K{K}_NX{tiles['NX']}_Ly{tiles['Ly']}"
         extra = {"levels_per_launch": K}
+    elif mxp.mxp_get_tiles(P, prec)["K"] == 3:
+        # three-level pass k_cheb3d3<R, VAR> (the 3D tuner's choice): levels in
+        # triples, then a pair or a single level for the remainder and the
+        # final level as a sweep.  Per point: the first pass reads x and writes
+        # two levels; every later pass reads in0, in1, x and writes two; a
+        # remainder pair the same; a single sweep and the final sweep read two
+        # levels and x and write one; each launch reads D.
+        trip = m // 3
+        rem = m - 3 * trip
+        per_series = ((3 * z + rd_D) + (trip - 1) * (5 * z + rd_D) + (rem == 2) * (5 * z + rd_D)
+                      + (rem == 1) * (4 * z + rd_D) + (4 * z + rd_D))
+        launches_per_series = trip + (rem == 2) + (rem == 1) + 1
+        kernel = f"k_cheb3d3<{R},VAR> (three Clenshaw levels per pass; with the series' last one or two launches)"
+        key = f"cheb3d3_{tag}"
+        extra = {"levels_per_launch": 3}
     elif mxp.mxp_get_tiles(P, prec)["K"] == 2:
         # two-level pass k_cheb3d<R, VAR> (the 3D tuner's choice): levels in
         # pairs, then an odd level and the final level as single sweeps.  Per

@@ -367,16 +367,17 @@ mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, mxp_
  * next action); mxp_get_tiles reports it (K = 0 if not tuned yet) with the
  * measured microseconds per Clenshaw level (0 if fixed by the caller).
  * precision selects the complex-double (MXP_PREC_FP64) or complex-float
- * (MXP_PREC_MIXED) kernels.  On 3D grids K = 2 selects passes of two
- * Clenshaw levels (k_cheb3d) over z-chunks of Ly planes (Ly = 0: 32) and
- * K = 1 single-level z-marching sweeps whose z segments are Ly planes
- * (Ly = 0: chosen from the grid, as the autotuner reports it); NX is unused
- * there.  By default the first action times one sweep
- * against two-level passes (16-, 32- and 64-plane chunks) on the problem's
- * buffers and keeps the fastest per level, the two-level pass only when it
- * wins by more than 3% (at 256^3 the two-level pass in complex double, the
- * sweep in complex float); grids with per-node absorbing-face terms always take
- * sweeps.  Errors: INVALID_ARG; UNSUPPORTED for K = 2 on such grids. */
+ * (MXP_PREC_MIXED) kernels.  On 3D grids K = 2 and K = 3 select passes of
+ * two (k_cheb3d) and three (k_cheb3d3) Clenshaw levels over z-chunks of Ly
+ * planes (Ly = 0: 32), and K = 1 single-level z-marching sweeps whose z
+ * segments are Ly planes (Ly = 0: chosen from the grid, as the autotuner
+ * reports it); NX is unused there.  By default the first action times one
+ * sweep against two-level (16-, 32- and 64-plane chunks) and three-level (16,
+ * 32) passes on the problem's buffers and keeps the fastest per level, a
+ * multi-level pass only when it wins by more than 3% (at 256^3 the
+ * three-level pass in complex double, the sweep in complex float); grids with
+ * per-node absorbing-face terms always take sweeps.  Errors: INVALID_ARG;
+ * UNSUPPORTED for K = 2, 3 on such grids. */
 mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, int32_t NX, int32_t Ly);
 mxp_status mxp_get_tiles(const mxp_problem* prob, mxp_precision precision, int32_t* K, int32_t* NX,
                          int32_t* Ly, double* us_per_level);

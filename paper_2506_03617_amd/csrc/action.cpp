@@ -237,7 +237,7 @@ static void cheb_series(const Emit<R>& em, const StencilArgs<R>& base, const mxp
 template <typename R>
 static void cheb_series3d(const Emit<R>& em, const StencilArgs<R>& base, const mxp_schedule& sc, const double* coef,
                           int m, const cpx<R>* x, cpx<R>* out, cpx<R>* const bufs[4], cd post, const cpx<R>* add,
-                          int64_t* steps, int zc) {
+                          int64_t* steps, int zc, int levels) {
     const double hw = sc.half_width;
     ChebPass3DArgs<R> a{};
     a.n0 = base.n0;
@@ -253,10 +253,32 @@ static void cheb_series3d(const Emit<R>& em, const StencilArgs<R>& base, const m
     a.Dref = base.Dref;
     a.kD = base.kD;
     a.x = x;
-    cheb3d_geometry<R>(a, zc);
     const cpx<R>* prevA = nullptr;  // L_{q-2}
     const cpx<R>* prevB = nullptr;  // L_{q-1}
     int q = 0, pair = 0;
+    if (levels == 3) {
+        // levels in triples: L_q, L_{q+1}, L_{q+2}, writing the last two
+        ChebPass3DArgs<R> a3 = a;
+        cheb3d3_geometry<R>(a3, zc);
+        while (q + 2 <= m - 1) {
+            a3.cx[0] = to_cpx<R>(coef_at(coef, m - q));
+            a3.g[0] = R(q == 0 ? 0.0 : 2.0 / hw);
+            a3.cx[1] = to_cpx<R>(coef_at(coef, m - q - 1));
+            a3.g[1] = R(2.0 / hw);
+            a3.cx[2] = to_cpx<R>(coef_at(coef, m - q - 2));
+            a3.g[2] = R(2.0 / hw);
+            a3.in0 = prevA;
+            a3.in1 = prevB;
+            a3.outA = bufs[2 * pair];
+            a3.outB = bufs[2 * pair + 1];
+            em.pass3d3(a3);
+            prevA = a3.outA;
+            prevB = a3.outB;
+            pair ^= 1;
+            q += 3;
+        }
+    }
+    cheb3d_geometry<R>(a, zc);
     while (q + 1 <= m - 1) {
         a.cx[0] = to_cpx<R>(coef_at(coef, m - q));
         a.g[0] = R(q == 0 ? 0.0 : 2.0 / hw);
@@ -410,7 +432,7 @@ static bool tiles_valid(const mxp_problem* P, bool dbl, const int v[3]) {
     if (P->g.dim == 2)
         return K >= 1 && K <= kMaxFused && (NX == 1 || NX == 2) && Ly >= 1 && NX * 64 - 2 * K > 0 &&
                !(dbl && NX == 2 && K > 3);
-    return Ly >= 0 && NX == 1 && (K == 1 || (K == 2 && !P->g.abc_per_node()));
+    return Ly >= 0 && NX == 1 && (K == 1 || ((K == 2 || K == 3) && !P->g.abc_per_node()));
 }
 template <typename R>
 static bool tiles_from_cache(mxp_problem* P) {
@@ -486,8 +508,8 @@ static void action_on(mxp_problem* P, const ActBufs<R>& B, const TileCfg& tc, co
         pick(xin, b, &spare);
         if (fused) {
             cheb_series_fused<R>(P, em, base, sd.diag, tc, sc, coef, m, xin, out, b, post, add, steps);
-        } else if (P->g.dim == 3 && tc.K == 2 && !P->g.abc_per_node()) {
-            cheb_series3d<R>(em, base, sc, coef, m, xin, out, b, post, add, steps, tc.Ly);
+        } else if (P->g.dim == 3 && (tc.K == 2 || tc.K == 3) && !P->g.abc_per_node()) {
+            cheb_series3d<R>(em, base, sc, coef, m, xin, out, b, post, add, steps, tc.Ly, tc.K);
         } else {
             cheb_series<R>(em, base, sc, coef, m, xin, out, b[0], b[1], post, add, steps);
         }
@@ -769,11 +791,12 @@ void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x
 // paper takes for its matrix functions (a Krylov method, Section 4
 
 // Chooses the 3D Clenshaw kernel of this problem and precision: times a
-// single-level sweep (a middle step: x, b_{k+1}, b_{k+2}) against a two-level
-// pass (x, in0, in1) on the problem's own buffers (HIP events on the context
-// stream) and keeps the faster per Clenshaw level: K = 2 for two-level
-// passes (Ly: the best of 16-, 32- and 64-plane z-chunks) when they beat the
-// sweep by more than 3%, else K = 1 with Ly = 0 (automatic z-chunk) for sweeps.  Grids whose
+// single-level sweep (a middle step: x, b_{k+1}, b_{k+2}) against two- and
+// three-level passes (x, in0, in1) on the problem's own buffers (HIP events on
+// the context stream) and keeps the fastest per Clenshaw level: K = 2 or 3
+// for the multi-level passes (Ly: the best z-chunk of 16, 32 and, for two
+// levels, 64 planes) when they beat the sweep by more than 3%, else K = 1 with
+// Ly = 0 (automatic z-chunk) for sweeps.  Grids whose
 // absorbing faces carry a per-node term take sweeps (the two-level pass does
 // not carry that term).
 template <typename R>
@@ -842,31 +865,45 @@ static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t 
         return 1e3 * ms / (reps * levels);
     };
     const double us_sweep = time_us([&] { launch_stencil(st, s); }, 1);
-    // the two-level pass with z-chunks of 16, 32 and 64 planes (no longer than the grid)
+    // two-level passes with z-chunks of 16, 32 and 64 planes and three-level
+    // passes with 16 and 32 (no longer than the grid)
     double us_pass = 1e300;
-    int best_zc = 0;
-    for (int zc : {16, 32, 64}) {
-        if (zc > 16 && zc / 2 >= P->g.n[2]) continue;
-        cheb3d_geometry<R>(a, zc);
-        const double us = time_us([&] { launch_cheb3d<R>(a, s); }, 2);
-        if (P->ctx->verbose)
-            std::fprintf(stderr, "[mxp] tune 3D %s: two-level pass, %d-plane chunks: %.3f us/level\n",
-                         sizeof(R) == 4 ? "c64" : "c128", zc, us);
-        if (us < us_pass) {
-            us_pass = us;
-            best_zc = zc;
+    int best_zc = 0, best_k = 2;
+    for (int levels : {2, 3}) {
+        for (int zc : {16, 32, 64}) {
+            if (zc > 16 && zc / 2 >= P->g.n[2]) continue;
+            if (levels == 3 && zc > 32) continue;
+            double us;
+            if (levels == 2) {
+                cheb3d_geometry<R>(a, zc);
+                us = time_us([&] { launch_cheb3d<R>(a, s); }, 2);
+            } else {
+                ChebPass3DArgs<R> a3 = a;
+                a3.cx[2] = {R(0.1), R(0)};
+                a3.g[2] = R(0.1);
+                cheb3d3_geometry<R>(a3, zc);
+                us = time_us([&] { launch_cheb3d3<R>(a3, s); }, 3);
+            }
+            if (P->ctx->verbose)
+                std::fprintf(stderr, "[mxp] tune 3D %s: %d-level pass, %d-plane chunks: %.3f us/level\n",
+                             sizeof(R) == 4 ? "c64" : "c128", levels, zc, us);
+            if (us < us_pass) {
+                us_pass = us;
+                best_zc = zc;
+                best_k = levels;
+            }
         }
     }
     HIP_CHECK(hipEventDestroy(e0));
     HIP_CHECK(hipEventDestroy(e1));
     if (P->ctx->verbose)
-        std::fprintf(stderr, "[mxp] tune 3D %s: sweep %.3f us/level, two-level pass %.3f us/level\n",
-                     sizeof(R) == 4 ? "c64" : "c128", us_sweep, us_pass);
-    // the two-level pass must win by a margin larger than the timing noise
+        std::fprintf(stderr, "[mxp] tune 3D %s: sweep %.3f us/level, best %d-level pass %.3f us/level\n",
+                     sizeof(R) == 4 ? "c64" : "c128", us_sweep, best_k, us_pass);
+    // a multi-level pass must win by a margin larger than the timing noise
     // of single launches, else the simpler sweep stays
     if (us_pass < 0.97 * us_sweep) {
         TileCfg two;
-        two.K = 2;
+        two.K = best_k;
         two.NX = 1;
         two.Ly = best_zc;
         two.us_per_level = us_pass;

@@ -346,12 +346,12 @@ mxp_status mxp_set_tiles(mxp_problem* prob, mxp_precision precision, int32_t K, 
         if (!prob) fail(MXP_ERR_INVALID_ARG, "problem is NULL");
         if (precision != MXP_PREC_FP64 && precision != MXP_PREC_MIXED) fail(MXP_ERR_INVALID_ARG, "unknown precision");
         // 3D sweeps and two-level passes also take Ly = 0 (automatic z-chunk)
-        const bool auto_chunk = prob->g.dim == 3 && (K == 1 || K == 2) && Ly == 0;
+        const bool auto_chunk = prob->g.dim == 3 && (K >= 1 && K <= 3) && Ly == 0;
         if (K < 0 || K > kMaxFused || (NX != 1 && NX != 2) || (Ly < 1 && !auto_chunk) ||
             (K > 0 && NX * 64 - 2 * K <= 0))
             fail(MXP_ERR_INVALID_ARG, "tiles: K in 0..8, NX in {1, 2}, Ly >= 1 (Ly = 0 for 3D K = 1, 2)");
-        if (K == 2 && prob->g.dim == 3 && prob->g.abc_per_node())
-            fail(MXP_ERR_UNSUPPORTED, "two-level 3D passes do not carry the absorbing-face term");
+        if ((K == 2 || K == 3) && prob->g.dim == 3 && prob->g.abc_per_node())
+            fail(MXP_ERR_UNSUPPORTED, "multi-level 3D passes do not carry the absorbing-face term");
         TileCfg& t = prob->tiles[precision == MXP_PREC_MIXED ? 1 : 0];
         (void)hipStreamSynchronize(prob->ctx->stream);
         prob->ws.drop_graphs();  // captured actions bake in the tile shape

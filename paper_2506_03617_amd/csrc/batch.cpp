@@ -23,9 +23,9 @@ namespace mxp {
 // lockstep action: step k of every request is launched before step k + 1 of
 // any.  The 3D sweeps of one step that share an operand set go out as a
 // single launch over all their grids (uneven sizes included), and so do the
-// 2D temporally blocked passes of one step that share K and NX; both batched
-// kernels are persistent (resident workgroups striding over every grid's
-// tiles).
+// 3D two- and three-level passes and the 2D temporally blocked passes of one
+// step that share a shape; the batched kernels are persistent (resident
+// workgroups striding over every grid's tiles).
 
 struct ActionReq {
     Run* run;
@@ -110,7 +110,7 @@ class Batcher {
 
     struct Group {  // one batched launch
         int prec;   // 0 double, 1 float
-        int kind;   // 0 3D sweeps, 1 2D passes, 2 3D two-level passes
+        int kind;   // 0 3D sweeps, 1 2D passes, 2 / 3 3D two- / three-level passes
         int ops;    // operand set / variant; 2D passes: K * 4 + NX
         size_t jobs_off, lut_off;
         int64_t blocks;
@@ -201,7 +201,13 @@ class Batcher {
             std::map<int, std::vector<const ChebPass3DArgs<float>*>> p32;
             std::map<int, std::vector<const StepRec<double>*>> f64;
             std::map<int, std::vector<const StepRec<float>*>> f32;
+            std::map<int, std::vector<const ChebPass3DArgs<double>*>> t64;
+            std::map<int, std::vector<const ChebPass3DArgs<float>*>> t32;
             for (size_t i = 0; i < nq; ++i) {
+                if (k < r64[i].size() && r64[i][k].kind == 3)
+                    t64[cheb3d_variant(r64[i][k].c3)].push_back(&r64[i][k].c3);
+                if (k < r32[i].size() && r32[i][k].kind == 3)
+                    t32[cheb3d_variant(r32[i][k].c3)].push_back(&r32[i][k].c3);
                 if (k < r64[i].size() && r64[i][k].kind == 1)
                     f64[r64[i][k].K * 4 + r64[i][k].NX].push_back(&r64[i][k]);
                 if (k < r32[i].size() && r32[i][k].kind == 1)
@@ -233,6 +239,16 @@ class Batcher {
             for (auto& kv : f32) {
                 Group g{1, 1, kv.first, 0, 0, 0};
                 add_passes2d<float>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+            for (auto& kv : t64) {
+                Group g{0, 3, kv.first, 0, 0, 0};
+                add_passes<double>(buf, g, kv.second);
+                plan[k].push_back(g);
+            }
+            for (auto& kv : t32) {
+                Group g{1, 3, kv.first, 0, 0, 0};
+                add_passes<float>(buf, g, kv.second);
                 plan[k].push_back(g);
             }
             for (auto& kv : p64) {
@@ -277,6 +293,12 @@ class Batcher {
                 else if (g.kind == 1)
                     launch_cheb2d_batch<float>(reinterpret_cast<const Cheb2DJob<float>*>(dev + g.jobs_off), lut,
                                                g.blocks, g.ops / 4, g.ops % 4, s_);
+                else if (g.kind == 3 && g.prec == 0)
+                    launch_cheb3d3_batch<double>(reinterpret_cast<const Cheb3DJob<double>*>(dev + g.jobs_off), lut,
+                                                 g.blocks, g.ops, s_);
+                else if (g.kind == 3)
+                    launch_cheb3d3_batch<float>(reinterpret_cast<const Cheb3DJob<float>*>(dev + g.jobs_off), lut,
+                                                g.blocks, g.ops, s_);
                 else if (g.kind == 2 && g.prec == 0)
                     launch_cheb3d_batch<double>(reinterpret_cast<const Cheb3DJob<double>*>(dev + g.jobs_off), lut,
                                                 g.blocks, g.ops, s_);

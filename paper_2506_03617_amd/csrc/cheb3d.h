@@ -27,8 +27,8 @@ struct ChebPass3DArgs {
     const cpx<R>* in1;
     cpx<R>* outA;
     cpx<R>* outB;
-    cpx<R> cx[2];
-    R g[2];
+    cpx<R> cx[3];  // the two-level pass reads [0..1], the three-level pass [0..2]
+    R g[3];
     int tiles_x, tiles_y, zchunks, zc;
 };
 template <typename R>
@@ -37,6 +37,17 @@ template <typename R>
 int cheb3d_variant(const ChebPass3DArgs<R>& a);  // 1: D present, 2: in0, 4: in1
 template <typename R>
 void launch_cheb3d(const ChebPass3DArgs<R>& a, hipStream_t s);
+// Three consecutive levels in one pass over a 3D grid:
+//   L_0 = cx[0] x + g[0] S(in1) - in0,   L_1 = cx[1] x + g[1] S(L_0) - in1,
+//   L_2 = cx[2] x + g[2] S(L_1) - L_0;
+// writes L_1 to outA and L_2 to outB (the two levels the next pass reads).
+// Geometry (cheb3d3_geometry): tiles of 60 columns and the workgroup's output
+// rows, chunks of zc planes (0: 32); L_0 is recomputed on a two-node halo and
+// L_1 on a one-node halo in x, y and z.
+template <typename R>
+void cheb3d3_geometry(ChebPass3DArgs<R>& a, int zc);
+template <typename R>
+void launch_cheb3d3(const ChebPass3DArgs<R>& a, hipStream_t s);
 // Batched form over grids of different sizes (same variant): as Sweep3DJob.
 template <typename R>
 struct Cheb3DJob {
@@ -46,5 +57,9 @@ struct Cheb3DJob {
 template <typename R>
 void launch_cheb3d_batch(const Cheb3DJob<R>* jobs, const uint32_t* lut, int64_t total_blocks, int variant,
                          hipStream_t s);
+// The same for three-level passes (jobs set up by cheb3d3_geometry).
+template <typename R>
+void launch_cheb3d3_batch(const Cheb3DJob<R>* jobs, const uint32_t* lut, int64_t total_blocks, int variant,
+                          hipStream_t s);
 
 }  // namespace mxp

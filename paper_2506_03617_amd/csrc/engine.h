@@ -190,7 +190,7 @@ inline cpx<R> to_cpx(cd v) { return {R(v.real()), R(v.imag())}; }
 // or into a list that a batched solve replays in lockstep with other actions.
 template <typename R>
 struct StepRec {
-    int kind;  // 0: stencil sweep (st); 1: temporally blocked 2D pass (cp, K, NX); 2: two-level 3D pass (c3)
+    int kind;  // 0: stencil sweep (st); 1: temporally blocked 2D pass (cp, K, NX); 2 / 3: two- / three-level 3D pass (c3)
     StencilArgs<R> st;
     ChebPassArgs<R> cp;
     ChebPass3DArgs<R> c3;
@@ -231,6 +231,16 @@ struct Emit {
             rec->push_back(r);
         } else {
             launch_cheb3d<R>(a, s);
+        }
+    }
+    void pass3d3(const ChebPass3DArgs<R>& a) const {
+        if (rec) {
+            StepRec<R> r{};
+            r.kind = 3;
+            r.c3 = a;
+            rec->push_back(r);
+        } else {
+            launch_cheb3d3<R>(a, s);
         }
     }
 };

@@ -58,16 +58,18 @@ def run_batch(ctx, handles, opts, rhs, max_resident=0):
     return status, stats, [to_host(u).reshape(f.shape) for u, f in zip(u_list, rhs)]
 
 
-@pytest.mark.parametrize("two_level", [False, True])
+@pytest.mark.parametrize("levels", [1, 2, 3])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_equals_separate_solves_bit_for_bit(ctx, prec, two_level):
+def test_batch_equals_separate_solves_bit_for_bit(ctx, prec, levels):
     probs, rhs = uneven_set()
-    announce("batch vs separate", prec, two_level)
+    announce("batch vs separate", prec, levels)
     handles = [mxp.Problem(ctx, p) for p in probs]
-    if two_level:  # the 3D grids run two-level passes (batched k_cheb3d)
-        for h, p in zip(handles, probs):
-            if p.dim == 3:
-                mxp.mxp_set_tiles(h, prec, 2, 1, 1)
+    # the 3D grids run sweeps, two-level (batched k_cheb3d) or three-level
+    # passes (batched k_cheb3d3), the mixed form's double iterations included
+    for h, p in zip(handles, probs):
+        if p.dim == 3:
+            for pr in (0, 1):
+                mxp.mxp_set_tiles(h, pr, levels, 1, 0 if levels > 1 else 16)
     opts = []
     for h in handles:
         o = h.default_opts()

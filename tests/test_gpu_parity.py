@@ -275,15 +275,18 @@ def test_autotuned_tiles_are_recorded(ctx):
     assert 1 <= tiles["K"] <= 8 and tiles["NX"] in (1, 2) and tiles["us_per_level"] > 0
 
 
+@pytest.mark.parametrize("levels,zc", [(2, 1), (3, 3), (3, 0)])
 @pytest.mark.parametrize("name", ["3d-homog", "3d-inh", "3d-ragged"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_two_level_3d_passes(ctx, name, prec):
-    # the two-level 3D pass (tiles K = 2): one-plane chunks, 62 x 14 tiles
-    # with ragged edges, odd and even series degrees through exp and psi_1
+def test_multi_level_3d_passes(ctx, name, prec, levels, zc):
+    # the two- and three-level 3D passes (tiles K = 2, 3): 62 x 14 and 60 x 12
+    # tiles with ragged edges, short z-chunks (chunk boundaries inside the
+    # grid) and the default, odd and even series degrees (remainders of one
+    # and two levels) through exp and psi_1
     prob = make(name)
-    announce("3d two-level passes", name, prec)
+    announce("3d multi-level passes", name, prec, levels, zc)
     P = mxp.Problem(ctx, prob)
-    mxp.mxp_set_tiles(P, prec, 2, 1, 1)
+    mxp.mxp_set_tiles(P, prec, levels, 1, zc)
     t, s = prob.default_t(), prob.default_shift()
     x = wl.random_vector(prob.npts, 9)
     tdt = torch.complex128 if prec == 0 else torch.complex64
@@ -299,9 +302,9 @@ def test_two_level_3d_passes(ctx, name, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_3d_kernel_choice_is_tuned_and_matches_the_oracle(ctx, prec):
-    # the first action on a 3D problem times a sweep against a two-level pass
-    # and keeps the faster per level (K = 1 with an automatic z-chunk, or
-    # K = 2); the chosen kernel's action matches the oracle, and a grid with
+    # the first action on a 3D problem times a sweep against two- and
+    # three-level passes and keeps the fastest per level (K = 1 with an
+    # automatic z-chunk, or K = 2, 3); the chosen kernel's action matches the oracle, and a grid with
     # per-node absorbing faces always takes sweeps
     prob = make("3d-inh")
     announce("3d kernel choice", prec)
@@ -313,8 +316,8 @@ def test_3d_kernel_choice_is_tuned_and_matches_the_oracle(ctx, prec):
     t, s = prob.default_t(), prob.default_shift()
     mxp.mxp_apply_exp(P, t, s, xd, yd)
     tiles = mxp.mxp_get_tiles(P, prec)
-    assert tiles["K"] in (1, 2) and tiles["us_per_level"] > 0
-    assert tiles["K"] == 2 or tiles["Ly"] == 0
+    assert tiles["K"] in (1, 2, 3) and tiles["us_per_level"] > 0
+    assert tiles["K"] >= 2 or tiles["Ly"] == 0
     tol = 1e-11 if prec == 0 else 1e-5
     assert rel(to_host(yd), matfun.exp_action(op.helmholtz(prob, s), t, to_host(xd))) <= tol
     P.close()
