@@ -60,11 +60,23 @@ def exp_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
     return spla.expm_multiply((1j * t) * As.tocsr(), np.asarray(v, dtype=np.complex128))
 
 
+def _unit_column(v: np.ndarray):
+    """v / ||v||_1 and ||v||_1.  psi_l(X) v is linear in v, so the augmented
+    exponentials below take the unit column and scale the result back: the
+    column's norm then does not inflate the augmented matrix's 1-norm, which
+    sets expm_multiply's step count."""
+    v = np.asarray(v, dtype=np.complex128)
+    beta = float(np.abs(v).sum())
+    return (v / beta if beta > 0 else v), beta
+
+
 def phi1_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
     """psi_1(i t A_s) v via the exponential of the augmented matrix
     [[i t A_s, v], [0, 0]] applied to the last unit vector."""
     N = As.shape[0]
-    v = np.asarray(v, dtype=np.complex128)
+    v, beta = _unit_column(v)
+    if beta == 0:
+        return np.zeros(N, dtype=np.complex128)
     M = (1j * t) * As.tocsc()
     col = sp.csc_matrix(v.reshape(-1, 1))
     top = sp.hstack([M, col])
@@ -72,7 +84,7 @@ def phi1_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
     aug = sp.vstack([top, bottom]).tocsr()
     e = np.zeros(N + 1, dtype=np.complex128)
     e[-1] = 1.0
-    return spla.expm_multiply(aug, e)[:N]
+    return beta * spla.expm_multiply(aug, e)[:N]
 
 
 def phi2_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
@@ -80,7 +92,9 @@ def phi2_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
     [[i t A_s, v, 0], [0, 0, 1], [0, 0, 0]] applied to the last unit vector:
     its top block is int_0^1 (1 - u) exp(u i t A_s) v du = psi_2(i t A_s) v."""
     N = As.shape[0]
-    v = np.asarray(v, dtype=np.complex128)
+    v, beta = _unit_column(v)
+    if beta == 0:
+        return np.zeros(N, dtype=np.complex128)
     M = (1j * t) * As.tocsc()
     cols = sp.csc_matrix(np.stack([v, np.zeros_like(v)], axis=1))
     top = sp.hstack([M, cols])
@@ -89,7 +103,7 @@ def phi2_action(As: sp.spmatrix, t: float, v: np.ndarray) -> np.ndarray:
     aug = sp.vstack([top, bottom]).tocsr()
     e = np.zeros(N + 2, dtype=np.complex128)
     e[-1] = 1.0
-    return spla.expm_multiply(aug, e)[:N]
+    return beta * spla.expm_multiply(aug, e)[:N]
 
 
 def exp_dense(As, t: float) -> np.ndarray:
