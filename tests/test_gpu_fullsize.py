@@ -160,6 +160,51 @@ def test_actions_full_size_grf_against_oracle(ctx, grf_oracle, fn, dt, tol):
     assert rel(y, g[fn]) <= tol
 
 
+@pytest.fixture(scope="module")
+def cube_oracle():
+    """The 256^3 workload (20-cell layer, c = 1), its operator in the oracle's
+    CSR form, a seeded input and the oracle's exp and psi_1 actions at t/32
+    (expm_multiply; about 15 s each on the host)."""
+    prob = wl.config3()
+    s = prob.default_shift()
+    t = prob.default_t() / 32
+    As = op.helmholtz(prob, s)
+    x = wl.random_vector(prob.npts, 33)
+    out = {"prob": prob, "s": s, "t": t, "x": x, "exp": matfun.exp_action(As, t, x)}
+    out["psi1"] = matfun.phi1_action(As, t, x)
+    return out
+
+
+@pytest.mark.parametrize("tiles", ["tuned", "three-level"])
+@pytest.mark.parametrize("fn,dt,tol", [("exp", "c128", 1e-11), ("exp", "c64", 1e-5), ("psi1", "c128", 1e-11),
+                                       ("psi1", "c64", 1e-5)])
+def test_actions_full_size_3d_layer_against_oracle(ctx, cube_oracle, fn, dt, tol, tiles):
+    # element by element at the benchmark's 256^3 shape with its absorbing
+    # layer: the 3D kernel the autotuner picks for this problem, and the
+    # three-level pass over its default 32-plane chunks (the complex-double
+    # solve's kernel at this size)
+    g = cube_oracle
+    prob = g["prob"]
+    announce("3d action full size vs oracle", prob.name, fn, dt, tiles)
+    P = mxp.Problem(ctx, prob)
+    prec = 0 if dt == "c128" else 1
+    if tiles == "three-level":
+        mxp.mxp_set_tiles(P, prec, 3, 1, 0)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    xd = to_dev(g["x"], tdt)
+    yd = torch.empty_like(xd)
+    (mxp.mxp_apply_exp if fn == "exp" else mxp.mxp_apply_psi1)(P, g["t"], g["s"], xd, yd)
+    torch.cuda.synchronize()
+    chosen = mxp.mxp_get_tiles(P, prec)
+    y = to_host(yd)
+    del xd, yd
+    P.close()
+    assert chosen["K"] in (1, 2, 3)
+    if tiles == "three-level":
+        assert chosen["K"] == 3
+    assert rel(y, g[fn]) <= tol
+
+
 def test_matfun_identities_full_size_grf(ctx):
     # with the layer and the random-field speed at full size:
     #   e^{itA_s} v - v = i t A_s psi_1(itA_s) v                       (Section 3.1)
