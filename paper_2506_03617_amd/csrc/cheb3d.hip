@@ -388,7 +388,7 @@ __device__ __forceinline__ void cheb3d3_body(const ChebPass3DArgs<R>& a, int til
     R D_m1 = a.Dconst, D_m2 = a.Dconst;
     // one plane step: L_0 on plane k from `cur` (its operands, loaded one
     // step earlier), L_1 on plane k - 1, L_2 on plane k - 2
-    auto step = [&](int64_t k, const PlaneIn& cur) {
+    auto step = [&](int64_t k, const PlaneIn& cur, auto&& after_l0) {
         const cpx<R> zp = keep_if(k + 1 >= 0 && k + 1 < n2, cur.zp);
         // ---- L_0 on plane k (every row)
         const bool kin = k >= 0 && k < n2;  // uniform
@@ -408,6 +408,10 @@ __device__ __forceinline__ void cheb3d3_body(const ChebPass3DArgs<R>& a, int til
         l0 = {l0.re - cur.in0.re, l0.im - cur.in0.im};
         l0 = keep_if(live && kin, l0);
         ring0[int(((k % 3) + 3) % 3)][w][lane] = l0;
+        // the plane's operands are dead past L_0 but for x and D
+        const cpx<R> xk = cur.x;
+        const R Dk = cur.D;
+        after_l0();
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt and expcnt left free
         __builtin_amdgcn_s_barrier();
         // ---- L_1 on plane k - 1 (rows 1 .. NW3 - 2)
@@ -464,9 +468,9 @@ __device__ __forceinline__ void cheb3d3_body(const ChebPass3DArgs<R>& a, int til
         a_m = a_c;
         a_c = zp;
         x_m2 = x_m1;
-        x_m1 = cur.x;
+        x_m1 = xk;
         D_m2 = D_m1;
-        D_m1 = cur.D;
+        D_m1 = Dk;
     };
     // Software pipeline.  In complex float the operands of plane k + 2 are
     // loaded before plane k is computed, and the loop is unrolled by three so
@@ -476,29 +480,26 @@ __device__ __forceinline__ void cheb3d3_body(const ChebPass3DArgs<R>& a, int til
     // per step the pass took 105.6 us per level at 256^3, unrolled by two
     // 95.3, with two planes 85.8.  In complex double an unrolled loop needs
     // more than the 128 registers of four wavefronts per SIMD (it spills), so
-    // the operands of plane k + 1 are loaded one step ahead and copied.
-    // Planes past the chunk read clamped, in-bounds nodes.
+    // one operand set serves: the loads of plane k + 1 go into it as soon as
+    // L_0 of plane k has read it, and stay in flight across the barrier, L_1
+    // and L_2.  Planes past the chunk read clamped, in-bounds nodes.
     if constexpr (sizeof(R) == 4) {
         PlaneIn pa = load_plane(z0 - 2);
         PlaneIn pb = load_plane(z0 - 1);
         PlaneIn pc;
         for (int64_t k = z0 - 2; k <= z1 + 1; k += 3) {
             pc = load_plane(k + 2);
-            step(k, pa);
+            step(k, pa, [] {});
             if (k + 1 > z1 + 1) break;
             pa = load_plane(k + 3);
-            step(k + 1, pb);
+            step(k + 1, pb, [] {});
             if (k + 2 > z1 + 1) break;
             pb = load_plane(k + 4);
-            step(k + 2, pc);
+            step(k + 2, pc, [] {});
         }
     } else {
         PlaneIn cur = load_plane(z0 - 2);
-        for (int64_t k = z0 - 2; k <= z1 + 1; ++k) {
-            const PlaneIn nxt = load_plane(k + 1);
-            step(k, cur);
-            cur = nxt;
-        }
+        for (int64_t k = z0 - 2; k <= z1 + 1; ++k) step(k, cur, [&] { cur = load_plane(k + 1); });
     }
 }
 
