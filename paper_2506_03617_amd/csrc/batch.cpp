@@ -24,8 +24,9 @@ namespace mxp {
 // any.  The 3D sweeps of one step that share an operand set go out as a
 // single launch over all their grids (uneven sizes included), and so do the
 // 3D two- and three-level passes and the 2D temporally blocked passes of one
-// step that share a shape; the batched kernels are persistent (resident
-// workgroups striding over every grid's tiles).
+// step that share a shape.  The batched sweep, two-level and 2D kernels are
+// persistent (resident workgroups striding over every grid's tiles); the
+// three-level pass runs one workgroup per tile.
 
 struct ActionReq {
     Run* run;
