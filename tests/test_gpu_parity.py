@@ -275,14 +275,16 @@ def test_autotuned_tiles_are_recorded(ctx):
     assert 1 <= tiles["K"] <= 8 and tiles["NX"] in (1, 2) and tiles["us_per_level"] > 0
 
 
-@pytest.mark.parametrize("levels,zc", [(2, 1), (3, 3), (3, 0)])
+@pytest.mark.parametrize("levels,zc", [(2, 1), (3, 1), (3, 2), (3, 3), (3, 0)])
 @pytest.mark.parametrize("name", ["3d-homog", "3d-inh", "3d-ragged"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_multi_level_3d_passes(ctx, name, prec, levels, zc):
     # the two- and three-level 3D passes (tiles K = 2, 3): 62 x 14 and 60 x 12
     # tiles with ragged edges, short z-chunks (chunk boundaries inside the
-    # grid) and the default, odd and even series degrees (remainders of one
-    # and two levels) through exp and psi_1
+    # grid; 1-, 2- and 3-plane chunks give 5, 6 and 7 plane steps, every
+    # remainder of the complex-float loop unrolled by three) and the default,
+    # odd and even series degrees (remainders of one and two levels) through
+    # exp and psi_1
     prob = make(name)
     announce("3d multi-level passes", name, prec, levels, zc)
     P = mxp.Problem(ctx, prob)
