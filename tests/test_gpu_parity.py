@@ -332,15 +332,20 @@ def test_3d_kernel_choice_is_tuned_and_matches_the_oracle(ctx, prec):
     Pa.close()
 
 
-@pytest.mark.parametrize("name", ["2d-inh", "3d-inh"])
+@pytest.mark.parametrize("name,levels", [("2d-inh", 0), ("3d-inh", 0), ("3d-inh", 3)])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_graph_replayed_actions_match_direct_launches(ctx, name, prec):
+def test_graph_replayed_actions_match_direct_launches(ctx, name, levels, prec):
     # every exp / psi_1 action after the first of its kind replays a captured
     # HIP graph, with the solver's own eager kernels and synchronisations in
     # between; solutions and statistics must equal the directly launched solve
+    # (with the tuner's tiles, and in 3D also with three-level passes pinned in
+    # both precisions, as the mixed form's double iterations use them too)
     prob = make(name)
-    announce("graphs", name, prec)
+    announce("graphs", name, levels, prec)
     P = mxp.Problem(ctx, prob)
+    if levels:
+        for pr in (0, 1):
+            mxp.mxp_set_tiles(P, pr, levels, 1, 0)
     centre = tuple(m // 2 for m in prob.n)
     fd = to_dev(wl.delta_source(prob, centre).ravel())
     o = P.default_opts()
