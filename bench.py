@@ -180,16 +180,25 @@ def measure_roofline(mxp, torch, P, prob, o, reps, prec):
 
 def bench_layered_batch(args, torch, mxp, wl):
     """The layered batch: `--rhs` of the 32 surface sources on the 512x512x256
-    grid plus the 16 uneven 96^3..192^3 problems (one source each), solved by
-    one mxp_solve_batch call in the mixed form with FGMRES(20).  One step =
-    the whole batched solve."""
+    grid (or the indices `--sources` names) plus the 16 uneven 96^3..192^3
+    problems (one source each; left out with `--no-extras`), solved by one
+    mxp_solve_batch call in the mixed form with FGMRES(20).  One step = the
+    whole batched solve."""
     os.environ.setdefault("MXP_VERBOSE", "1")   # one line per outer iteration: progress
+    if args.sources:
+        which = []
+        for part in args.sources.split(","):
+            lo, _, hi = part.partition("-")
+            which.extend(range(int(lo), int(hi or lo) + 1))
+        if not which or min(which) < 0 or max(which) > 31 or len(set(which)) != len(which):
+            raise SystemExit("--sources: distinct indices in 0..31")
+    else:
+        which = [round(k * 31 / max(args.rhs - 1, 1)) for k in range(args.rhs)]
     main_p = wl.config4_main()
-    extras = wl.config4_extras()
+    extras = [] if args.no_extras else wl.config4_extras()
     ctx = mxp.Context(0)
     probs = [main_p] + extras
     handles = [mxp.Problem(ctx, p) for p in probs]
-    which = [round(k * 31 / max(args.rhs - 1, 1)) for k in range(args.rhs)]
     rhs = [wl.config4_sources(main_p, which)]
     for p in extras:
         rhs.append(wl.delta_source(p, (p.n[0] // 2, p.n[1] // 2, p.layer + 2)).ravel()[None, :])
@@ -202,7 +211,7 @@ def bench_layered_batch(args, torch, mxp, wl):
     f_list = [torch.from_numpy(f).to("cuda:0") for f in rhs]
     del rhs
     u_list = [torch.zeros_like(f) for f in f_list]
-    print(f"[bench] layered batch: {args.rhs} sources on {main_p.n} + {len(extras)} extra grids",
+    print(f"[bench] layered batch: sources {which} on {main_p.n} + {len(extras)} extra grids",
           file=sys.stderr, flush=True)
     times, all_stats = [], None
     for k in range(args.warmup + max(args.steps, 1)):
@@ -218,14 +227,15 @@ def bench_layered_batch(args, torch, mxp, wl):
             times.append(dt)
     s_per = sum(times) / len(times)
     n_rhs = len(all_stats)
-    pts = sum(p.npts * (args.rhs if i == 0 else 1) for i, p in enumerate(probs))
+    pts = sum(p.npts * (len(which) if i == 0 else 1) for i, p in enumerate(probs))
     line = {
         "metric": "s to 1e-6 rel. residual (plain vs FP32/learned); stencil HBM GB/s vs peak",
         "value": round(s_per, 3), "unit": "s", "n_gpus": 1, "steps": len(times), "warmup": args.warmup,
         "ms_per_step": round(s_per * 1e3, 1), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64 stepping and inner basis + c128 Krylov sums and outer solve",
         "data": "synthetic (seeded layered speeds with two lenses, point sources)",
-        "config": {"workload": "3d-layered-batch", "main_grid": list(main_p.n), "main_sources": args.rhs,
+        "config": {"workload": "3d-layered-batch", "main_grid": list(main_p.n), "main_sources": len(which),
+                   "source_indices": which,
                    "extra_grids": [list(p.n) for p in extras], "right_hand_sides": n_rhs,
                    "grid_points_total": pts, "precision": "mixed", "outer_restart": 20},
         "per_rhs": [{k: s[k] for k in ("outer_its", "inner_mean", "stencil_steps", "true_relres", "seconds",
@@ -686,7 +696,12 @@ def main():
     ap.add_argument("--conv-only", action="store_true",
                     help="3d-learned: time the network alone (forward at 256^3, training steps on 4 x 64^3)")
     ap.add_argument("--rhs", type=int, default=2,
-                    help="3d-layered-batch: surface sources on the 512x512x256 grid (of 32)")
+                    help="3d-layered-batch: surface sources on the 512x512x256 grid (of 32), equally spaced")
+    ap.add_argument("--sources", default=None,
+                    help="3d-layered-batch: explicit source indices (of the 32), e.g. 0-10 or 3,7,12 "
+                         "(overrides --rhs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="3d-layered-batch: leave out the 16 uneven grids")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-form solves beside the double ones")
     ap.add_argument("--fp64-below", type=float, default=None,
                     help="mixed form: relative residual below which its actions run in double "

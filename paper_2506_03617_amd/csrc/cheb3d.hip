@@ -386,8 +386,9 @@ __device__ __forceinline__ void cheb3d3_body(const ChebPass3DArgs<R>& a, int til
     cpx<R> l1_m2 = zero, l1_m1 = zero;  // L_1 on planes k - 3, k - 2
     cpx<R> x_m1 = zero, x_m2 = zero;
     R D_m1 = a.Dconst, D_m2 = a.Dconst;
-    // one plane step: L_0 on plane k from `cur` (its operands, loaded one
-    // step earlier), L_1 on plane k - 1, L_2 on plane k - 2
+    // one plane step: L_0 on plane k from `cur` (its operands, loaded one or
+    // two steps ahead, see below), L_1 on plane k - 1, L_2 on plane k - 2;
+    // after_l0 runs once L_0 has read `cur` (complex double reloads it there)
     auto step = [&](int64_t k, const PlaneIn& cur, auto&& after_l0) {
         const cpx<R> zp = keep_if(k + 1 >= 0 && k + 1 < n2, cur.zp);
         // ---- L_0 on plane k (every row)
