@@ -178,6 +178,25 @@ def measure_roofline(mxp, torch, P, prob, o, reps, prec):
             f"schedule_{tag}": {"S": sch.S, "m": m, "m_psi": sch.m_psi}}
 
 
+def layered_sources(args):
+    """Indices (of the 32 surface sources) the layered batch solves: --sources
+    (e.g. 0-10 or 3,7,12), else --rhs equally spaced ones.  Exits with a
+    message on indices outside 0..31, repeated or malformed."""
+    if not args.sources:
+        return [round(k * 31 / max(args.rhs - 1, 1)) for k in range(args.rhs)]
+    which = []
+    try:
+        for part in args.sources.split(","):
+            lo, _, hi = part.partition("-")
+            which.extend(range(int(lo), int(hi or lo) + 1))
+    except ValueError:
+        which = []
+    if not which or min(which) < 0 or max(which) > 31 or len(set(which)) != len(which):
+        print(f"--sources {args.sources!r}: distinct indices in 0..31 expected", file=sys.stderr)
+        sys.exit(2)
+    return which
+
+
 def bench_layered_batch(args, torch, mxp, wl):
     """The layered batch: `--rhs` of the 32 surface sources on the 512x512x256
     grid (or the indices `--sources` names) plus the 16 uneven 96^3..192^3
@@ -185,15 +204,7 @@ def bench_layered_batch(args, torch, mxp, wl):
     mxp_solve_batch call in the mixed form with FGMRES(20).  One step = the
     whole batched solve."""
     os.environ.setdefault("MXP_VERBOSE", "1")   # one line per outer iteration: progress
-    if args.sources:
-        which = []
-        for part in args.sources.split(","):
-            lo, _, hi = part.partition("-")
-            which.extend(range(int(lo), int(hi or lo) + 1))
-        if not which or min(which) < 0 or max(which) > 31 or len(set(which)) != len(which):
-            raise SystemExit("--sources: distinct indices in 0..31")
-    else:
-        which = [round(k * 31 / max(args.rhs - 1, 1)) for k in range(args.rhs)]
+    which = layered_sources(args)
     main_p = wl.config4_main()
     extras = [] if args.no_extras else wl.config4_extras()
     ctx = mxp.Context(0)
@@ -720,6 +731,8 @@ def main():
         print(f"bench.py measures one GPU (asked for {args.gpus}): the solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "3d-layered-batch":
+        layered_sources(args)  # argument errors before any device work
 
     import torch
     import paper_2506_03617_amd as mxp

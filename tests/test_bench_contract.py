@@ -17,3 +17,11 @@ def test_unknown_workload_is_rejected():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "nope"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "invalid choice" in r.stderr
+
+
+def test_layered_batch_source_list_is_checked_before_any_device_work():
+    for bad in ("32", "0-40", "3,3", "x"):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "3d-layered-batch",
+                            "--sources", bad], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2, bad
+        assert "distinct indices in 0..31" in r.stderr and r.stdout == "", bad
