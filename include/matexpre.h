@@ -123,7 +123,8 @@ void mxp_context_destroy(mxp_context* ctx);
  * pointer stays valid until the next call on this thread. */
 const char* mxp_last_error(void);
 
-/* Library version string. */
+/* Library version string.  It is part of the key of the autotuner cache
+ * (MXP_AUTOTUNE_CACHE), so choices cached by another version are re-timed. */
 const char* mxp_version(void);
 
 /* ---------------------------------------------------------------- problem */

@@ -94,7 +94,9 @@ extern "C" {
 
 const char* mxp_last_error(void) { return g_last_error.c_str(); }
 
-const char* mxp_version(void) { return "matexpre-mi355x 0.1.0 (gfx950)"; }
+// The version is part of the autotuner cache key, so it changes whenever the
+// tuner's candidates or the kernels they name do (0.2: three-level 3D passes).
+const char* mxp_version(void) { return "matexpre-mi355x 0.2.0 (gfx950)"; }
 
 mxp_status mxp_context_create(int device, void* hip_stream, mxp_alloc_fn alloc, mxp_free_fn release, void* user,
                               mxp_context** out) {
