@@ -374,7 +374,7 @@ mxp_status mxp_apply_precond(mxp_problem* prob, const mxp_solve_opts* opts, mxp_
  * segments are Ly planes (Ly = 0: chosen from the grid, as the autotuner
  * reports it); NX is unused there.  By default the first action times one
  * sweep against two-level (16-, 32- and 64-plane chunks) and three-level (16,
- * 32) passes on the problem's buffers and keeps the fastest per level, a
+ * 32, 64, 128) passes on the problem's buffers and keeps the fastest per level, a
  * multi-level pass only when it wins by more than 3% (at 256^3 the
  * three-level pass in complex double, the sweep in complex float); grids with
  * per-node absorbing-face terms always take sweeps.  Errors: INVALID_ARG;

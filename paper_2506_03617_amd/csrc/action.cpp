@@ -794,8 +794,8 @@ void apply_A64(mxp_problem* P, hipStream_t s, double shift, const cpx<double>* x
 // single-level sweep (a middle step: x, b_{k+1}, b_{k+2}) against two- and
 // three-level passes (x, in0, in1) on the problem's own buffers (HIP events on
 // the context stream) and keeps the fastest per Clenshaw level: K = 2 or 3
-// for the multi-level passes (Ly: the best z-chunk of 16, 32 and, for two
-// levels, 64 planes) when they beat the sweep by more than 3%, else K = 1 with
+// for the multi-level passes (Ly: the best z-chunk of 16, 32, 64 and, for
+// three levels, 128 planes) when they beat the sweep by more than 3%, else K = 1 with
 // Ly = 0 (automatic z-chunk) for sweeps.  Grids whose
 // absorbing faces carry a per-node term take sweeps (the two-level pass does
 // not carry that term).
@@ -866,13 +866,15 @@ static void tune_3d(mxp_problem* P, Workspace& ws, const Sched& sd, hipStream_t 
     };
     const double us_sweep = time_us([&] { launch_stencil(st, s); }, 1);
     // two-level passes with z-chunks of 16, 32 and 64 planes and three-level
-    // passes with 16 and 32 (no longer than the grid)
+    // passes with 16, 32, 64 and 128 (no longer than the grid; at 256^3 the
+    // long chunks win although they leave compute units idle: their z-halo
+    // is smaller)
     double us_pass = 1e300;
     int best_zc = 0, best_k = 2;
     for (int levels : {2, 3}) {
-        for (int zc : {16, 32, 64}) {
+        for (int zc : {16, 32, 64, 128}) {
             if (zc > 16 && zc / 2 >= P->g.n[2]) continue;
-            if (levels == 3 && zc > 32) continue;
+            if (levels == 2 && zc > 64) continue;
             double us;
             if (levels == 2) {
                 cheb3d_geometry<R>(a, zc);
